@@ -1,0 +1,191 @@
+"""Benchmark: batched PAQIF banded-LCP solves/s on one MI355X.
+
+Workload (synthetic, seeded; stands in for the paper's unpublished matrices):
+three batches of 4096 symmetric, strictly diagonally dominant band systems,
+orders uniform in [513, 4097], half-bandwidth q = 2, 4 and 8, off-diagonals
+U(-1, 1), diagonal = sum|off-diagonals| + U(0.5, 1.5), right-hand side
+N(0, 1).  One step = the exact LCP solve (active-set PAQIF, FP64) of all three
+batches, 12288 solves; inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
+GPU (batches would shard by total rows across GPUs with no exchange).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNT = 4096
+QS = (2, 4, 8)
+
+
+def algorithmic_bytes_per_row(q):
+    # band 8(2q+1) + b 8 + u 8 + Z0 written and read back 2*8(2q+1), per
+    # active-set iteration (the per-row unit of the LCP solve)
+    return 8 * (2 * q + 1) + 8 + 8 + 2 * 8 * (2 * q + 1)
+
+
+def cpu_baseline(batches, sample, nthreads):
+    import oracle
+    t_total = 0.0
+    solves = 0
+    for q, (offs, band, f) in batches.items():
+        so = offs[: sample + 1]
+        nrow = int(so[-1])
+        t0 = time.perf_counter()
+        oracle.lcp_batch(q, so, band[:nrow], f[:nrow], mode=oracle.EXACT, nthreads=nthreads)
+        t_total += time.perf_counter() - t0
+        solves += sample
+    return solves / t_total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "
+              "(batches shard by rows across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2008_03276_amd as P
+
+    P.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    batches = {}
+    gpu = {}
+    for q in QS:
+        offs, band, f = synth.lcp_batch(COUNT, q, seed=args.seed)
+        batches[q] = (offs, band, f)
+        bt = P.paqif.Batch(offs, q, device=dev, order="lpt")
+        gpu[q] = dict(bt=bt, band=torch.as_tensor(band, device=dev),
+                      f=torch.as_tensor(f, device=dev),
+                      ws64=bt.workspace(P.PREC_FP64), ws32=bt.workspace(P.PREC_FP32_IR))
+    torch.cuda.synchronize()
+
+    def step(prec):
+        out = {}
+        for q in QS:
+            g = gpu[q]
+            out[q] = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT, prec=prec,
+                                       workspace=g["ws64"] if prec == P.PREC_FP64 else g["ws32"],
+                                       refine_tol=1e-10)
+        return out
+
+    for _ in range(args.warmup):
+        step(P.PREC_FP64)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, events per solve on the launching stream
+    ev = {q: [] for q in QS}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for q in QS:
+            g = gpu[q]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT,
+                                  prec=P.PREC_FP64, workspace=g["ws64"])
+            e1.record()
+            ev[q].append((e0, e1, r))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    solves_per_s = len(QS) * COUNT / (ms_per_step / 1e3)
+
+    per_q = {}
+    for q in QS:
+        durs = [a.elapsed_time(b) for a, b, _ in ev[q]]
+        r = ev[q][-1][2]
+        iters = r["iters"].cpu().numpy().astype(np.int64)
+        status = r["status"].cpu().numpy()
+        sizes = batches[q][0][1:] - batches[q][0][:-1]
+        units = int((sizes * iters).sum())  # rows x active-set iterations
+        avg_ms = float(np.mean(durs))
+        bytes_alg = units * algorithmic_bytes_per_row(q)
+        per_q[q] = dict(avg_ms=avg_ms, iters_mean=float(iters.mean()),
+                        status_ok=bool((status == 0).all()),
+                        active_frac=float(r["active"].float().mean().item()),
+                        gbs=bytes_alg / (avg_ms / 1e3) / 1e9, bytes=bytes_alg)
+
+    # mixed precision (FP32 factors + FP64 refinement): same workload
+    for _ in range(max(1, args.warmup // 2)):
+        step(P.PREC_FP32_IR)
+    torch.cuda.synchronize()
+    tm0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        rm = step(P.PREC_FP32_IR)
+    torch.cuda.synchronize()
+    ms_mixed = (time.perf_counter() - tm0) * 1e3 / max(1, args.steps // 2)
+    r64 = step(P.PREC_FP64)
+    torch.cuda.synchronize()
+    mixed_err = 0.0
+    mixed_active_match = True
+    for q in QS:
+        u64 = r64[q]["u"]
+        mixed_err = max(mixed_err, float((rm[q]["u"] - u64).abs().max() /
+                                         max(1.0, float(u64.abs().max()))))
+        mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
+
+    dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
+    roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=f"paqif_lcp_kernel<{dom},double>")
+
+    cpu = None
+    if not args.no_cpu:
+        nthreads = os.cpu_count() or 1
+        v = cpu_baseline(batches, args.cpu_sample, nthreads)
+        cpu = dict(value=round(v, 2), unit="LCP solves/s", cores=nthreads, kind="oracle",
+                   sample=f"first {args.cpu_sample} systems of each q batch, exact LCP, "
+                          f"OpenMP over systems")
+
+    line = {
+        "metric": "PAQIF banded-LCP solves/s (exact LCP, FP64)",
+        "value": round(solves_per_s, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched banded LCP: 3 x 4096 systems, n~U[513,4097], "
+                               "q in {2,4,8}, b~N(0,1)",
+                   "systems_per_step": len(QS) * COUNT},
+        "per_q": {str(q): {k: (round(v, 4) if isinstance(v, float) else v)
+                           for k, v in per_q[q].items() if k != "bytes"} for q in QS},
+        "mixed_fp32_ir": {"ms_per_step": round(ms_mixed, 4),
+                          "solves_per_s": round(len(QS) * COUNT / (ms_mixed / 1e3), 2),
+                          "speedup_vs_fp64": round(ms_per_step / ms_mixed, 4),
+                          "max_rel_err_vs_fp64": mixed_err,
+                          "active_set_match": mixed_active_match},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

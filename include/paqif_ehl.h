@@ -1,0 +1,164 @@
+/*
+ * paqif_ehl.h -- C ABI of the MI355X (gfx950) PAQIF / EHL library.
+ *
+ * Paper: P. Singh, P. Dutt, "Total Variation Diminishing (TVD) method for
+ * Elastohydrodynamic Lubrication (EHL) problem on Parallel Computers".
+ *
+ * Conventions for every entry point
+ *  - All functions are extern "C", never throw, and return an int call
+ *    status (PAQIF_OK or a negative PAQIF_E* code).
+ *  - Array arguments are DEVICE pointers owned by the caller, unless the
+ *    comment says "host".  The library never frees caller memory.
+ *  - Work is enqueued on the caller's stream (hipStream_t passed as void*;
+ *    NULL = default stream) and is asynchronous: the call returns once the
+ *    kernels are queued.  Numerical outcomes are written per system into
+ *    int32 status arrays on the device; read them after synchronising.
+ *  - Argument errors (NULL where a pointer is required, sizes out of range,
+ *    unsupported half-bandwidth, workspace too small) are detected on the
+ *    host before anything is launched and return PAQIF_EINVAL /
+ *    PAQIF_EWORKSPACE.  A failing HIP launch returns PAQIF_EHIP.
+ *  - Entry points do not allocate device memory; scratch space is passed
+ *    in as `workspace`, sized by the matching *_workspace_bytes query.
+ *
+ * Band layout (all band arguments): a system of order n with half-bandwidth
+ * q is stored row major with 2q+1 doubles per row,
+ *     band[i*(2q+1) + d] = a(i, i+d-q),   d = 0..2q,
+ * entries whose column falls outside [0, n) are ignored.  A batch
+ * concatenates its systems; system s owns rows offsets[s] .. offsets[s+1]-1
+ * of band, right-hand sides and solutions.
+ */
+#ifndef PAQIF_EHL_H
+#define PAQIF_EHL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call-level status */
+enum {
+    PAQIF_OK = 0,
+    PAQIF_EINVAL = -1,
+    PAQIF_EWORKSPACE = -2,
+    PAQIF_EHIP = -3
+};
+
+/* per-system numerical status (device int32 arrays) */
+enum {
+    SYS_OK = 0,
+    SYS_ZERO_PIVOT = 1,          /* a 2x2 (or centre 1x1) pivot block was singular or not finite */
+    SYS_NONFINITE = 2,           /* a non-finite value appeared in the solution */
+    SYS_LCP_NOT_CONVERGED = 3,   /* active-set iteration hit max_iter */
+    SYS_REFINE_STALLED = 4,      /* iterative refinement did not reach the tolerance */
+    SYS_NEGATIVE_FILM = 5,       /* EHL: film thickness H <= 0 somewhere */
+    SYS_NEWTON_NOT_CONVERGED = 6 /* EHL: Newton iteration hit max_newton */
+};
+
+/* arithmetic of the band factorisation */
+enum {
+    PREC_FP64 = 0,    /* factor, solve and decisions in FP64 */
+    PREC_FP32_IR = 1, /* FP32 factors, FP64 residuals, iterative refinement */
+    PREC_SPLIT_BF16 = 2,
+    PREC_FP32 = 3
+};
+
+/* complementarity handling of paqif_solve_lcp */
+enum {
+    LCP_LINEAR = 0, /* u = A^{-1} b, no projection                         */
+    LCP_CLIP = 1,   /* u = max(0, A^{-1} b) on bounded rows (projection)    */
+    LCP_EXACT = 2   /* exact LCP by a primal-dual active-set iteration      */
+};
+
+/* Library handle: device properties.  Create once per process/device. */
+typedef struct paqif_handle_s *paqif_handle;
+int paqif_create(paqif_handle *handle);
+int paqif_destroy(paqif_handle handle);
+const char *paqif_status_str(int code);
+
+/* A batch of band systems sharing one half-bandwidth q (q in {2, 4, 8}).
+ * offsets: DEVICE int64[count+1], offsets[0] = 0, non-decreasing.
+ * max_n: largest system order; total_rows = offsets[count] (host copies).
+ * order: optional DEVICE int32[count] permutation giving the processing
+ *        order (largest systems first is best); NULL = natural order. */
+typedef struct {
+    int32_t count;
+    int32_t q;
+    const int64_t *offsets;
+    int64_t max_n;
+    int64_t total_rows;
+    const int32_t *order;
+} paqif_batch;
+
+/*
+ * Workspace for paqif_solve_lcp / paqif_factor, in bytes (host query).
+ * Holds, per system, one record per elimination level (the two Z0 rows on
+ * the frontier, the inverse 2x2 pivot, the forward-solve values and, for
+ * paqif_factor and PREC_FP32_IR, the W0 multipliers) plus the active-set
+ * flags.  Returns 0 for an invalid batch.
+ */
+size_t paqif_workspace_bytes(paqif_handle handle, const paqif_batch *batch, int prec, int mode);
+
+/*
+ * paqif_factor -- alternate quadrant interlocking factorisation A = W0 Z0
+ * of every system, centre-out (Sec. 2.2, "The Factorization" and
+ * "Evaluation of W0 and Z0": at level k the two central rows of the reduced
+ * matrix become rows of Z0, the two columns of W0 come from one 2x2 solve
+ * per remaining row, then the rank-2 update).  n odd: the centre row is a
+ * 1x1 pivot first.
+ *  band     : DEVICE, total_rows x (2q+1) doubles (layout above).
+ *  pinned   : DEVICE uint8[total_rows] or NULL; rows/columns with a nonzero
+ *             flag are replaced by the identity before factorising.
+ *  prec     : PREC_FP64 only.
+ *  factors  : DEVICE, paqif_workspace_bytes(handle, batch, prec, LCP_LINEAR)
+ *             bytes; receives the level records (layout in the library
+ *             source; consumed by paqif_solve_factored).
+ *  sys_status: DEVICE int32[count]: SYS_OK or SYS_ZERO_PIVOT.
+ */
+int paqif_factor(paqif_handle handle, const paqif_batch *batch, const double *band,
+                 const uint8_t *pinned, int prec, void *factors, int32_t *sys_status,
+                 void *stream);
+
+/*
+ * paqif_solve_factored -- x = (W0 Z0)^{-1} rhs with factors from
+ * paqif_factor: W0 y = rhs from the centre outwards, Z0 x = y from both ends
+ * inwards (Sec. 2.2.2).  rhs entries of pinned rows are treated as 0.
+ *  rhs, x : DEVICE, total_rows doubles each (may not alias).
+ *  pinned : the same mask given to paqif_factor (or NULL).
+ */
+int paqif_solve_factored(paqif_handle handle, const paqif_batch *batch, const void *factors,
+                         const uint8_t *pinned, const double *rhs, double *x, void *stream);
+
+/*
+ * paqif_solve_lcp -- PAQIF solve of the banded linear complementarity
+ * problem of Sec. 2.1 eq. (14):  u >= 0, w = A u - b >= 0, u_i w_i = 0,
+ * on the rows flagged in `bounded` (NULL = all rows); other rows are free.
+ *  mode LCP_LINEAR: u = A^{-1} b.
+ *  mode LCP_CLIP  : u = max(0, A^{-1} b) on bounded rows (the paper's
+ *                   projection of the AQIF solution onto u >= 0).
+ *  mode LCP_EXACT : active sets A_0 = {}, solve with rows/columns of A_k
+ *                   replaced by the identity and b = 0 there, w = A u - b,
+ *                   A_{k+1} = {i in A_k : w_i > 0} u {i not in A_k : u_i < 0}
+ *                   (bounded rows), until A_{k+1} = A_k or max_iter solves.
+ *  prec       : PREC_FP64, or PREC_FP32_IR (FP32 factors; every solve is
+ *               refined with FP64 residuals until |r|_inf <= refine_tol *
+ *               max(|b|_inf, 1) or 8 refinement steps, else
+ *               SYS_REFINE_STALLED).
+ *  u          : DEVICE out, total_rows doubles.
+ *  w          : DEVICE out or NULL, total_rows doubles, w = A u - b.
+ *  active_out : DEVICE out or NULL, uint8 per row (1 = u_i pinned at 0).
+ *  sys_status : DEVICE out, int32[count].
+ *  sys_iters  : DEVICE out or NULL, int32[count], number of AQIF solves.
+ *  workspace  : DEVICE, paqif_workspace_bytes(handle, batch, prec, mode).
+ */
+int paqif_solve_lcp(paqif_handle handle, const paqif_batch *batch, const double *band,
+                    const double *b, const uint8_t *bounded, int mode, int prec,
+                    double refine_tol, int max_iter, double *u, double *w, uint8_t *active_out,
+                    int32_t *sys_status, int32_t *sys_iters, void *workspace, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAQIF_EHL_H */

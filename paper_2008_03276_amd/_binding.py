@@ -1,0 +1,71 @@
+"""ctypes binding of libpaqif_ehl.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only converts
+torch tensors on the GPU into the raw pointers and sizes of the C ABI
+declared in ``include/paqif_ehl.h`` and raises on call-level errors.  There
+is no CPU fallback: if the library is missing the import of a function
+fails loudly.
+"""
+import ctypes
+import os
+
+from . import build as _build
+
+_LIB = None
+
+PAQIF_OK, PAQIF_EINVAL, PAQIF_EWORKSPACE, PAQIF_EHIP = 0, -1, -2, -3
+SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE, SYS_LCP_NOT_CONVERGED = 0, 1, 2, 3
+SYS_REFINE_STALLED, SYS_NEGATIVE_FILM, SYS_NEWTON_NOT_CONVERGED = 4, 5, 6
+PREC_FP64, PREC_FP32_IR, PREC_SPLIT_BF16, PREC_FP32 = 0, 1, 2, 3
+LCP_LINEAR, LCP_CLIP, LCP_EXACT = 0, 1, 2
+
+
+class PaqifBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("max_n", ctypes.c_int64),
+                ("total_rows", ctypes.c_int64), ("order", ctypes.c_void_p)]
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def library_path():
+    return _build.LIB
+
+
+def lib():
+    """Load the HIP library; raise LibraryMissing if it was not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise LibraryMissing(
+            f"{path} not found: build it with paper_2008_03276_amd.build.build() "
+            "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    bp = ctypes.POINTER(PaqifBatch)
+    sig = {
+        "paqif_create": ([ctypes.POINTER(vp)], ctypes.c_int),
+        "paqif_destroy": ([vp], ctypes.c_int),
+        "paqif_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "paqif_workspace_bytes": ([vp, bp, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+        "paqif_factor": ([vp, bp, vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "paqif_solve_factored": ([vp, bp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "paqif_solve_lcp": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
+                             vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = L
+    return L
+
+
+def check(code, what):
+    if code != PAQIF_OK:
+        msg = lib().paqif_status_str(code).decode()
+        raise RuntimeError(f"{what} failed: {msg} ({code})")

@@ -1,0 +1,168 @@
+// C ABI of the library: argument validation, workspace layout, launches.
+#include <new>
+
+#include "common.h"
+
+#include "paqif_args.h"
+
+struct paqif_handle_s {
+    int device;
+    int cu_count;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool valid_batch(const paqif_batch* b)
+{
+    if (!b) return false;
+    if (b->count < 0) return false;
+    if (!(b->q == 2 || b->q == 4 || b->q == 8)) return false;
+    if (b->count > 0 && !b->offsets) return false;
+    if (b->total_rows < 0 || b->max_n < 0) return false;
+    if (b->max_n > (int64_t)1 << 30) return false;
+    return true;
+}
+
+static size_t n_records(const paqif_batch* b) { return (size_t)((b->total_rows + b->count) / 2 + 1); }
+
+// workspace: [records][active flags][refinement residual]
+struct LcpLayout {
+    size_t rec_bytes, act_off, r_off, total;
+};
+
+static LcpLayout lcp_layout(const paqif_batch* b, int prec)
+{
+    LcpLayout L;
+    const bool mixed = prec == PREC_FP32_IR;
+    const size_t elt = mixed ? sizeof(float) : sizeof(double);
+    // records are sized with room for the W0 part (paqif_factor and the
+    // mixed-precision path store it; the FP64 LCP path uses a shorter stride)
+    L.rec_bytes = align256(n_records(b) * (size_t)pq::record_stride(b->q, true) * elt);
+    L.act_off = L.rec_bytes;
+    L.r_off = L.act_off + align256((size_t)b->total_rows);
+    L.total = L.r_off + (mixed ? align256((size_t)b->total_rows * sizeof(double)) : 0);
+    return L;
+}
+
+extern "C" {
+
+int paqif_create(paqif_handle* handle)
+{
+    if (!handle) return PAQIF_EINVAL;
+    paqif_handle_s* h = new (std::nothrow) paqif_handle_s;
+    if (!h) return PAQIF_EINVAL;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return PAQIF_EHIP;
+    }
+    h->cu_count = 0;
+    if (hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) !=
+        hipSuccess)
+        h->cu_count = 0;
+    *handle = h;
+    return PAQIF_OK;
+}
+
+int paqif_destroy(paqif_handle handle)
+{
+    delete handle;
+    return PAQIF_OK;
+}
+
+const char* paqif_status_str(int code)
+{
+    switch (code) {
+    case PAQIF_OK: return "ok";
+    case PAQIF_EINVAL: return "invalid argument";
+    case PAQIF_EWORKSPACE: return "workspace too small";
+    case PAQIF_EHIP: return "HIP launch error";
+    case SYS_ZERO_PIVOT: return "zero or non-finite pivot";
+    case SYS_NONFINITE: return "non-finite solution";
+    case SYS_LCP_NOT_CONVERGED: return "active-set iteration not converged";
+    case SYS_REFINE_STALLED: return "iterative refinement stalled";
+    case SYS_NEGATIVE_FILM: return "negative film thickness";
+    case SYS_NEWTON_NOT_CONVERGED: return "Newton iteration not converged";
+    default: return "unknown status";
+    }
+}
+
+size_t paqif_workspace_bytes(paqif_handle handle, const paqif_batch* batch, int prec, int mode)
+{
+    (void)handle;
+    (void)mode;
+    if (!valid_batch(batch)) return 0;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return 0;
+    return lcp_layout(batch, prec).total;
+}
+
+int paqif_factor(paqif_handle handle, const paqif_batch* batch, const double* band,
+                 const uint8_t* pinned, int prec, void* factors, int32_t* sys_status,
+                 void* stream)
+{
+    if (!handle || !valid_batch(batch) || prec != PREC_FP64) return PAQIF_EINVAL;
+    if (batch->count == 0) return PAQIF_OK;
+    if (!band || !factors || !sys_status) return PAQIF_EINVAL;
+    pq::FactorArgs a;
+    a.count = batch->count;
+    a.offsets = batch->offsets;
+    a.order = batch->order;
+    a.band = band;
+    a.pinned = pinned;
+    a.rec = factors;
+    a.status = sys_status;
+    return pq::dispatch_factor(batch->q, a, (hipStream_t)stream);
+}
+
+int paqif_solve_factored(paqif_handle handle, const paqif_batch* batch, const void* factors,
+                         const uint8_t* pinned, const double* rhs, double* x, void* stream)
+{
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (batch->count == 0) return PAQIF_OK;
+    if (!factors || !rhs || !x || (const void*)rhs == (const void*)x) return PAQIF_EINVAL;
+    pq::SolveArgs a;
+    a.count = batch->count;
+    a.offsets = batch->offsets;
+    a.order = batch->order;
+    a.pinned = pinned;
+    a.rec = const_cast<void*>(factors);
+    a.rhs = rhs;
+    a.x = x;
+    return pq::dispatch_solve(batch->q, a, (hipStream_t)stream);
+}
+
+int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double* band,
+                    const double* b, const uint8_t* bounded, int mode, int prec,
+                    double refine_tol, int max_iter, double* u, double* w, uint8_t* active_out,
+                    int32_t* sys_status, int32_t* sys_iters, void* workspace, void* stream)
+{
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if (batch->count == 0) return PAQIF_OK;
+    if (!band || !b || !u || !sys_status || !workspace) return PAQIF_EINVAL;
+    if (mode == LCP_EXACT && max_iter < 1) return PAQIF_EINVAL;
+    if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
+    const LcpLayout L = lcp_layout(batch, prec);
+    char* ws = static_cast<char*>(workspace);
+    pq::LcpArgs a;
+    a.count = batch->count;
+    a.offsets = batch->offsets;
+    a.order = batch->order;
+    a.band = band;
+    a.b = b;
+    a.bounded = bounded;
+    a.mode = mode;
+    a.max_iter = max_iter;
+    a.refine_tol = refine_tol;
+    a.u = u;
+    a.w = w;
+    a.active_out = active_out;
+    a.status = sys_status;
+    a.iters = sys_iters;
+    a.rec = ws;
+    a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
+    a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
+    return pq::dispatch_lcp(batch->q, a, prec, (hipStream_t)stream);
+}
+
+}  // extern "C"

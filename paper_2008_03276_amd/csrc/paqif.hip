@@ -1,0 +1,833 @@
+// PAQIF: batched alternate quadrant interlocking factorisation and banded
+// LCP solve on gfx950.
+//
+// Method (Singh & Dutt, Sec. 2.2): A = W0 Z0 is computed from the centre of
+// the band outwards.  Level k takes the pivot pair (p1, p2) = (s-k, s+k-1)
+// (n = 2s; for n = 2m+1 the centre row is a 1x1 pivot first and level k
+// takes (m-k, m+k)); the two pivot rows of the reduced matrix become rows of
+// Z0, the two W0 columns come from one 2x2 solve per remaining row, and the
+// remaining rows get a rank-2 update.  Z0 x = y is then solved from both
+// ends inwards, one 2x2 system per level.
+//
+// GPU formulation.  On a band of half-width q only a 2q x 2q "frontier"
+// block of the reduced matrix is ever modified: the q not-yet-eliminated
+// rows left of the eliminated centre and the q rows right of it.  Each
+// level consumes the two innermost frontier rows as pivots and brings in one
+// new band row at each end.  A frontier row keeps its slot for its whole
+// lifetime: left index g lives in slot (P1_0 - g) mod q, right index g in
+// q + (g - P2_0) mod q, so the pivots of level k sit in slots j and q+j
+// with j = (k-1) mod q, and the new rows of level k take those same slots.
+// Unrolling the level loop by q makes every slot index a compile-time
+// constant and the frontier never moves between lanes.
+//
+// One system per 2q*2q lanes (q = 2: four systems per wave; q = 4: one per
+// wave; q = 8: one per wave, four frontier elements per lane).  Per level a
+// lane publishes its frontier element to LDS, reads back the pivot block,
+// its row's two pivot-column entries and its column's two pivot-row
+// entries, and applies the rank-2 update to its element.  New band entries
+// are prefetched q levels ahead into registers.  The forward solve
+// W0 y = b is fused into the elimination (the right-hand side rides along as
+// one more column).  Per level one record is written:
+//
+//   rec[0      .. 2q)    Z0 row p1 over the 2q outer unknowns (frontier slots
+//                        after the level), i.e. the coefficients the back
+//                        solve needs
+//   rec[2q     .. 4q)    Z0 row p2, same slots
+//   rec[4q     .. 4q+4)  inverse of the 2x2 pivot block, row major
+//                        (centre 1x1 level: [1/a, 0, 0, 0])
+//   rec[4q+4   .. 4q+6)  y(p1), y(p2) of the forward solve
+//   rec[4q+6   .. 8q+6)  (optional) W0 multipliers (w1, w2) of the row held
+//                        by each frontier slot after the level
+//
+// The back solve (Z0 x = y, ends inwards) runs in the same wave: 2q lanes
+// hold the solved outer unknowns of the frontier slots, each level forms two
+// dot products with a DPP butterfly, applies the stored inverse pivot and
+// drops the two new unknowns into slots j and q+j.
+#include "common.h"
+#include "paqif_args.h"
+
+namespace pq {
+
+template <int Q>
+struct Geo {
+    static constexpr int N2 = 2 * Q;
+    static constexpr int E = N2 * N2;
+    static constexpr int EPL = E > 64 ? E / 64 : 1;  // frontier elements per lane
+    static constexpr int LPS = E > 64 ? 64 : E;      // lanes per system
+    static constexpr int SPW = 64 / LPS;             // systems per wave
+    static constexpr int BW = 2 * Q + 1;             // band width
+    static constexpr int ZREC = 4 * Q + 6;           // record without W0
+    static constexpr int WREC = 4 * Q;               // W0 part of a record
+};
+
+// Number of level records of a system of order n: ceil(n/2).
+PQ_DEV int64_t level_base(int64_t row_offset, int sys) { return (row_offset + sys) >> 1; }
+
+struct SysView {
+    int n;
+    int npair;  // number of 2x2 levels
+    bool odd;
+    int P1_0, P2_0;  // pivots of the first 2x2 level
+    const double* band;
+    const uint8_t* pin;
+    const double* rhs;
+};
+
+PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8_t* pin,
+                         const double* rhs, int bw)
+{
+    SysView v;
+    v.n = (int)n;
+    v.odd = (n & 1) != 0;
+    if (v.odd) {
+        int m = (int)((n - 1) / 2);
+        v.npair = m;
+        v.P1_0 = m - 1;
+        v.P2_0 = m + 1;
+    } else {
+        int s = (int)(n / 2);
+        v.npair = s;
+        v.P1_0 = s - 1;
+        v.P2_0 = s;
+    }
+    v.band = band + off * bw;
+    v.pin = pin ? pin + off : nullptr;
+    v.rhs = rhs ? rhs + off : nullptr;
+    return v;
+}
+
+// Effective matrix entry: pinned rows/columns replaced by the identity.
+template <int Q>
+PQ_DEV double aeff(const SysView& v, int i, int j)
+{
+    if (i < 0 || j < 0 || i >= v.n || j >= v.n) return 0.0;
+    int d = j - i;
+    if (d < -Q || d > Q) return 0.0;
+    if (v.pin && (v.pin[i] | v.pin[j])) return i == j ? 1.0 : 0.0;
+    return v.band[(int64_t)i * (2 * Q + 1) + (d + Q)];
+}
+
+PQ_DEV double beff(const SysView& v, const double* rhs, int i)
+{
+    if (i < 0 || i >= v.n) return 0.0;
+    if (v.pin && v.pin[i]) return 0.0;
+    return rhs[i];
+}
+
+// Global index held by frontier slot c after level k (pivot slot j).
+template <int Q>
+PQ_DEV int slot_index_post(int c, int j, int p1k, int p2k)
+{
+    if (c < Q) return p1k - 1 - ((c - j - 1 + Q) & (Q - 1));
+    return p2k + 1 + ((c - Q - j - 1 + Q) & (Q - 1));
+}
+
+// Global index held by slot c before the first 2x2 level.
+template <int Q>
+PQ_DEV int slot_index_init(int c, const SysView& v)
+{
+    return c < Q ? v.P1_0 - c : v.P2_0 + (c - Q);
+}
+
+// --------------------------------------------------------------------------
+// Factorisation (+ fused forward solve when FUSED).
+// lF: LDS frontier (N2*N2), lY: LDS rhs column (N2), lX: LDS extras (6q).
+// rec: this system's first record, `stride` elements per record.
+// `kmax` = largest npair among the systems sharing the wave (loop bound).
+// Returns true if a pivot was singular / non-finite.
+//
+// Prefetch: within a block of q levels (j = 0..q-1) frontier element
+// (a, b) receives a new band entry exactly at j = a mod q (its row slot is
+// refilled) and at j = b mod q (its column slot is refilled).  So each lane
+// loads two values per element per block, one block ahead.  The six
+// per-level scalars (the four band entries coupling the pivots with the
+// incoming rows and the two incoming right-hand sides) are loaded by lanes
+// 0..6q-1, one block ahead, and published through LDS at the block start.
+// --------------------------------------------------------------------------
+template <int Q>
+PQ_DEV double level_extra(const SysView& v, const double* rhs, bool fused, int k, int e)
+{
+    const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
+    const int g1 = p1k - Q, g2 = p2k + Q;
+    switch (e) {
+    case 0: return aeff<Q>(v, p1k, g1);
+    case 1: return aeff<Q>(v, g1, p1k);
+    case 2: return aeff<Q>(v, p2k, g2);
+    case 3: return aeff<Q>(v, g2, p2k);
+    case 4: return fused ? beff(v, rhs, g1) : 0.0;
+    default: return fused ? beff(v, rhs, g2) : 0.0;
+    }
+}
+
+// New entry of element (a, b) at level k (pivot slot j = (k-1) mod q).
+template <int Q>
+PQ_DEV double level_new(const SysView& v, int k, int a, int b)
+{
+    const int j = (k - 1) & (Q - 1);
+    const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
+    return aeff<Q>(v, slot_index_post<Q>(a, j, p1k, p2k), slot_index_post<Q>(b, j, p1k, p2k));
+}
+
+template <int Q, typename FT, bool STORE_W, bool FUSED>
+__device__ __noinline__ bool factor_system(const SysView& v, bool live, FT* __restrict__ rec,
+                                           int stride, LDS_PTR(FT) lF, LDS_PTR(FT) lY,
+                                           LDS_PTR(FT) lX, int ls, int kmax)
+{
+    using G = Geo<Q>;
+    constexpr int N2 = G::N2;
+    constexpr int EPL = G::EPL;
+    const int b = ls % N2;
+    const int jc = b & (Q - 1);
+    int a[EPL], jr[EPL];
+#pragma unroll
+    for (int t = 0; t < EPL; t++) {
+        a[t] = (ls + 64 * t) / N2;
+        jr[t] = a[t] & (Q - 1);
+    }
+
+    bool bad = false;
+    FT f[EPL], y[EPL];
+    const double* rhs = v.rhs;
+
+    // ---- initial frontier (and the odd-n centre level) ------------------
+    const int ib0 = slot_index_init<Q>(b, v);
+    if (v.odd) {
+        const int m = v.npair;  // centre index (n = 2m+1)
+        const double amm = live ? aeff<Q>(v, m, m) : 1.0;
+        if (!(amm != 0.0 && isfinite(amm))) bad = true;
+        const double ramm = 1.0 / amm;
+        const double bm = (FUSED && live) ? beff(v, rhs, m) : 0.0;
+        const double amb = aeff<Q>(v, m, ib0);
+#pragma unroll
+        for (int t = 0; t < EPL; t++) {
+            const int ia = slot_index_init<Q>(a[t], v);
+            double aim = aeff<Q>(v, ia, m) * ramm;
+            f[t] = (FT)(aeff<Q>(v, ia, ib0) - aim * amb);
+            y[t] = FUSED ? (FT)(beff(v, rhs, ia) - aim * bm) : (FT)0;
+            if (STORE_W && live && b == 0) {
+                rec[4 * Q + 6 + 2 * a[t]] = (FT)aim;
+                rec[4 * Q + 6 + 2 * a[t] + 1] = (FT)0;
+            }
+        }
+        if (live) {
+            // centre record: Z0 row m over the frontier slots, 1x1 pivot
+            if (ls < N2) {
+                rec[ls] = (FT)amb;
+                rec[N2 + ls] = (FT)0;
+            }
+            if (ls == 0) {
+                rec[4 * Q + 0] = (FT)ramm;
+                rec[4 * Q + 1] = (FT)0;
+                rec[4 * Q + 2] = (FT)0;
+                rec[4 * Q + 3] = (FT)0;
+                rec[4 * Q + 4] = (FT)bm;
+                rec[4 * Q + 5] = (FT)0;
+            }
+        }
+        rec += stride;
+    } else {
+#pragma unroll
+        for (int t = 0; t < EPL; t++) {
+            const int ia = slot_index_init<Q>(a[t], v);
+            f[t] = (FT)aeff<Q>(v, ia, ib0);
+            y[t] = FUSED ? (FT)beff(v, rhs, ia) : (FT)0;
+        }
+    }
+
+    // ---- prefetch for block 0 ------------------------------------------
+    FT nR[EPL], nC[EPL], nX;
+    {
+#pragma unroll
+        for (int t = 0; t < EPL; t++) {
+            const int kr = jr[t] + 1, kc = jc + 1;
+            nR[t] = (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[t], b) : 0.0);
+            nC[t] = (FT)((live && kc <= v.npair && jc != jr[t]) ? level_new<Q>(v, kc, a[t], b)
+                                                                 : 0.0);
+        }
+        const int kx = ls / 6 + 1;
+        nX = (FT)((live && ls < 6 * Q && kx <= v.npair)
+                      ? level_extra<Q>(v, rhs, FUSED, kx, ls % 6)
+                      : 0.0);
+    }
+
+    // ---- level loop, unrolled by Q ----------------------------------------
+    for (int kb = 0; kb < kmax; kb += Q) {
+        // current block's prefetched values; issue loads for the next block
+        FT vR[EPL], vC[EPL];
+#pragma unroll
+        for (int t = 0; t < EPL; t++) {
+            vR[t] = nR[t];
+            vC[t] = nC[t];
+        }
+        if (ls < 6 * Q) lX[ls] = nX;
+        {
+            const int kn = kb + Q;
+#pragma unroll
+            for (int t = 0; t < EPL; t++) {
+                const int kr = kn + jr[t] + 1, kc = kn + jc + 1;
+                nR[t] = (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[t], b) : 0.0);
+                nC[t] = (FT)((live && kc <= v.npair && jc != jr[t])
+                                 ? level_new<Q>(v, kc, a[t], b)
+                                 : 0.0);
+            }
+            const int kx = kn + ls / 6 + 1;
+            nX = (FT)((live && ls < 6 * Q && kx <= v.npair)
+                          ? level_extra<Q>(v, rhs, FUSED, kx, ls % 6)
+                          : 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            const int k = kb + j + 1;  // level number (1-based)
+            if (k > kmax) break;
+            const bool act = live && (k <= v.npair);
+
+            // publish frontier and rhs column
+#pragma unroll
+            for (int t = 0; t < EPL; t++) lF[a[t] * N2 + b] = f[t];
+            if (b == 0) {
+#pragma unroll
+                for (int t = 0; t < EPL; t++) lY[a[t]] = y[t];
+            }
+            wave_sync();
+            const FT P11 = lF[j * N2 + j], P12 = lF[j * N2 + Q + j];
+            const FT P21 = lF[(Q + j) * N2 + j], P22 = lF[(Q + j) * N2 + Q + j];
+            const FT y1 = lY[j], y2 = lY[Q + j];
+            const FT c1 = lF[j * N2 + b], c2 = lF[(Q + j) * N2 + b];
+            FT r1[EPL], r2[EPL];
+#pragma unroll
+            for (int t = 0; t < EPL; t++) {
+                r1[t] = lF[a[t] * N2 + j];
+                r2[t] = lF[a[t] * N2 + Q + j];
+            }
+            const FT E0 = lX[6 * j + 0], E1 = lX[6 * j + 1], E2 = lX[6 * j + 2];
+            const FT E3 = lX[6 * j + 3], E4 = lX[6 * j + 4], E5 = lX[6 * j + 5];
+            wave_sync();
+
+            const FT det = P11 * P22 - P12 * P21;
+            if (act && !(det != (FT)0 && isfinite(det))) bad = true;
+            const FT rd = (FT)1 / det;
+            const FT i11 = P22 * rd, i12 = -P12 * rd, i21 = -P21 * rd, i22 = P11 * rd;
+
+            // record: Z0 rows p1, p2 over the slots after this level
+            if (act) {
+#pragma unroll
+                for (int t = 0; t < EPL; t++) {
+                    if (a[t] == j) rec[b] = (b == j) ? E0 : ((b == Q + j) ? (FT)0 : f[t]);
+                    if (a[t] == Q + j)
+                        rec[N2 + b] = (b == j) ? (FT)0 : ((b == Q + j) ? E2 : f[t]);
+                }
+                if (ls == 0) {
+                    rec[4 * Q + 0] = i11;
+                    rec[4 * Q + 1] = i12;
+                    rec[4 * Q + 2] = i21;
+                    rec[4 * Q + 3] = i22;
+                    rec[4 * Q + 4] = y1;
+                    rec[4 * Q + 5] = y2;
+                }
+            }
+
+            // pivot-row values at this lane's column (after the shift)
+            const FT cA = (b == j) ? E0 : ((b == Q + j) ? (FT)0 : c1);
+            const FT cB = (b == j) ? (FT)0 : ((b == Q + j) ? E2 : c2);
+#pragma unroll
+            for (int t = 0; t < EPL; t++) {
+                FT w1, w2;
+                if (a[t] == j) {
+                    w1 = E1 * i11;
+                    w2 = E1 * i12;
+                } else if (a[t] == Q + j) {
+                    w1 = E3 * i21;
+                    w2 = E3 * i22;
+                } else {
+                    w1 = r1[t] * i11 + r2[t] * i21;
+                    w2 = r1[t] * i12 + r2[t] * i22;
+                }
+                const FT base = (jr[t] == j) ? vR[t] : ((jc == j) ? vC[t] : f[t]);
+                f[t] = base - (w1 * cA + w2 * cB);
+                if (FUSED) {
+                    const FT yb = (a[t] == j) ? E4 : ((a[t] == Q + j) ? E5 : y[t]);
+                    y[t] = yb - (w1 * y1 + w2 * y2);
+                }
+                if (STORE_W && act && b == 0) {
+                    rec[4 * Q + 6 + 2 * a[t]] = w1;
+                    rec[4 * Q + 6 + 2 * a[t] + 1] = w2;
+                }
+            }
+            rec += stride;
+        }
+    }
+    return bad;
+}
+
+// --------------------------------------------------------------------------
+// Forward solve W0 y = rhs with stored multipliers; writes y(p1), y(p2) into
+// the records (used when the forward solve was not fused).  2q lanes per
+// system hold the running right-hand side of their frontier slot.
+// --------------------------------------------------------------------------
+template <int Q, typename FT>
+__device__ __noinline__ void wsolve_system(const SysView& v, bool live, const double* __restrict__ rhs,
+                          FT* __restrict__ rec, int stride, int ls, int kmax, int gbase)
+{
+    constexpr int N2 = 2 * Q;
+    const bool mine = ls < N2;
+    const int c = mine ? ls : 0;
+    double bc = 0.0;
+    if (v.odd) {
+        const int m = v.npair;
+        const double ym = live ? beff(v, rhs, m) : 0.0;
+        if (mine && live) {
+            bc = beff(v, rhs, slot_index_init<Q>(c, v)) - (double)rec[4 * Q + 6 + 2 * c] * ym;
+            if (ls == 0) rec[4 * Q + 4] = (FT)ym;
+        }
+        rec += stride;
+    } else if (mine && live) {
+        bc = beff(v, rhs, slot_index_init<Q>(c, v));
+    }
+    for (int kb = 0; kb < kmax; kb += Q) {
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            const int k = kb + j + 1;
+            if (k > kmax) break;
+            const bool act = live && (k <= v.npair);
+            const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
+            const double y1 = __shfl(bc, gbase + j);
+            const double y2 = __shfl(bc, gbase + Q + j);
+            if (act && mine) {
+                double base = bc;
+                if (c == j) base = beff(v, rhs, p1k - Q);
+                if (c == Q + j) base = beff(v, rhs, p2k + Q);
+                const double w1 = (double)rec[4 * Q + 6 + 2 * c];
+                const double w2 = (double)rec[4 * Q + 6 + 2 * c + 1];
+                bc = base - (w1 * y1 + w2 * y2);
+                if (c == 0) {
+                    rec[4 * Q + 4] = (FT)y1;
+                    rec[4 * Q + 5] = (FT)y2;
+                }
+            }
+            rec += stride;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Back solve Z0 x = y, from both ends inwards.  x written to `x` (system
+// base).  2q lanes per system hold the outer unknowns of the frontier slots.
+// The q records of a block are contiguous; the system's lanes load the next
+// block (going inwards) into registers while the current one is solved from
+// LDS.  If ADD, x += solution instead of x = solution.
+// --------------------------------------------------------------------------
+template <int Q, typename FT, bool ADD>
+__device__ __noinline__ void back_system(const SysView& v, bool live, const FT* __restrict__ rec0,
+                                         int stride, double* __restrict__ x, LDS_PTR(FT) lB,
+                                         int ls, int kmax)
+{
+    using G = Geo<Q>;
+    constexpr int N2 = 2 * Q;
+    constexpr int LPS = G::LPS;
+    const bool mine = ls < N2;
+    const int c = mine ? ls : 0;
+    const int blk = Q * stride;                  // elements per block of records
+    const int per_lane = (blk + LPS - 1) / LPS;  // <= MAXPL
+    constexpr int MAXPL = (Q * (8 * Q + 6) + LPS - 1) / LPS;
+    double xs = 0.0;
+    const FT* recp = rec0 + (v.odd ? stride : 0);  // first 2x2 level record
+    const int kb_last = kmax > 0 ? ((kmax - 1) / Q) * Q : -Q;
+    const int64_t lim = live ? (int64_t)v.npair * stride : 0;  // valid elements from recp
+
+    FT nb[MAXPL];
+    auto load_block = [&](int kb) {
+#pragma unroll
+        for (int r = 0; r < MAXPL; r++) {
+            const int e = ls + LPS * r;
+            const int64_t ge = (int64_t)kb * stride + e;
+            nb[r] = (r < per_lane && e < blk && kb >= 0 && ge < lim) ? recp[ge] : (FT)0;
+        }
+    };
+    load_block(kb_last);
+    for (int kb = kb_last; kb >= 0; kb -= Q) {
+#pragma unroll
+        for (int r = 0; r < MAXPL; r++) {
+            const int e = ls + LPS * r;
+            if (r < per_lane && e < blk) lB[e] = nb[r];
+        }
+        wave_sync();
+        load_block(kb - Q);
+#pragma unroll
+        for (int jj = Q - 1; jj >= 0; jj--) {
+            const int k = kb + jj + 1;
+            if (k > kmax) continue;
+            const bool act = live && (k <= v.npair);
+            LDS_PTR(FT) r = lB + jj * stride;
+            const double z1 = (double)r[c], z2 = (double)r[N2 + c];
+            const double i11 = (double)r[4 * Q + 0], i12 = (double)r[4 * Q + 1];
+            const double i21 = (double)r[4 * Q + 2], i22 = (double)r[4 * Q + 3];
+            const double y1 = (double)r[4 * Q + 4], y2 = (double)r[4 * Q + 5];
+            const double s1 = group_sum<N2>(mine ? z1 * xs : 0.0);
+            const double s2 = group_sum<N2>(mine ? z2 * xs : 0.0);
+            const double r1 = y1 - s1, r2 = y2 - s2;
+            const double x1 = i11 * r1 + i12 * r2;
+            const double x2 = i21 * r1 + i22 * r2;
+            if (act) {
+                if (c == jj && mine) xs = x1;
+                if (c == Q + jj && mine) xs = x2;
+                const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
+                if (ls == 0) {
+                    if (ADD) {
+                        x[p1k] += x1;
+                        x[p2k] += x2;
+                    } else {
+                        x[p1k] = x1;
+                        x[p2k] = x2;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+    if (v.odd && live) {
+        const FT* r = rec0;
+        const double z = (double)r[c];
+        const double s = group_sum<N2>(mine ? z * xs : 0.0);
+        const double xm = (double)r[4 * Q] * ((double)r[4 * Q + 4] - s);
+        if (ls == 0) {
+            if (ADD)
+                x[v.npair] += xm;
+            else
+                x[v.npair] = xm;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Kernels
+// --------------------------------------------------------------------------
+
+template <int Q, typename FT>
+struct LdsBlock {
+    FT F[Geo<Q>::SPW][Geo<Q>::E];
+    FT Y[Geo<Q>::SPW][Geo<Q>::N2];
+    FT X[Geo<Q>::SPW][6 * Q];
+    FT B[Geo<Q>::SPW][Q * (8 * Q + 6)];
+};
+
+template <typename T>
+PQ_DEV LDS_PTR(T) as_lds(T* p)
+{
+    return (LDS_PTR(T))p;
+}
+
+// Residual pass over one system: w = A u - b with the original band.
+// Returns (in *changes) the number of active-set changes for LCP_EXACT.
+template <int Q>
+__device__ __noinline__ void residual_update(const SysView& v, bool live, const LcpArgs& A, int64_t off, int ls,
+                            bool update, bool write_w, int& changes, int& nonfinite)
+{
+    using G = Geo<Q>;
+    constexpr int BW = G::BW;
+    const double* u = A.u + off;
+    const double* bb = A.b + off;
+    const double* band = A.band + off * BW;
+    int ch = 0, nf = 0;
+    if (live) {
+        for (int i = ls; i < v.n; i += G::LPS) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < BW; d++) {
+                const int jcol = i + d - Q;
+                if (jcol >= 0 && jcol < v.n) s += band[(int64_t)i * BW + d] * u[jcol];
+            }
+            const double wi = s - bb[i];
+            const double ui = u[i];
+            if (!isfinite(ui)) nf = 1;
+            if (write_w && A.w) A.w[off + i] = wi;
+            if (update) {
+                const int bnd = A.bounded ? (A.bounded[off + i] != 0) : 1;
+                const int cur = A.act[off + i];
+                const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
+                ch += (nxt != cur);
+                A.act[off + i] = (uint8_t)nxt;
+            }
+        }
+    }
+    changes = group_sum_int<G::LPS>(ch);
+    nonfinite = group_max_int<G::LPS>(nf);
+}
+
+// Effective residual r = b_eff - A_eff u on one system (for refinement);
+// returns the group max |r| and max |b_eff|.
+template <int Q>
+__device__ __noinline__ void eff_residual(const SysView& v, bool live, const double* __restrict__ bsys,
+                         const double* __restrict__ u, double* __restrict__ r, int ls,
+                         double& rmax, double& bmax)
+{
+    using G = Geo<Q>;
+    double rm = 0.0, bm = 0.0;
+    if (live) {
+        for (int i = ls; i < v.n; i += G::LPS) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < G::BW; d++) s += aeff<Q>(v, i, i + d - Q) * ((i + d - Q >= 0 && i + d - Q < v.n) ? u[i + d - Q] : 0.0);
+            const double be = beff(v, bsys, i);
+            const double ri = be - s;
+            r[i] = ri;
+            rm = fmax(rm, fabs(ri));
+            bm = fmax(bm, fabs(be));
+        }
+    }
+#pragma unroll
+    for (int m = G::LPS / 2; m >= 1; m >>= 1) {
+        rm = fmax(rm, __shfl_xor(rm, m, G::LPS));
+        bm = fmax(bm, __shfl_xor(bm, m, G::LPS));
+    }
+    rmax = rm;
+    bmax = bm;
+}
+
+// Whole LCP solve, one wave per SPW systems.
+template <int Q, typename FT>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) paqif_lcp_kernel(LcpArgs A)
+{
+    using G = Geo<Q>;
+    __shared__ LdsBlock<Q, FT> lds;
+    const int lane = threadIdx.x;
+    const int grp = lane / G::LPS;
+    const int ls = lane % G::LPS;
+    const int gbase = grp * G::LPS;
+    const int slot = blockIdx.x * G::SPW + grp;
+    const bool live = slot < A.count;
+    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    const int64_t off = live ? A.offsets[sys] : 0;
+    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    SysView v = make_view(off, n, A.band, A.act, A.b, G::BW);
+    if (!live) {
+        v.n = 0;
+        v.npair = 0;
+    }
+    int kmax = group_max_int<64>(v.npair);  // whole wave loops to the largest system
+    constexpr bool MIXED = sizeof(FT) == 4;
+    constexpr int stride = MIXED ? (G::ZREC + G::WREC) : G::ZREC;
+    FT* rec = reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride;
+
+    // clear the working active set
+    if (live)
+        for (int i = ls; i < v.n; i += G::LPS) A.act[off + i] = 0;
+    __syncthreads();
+
+    const bool exact = A.mode == LCP_EXACT;
+    const int max_it = exact ? max(A.max_iter, 1) : 1;
+    int st = SYS_OK;
+    int it = 0;
+    bool done = !live;
+    for (; it < max_it;) {
+        // ---- factor (+ forward) and back solve ----------------------------
+        bool bad;
+        if constexpr (!MIXED) {
+            bad = factor_system<Q, FT, false, true>(v, live && !done, rec, stride,
+                                                    as_lds(lds.F[grp]), as_lds(lds.Y[grp]),
+                                                    as_lds(lds.X[grp]), ls, kmax);
+            __syncthreads();
+            back_system<Q, FT, false>(v, live && !done, rec, stride, A.u + off,
+                                      as_lds(lds.B[grp]), ls, kmax);
+        } else {
+            bad = factor_system<Q, FT, true, false>(v, live && !done, rec, stride,
+                                                    as_lds(lds.F[grp]), as_lds(lds.Y[grp]),
+                                                    as_lds(lds.X[grp]), ls, kmax);
+            __syncthreads();
+            // u = 0, then refinement sweeps: r = b_eff - A_eff u; u += solve(r)
+            if (live && !done)
+                for (int i = ls; i < v.n; i += G::LPS) A.u[off + i] = 0.0;
+            __syncthreads();
+            double bmax = 0.0, rmax = 0.0;
+            int steps = 0;
+            bool conv = false;
+            for (;;) {
+                eff_residual<Q>(v, live && !done, A.b + off, A.u + off, A.r + off, ls, rmax, bmax);
+                const double tol = A.refine_tol * fmax(bmax, 1.0);
+                const bool ok_here = !(live && !done) || (rmax <= tol) || bad;
+                const int need = group_max_int<64>(ok_here ? 0 : 1);
+                conv = ok_here;
+                if (need == 0 || steps >= 8) break;
+                __syncthreads();
+                wsolve_system<Q, FT>(v, live && !done && !ok_here, A.r + off, rec, stride, ls,
+                                     kmax, gbase);
+                __syncthreads();
+                back_system<Q, FT, true>(v, live && !done && !ok_here, rec, stride, A.u + off,
+                                         as_lds(lds.B[grp]), ls, kmax);
+                __syncthreads();
+                steps++;
+            }
+            if (live && !done && !conv && !bad) st = SYS_REFINE_STALLED;
+        }
+        __syncthreads();
+        if (live && !done) it++;
+        const int badg = group_max_int<G::LPS>(bad ? 1 : 0);
+        if (live && !done && badg) {
+            st = SYS_ZERO_PIVOT;
+            done = true;
+        }
+
+        // ---- projection / residual / active-set update --------------------
+        int changes = 0, nonfinite = 0;
+        if (A.mode == LCP_CLIP && live && !done) {
+            for (int i = ls; i < v.n; i += G::LPS) {
+                const int bnd = A.bounded ? (A.bounded[off + i] != 0) : 1;
+                const double ui = A.u[off + i];
+                if (bnd && ui < 0.0) {
+                    A.u[off + i] = 0.0;
+                    A.act[off + i] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        residual_update<Q>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
+        __syncthreads();
+        if (live && !done) {
+            if (nonfinite) {
+                st = SYS_NONFINITE;
+                done = true;
+            } else if (!exact || changes == 0) {
+                done = true;
+            } else if (it >= max_it) {
+                st = SYS_LCP_NOT_CONVERGED;
+                done = true;
+            }
+        }
+        const int all_done = group_max_int<64>(done ? 0 : 1) == 0;
+        if (all_done) break;
+        // systems that are done keep their results; the loop continues for
+        // the others in the wave
+    }
+    if (live) {
+        if (A.active_out)
+            for (int i = ls; i < v.n; i += G::LPS) A.active_out[off + i] = A.act[off + i];
+        if (ls == 0) {
+            A.status[sys] = st;
+            if (A.iters) A.iters[sys] = it;
+        }
+    }
+}
+
+// Factor only (records with W0), no right-hand side.
+
+template <int Q>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) paqif_factor_kernel(FactorArgs A)
+{
+    using G = Geo<Q>;
+    __shared__ LdsBlock<Q, double> lds;
+    const int lane = threadIdx.x;
+    const int grp = lane / G::LPS;
+    const int ls = lane % G::LPS;
+    const int slot = blockIdx.x * G::SPW + grp;
+    const bool live = slot < A.count;
+    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    const int64_t off = live ? A.offsets[sys] : 0;
+    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    SysView v = make_view(off, n, A.band, A.pinned, nullptr, G::BW);
+    if (!live) {
+        v.n = 0;
+        v.npair = 0;
+    }
+    const int kmax = group_max_int<64>(v.npair);
+    constexpr int stride = G::ZREC + G::WREC;
+    double* rec = reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride;
+    bool bad = factor_system<Q, double, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
+                                                     as_lds(lds.Y[grp]), as_lds(lds.X[grp]), ls,
+                                                     kmax);
+    const int badg = group_max_int<G::LPS>(bad ? 1 : 0);
+    if (live && ls == 0) A.status[sys] = badg ? SYS_ZERO_PIVOT : SYS_OK;
+}
+
+
+template <int Q>
+__global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
+{
+    using G = Geo<Q>;
+    __shared__ LdsBlock<Q, double> lds;
+    const int lane = threadIdx.x;
+    const int grp = lane / G::LPS;
+    const int ls = lane % G::LPS;
+    const int gbase = grp * G::LPS;
+    const int slot = blockIdx.x * G::SPW + grp;
+    const bool live = slot < A.count;
+    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    const int64_t off = live ? A.offsets[sys] : 0;
+    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    SysView v = make_view(off, n, nullptr, A.pinned, nullptr, G::BW);
+    if (!live) {
+        v.n = 0;
+        v.npair = 0;
+    }
+    const int kmax = group_max_int<64>(v.npair);
+    constexpr int stride = G::ZREC + G::WREC;
+    double* rec = reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride;
+    wsolve_system<Q, double>(v, live, A.rhs + off, rec, stride, ls, kmax, gbase);
+    __syncthreads();
+    back_system<Q, double, false>(v, live, rec, stride, A.x + off, as_lds(lds.B[grp]), ls, kmax);
+}
+
+// --------------------------------------------------------------------------
+// Host launchers
+// --------------------------------------------------------------------------
+template <int Q>
+static int launch_lcp(const LcpArgs& a, int prec, hipStream_t s)
+{
+    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    if (grid == 0) return PAQIF_OK;
+    if (prec == PREC_FP32_IR)
+        hipLaunchKernelGGL((paqif_lcp_kernel<Q, float>), dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((paqif_lcp_kernel<Q, double>), dim3(grid), dim3(64), 0, s, a);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+template <int Q>
+static int launch_factor(const FactorArgs& a, hipStream_t s)
+{
+    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    if (grid == 0) return PAQIF_OK;
+    hipLaunchKernelGGL((paqif_factor_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+template <int Q>
+static int launch_solve(const SolveArgs& a, hipStream_t s)
+{
+    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    if (grid == 0) return PAQIF_OK;
+    hipLaunchKernelGGL((paqif_solve_factored_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+int record_stride(int q, bool with_w) { return (4 * q + 6) + (with_w ? 4 * q : 0); }
+
+int dispatch_lcp(int q, const LcpArgs& a, int prec, hipStream_t s)
+{
+    switch (q) {
+    case 2: return launch_lcp<2>(a, prec, s);
+    case 4: return launch_lcp<4>(a, prec, s);
+    case 8: return launch_lcp<8>(a, prec, s);
+    default: return PAQIF_EINVAL;
+    }
+}
+
+int dispatch_factor(int q, const FactorArgs& a, hipStream_t s)
+{
+    switch (q) {
+    case 2: return launch_factor<2>(a, s);
+    case 4: return launch_factor<4>(a, s);
+    case 8: return launch_factor<8>(a, s);
+    default: return PAQIF_EINVAL;
+    }
+}
+
+int dispatch_solve(int q, const SolveArgs& a, hipStream_t s)
+{
+    switch (q) {
+    case 2: return launch_solve<2>(a, s);
+    case 4: return launch_solve<4>(a, s);
+    case 8: return launch_solve<8>(a, s);
+    default: return PAQIF_EINVAL;
+    }
+}
+
+}  // namespace pq

@@ -1,0 +1,54 @@
+// Launch arguments of the PAQIF kernels (internal; shared by paqif.hip and
+// api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pq {
+
+struct LcpArgs {
+    int32_t count;
+    const int64_t* offsets;
+    const int32_t* order;
+    const double* band;
+    const double* b;
+    const uint8_t* bounded;
+    int mode;
+    int max_iter;
+    double refine_tol;
+    double* u;
+    double* w;
+    uint8_t* active_out;
+    int32_t* status;
+    int32_t* iters;
+    void* rec;     // level records
+    uint8_t* act;  // working active flags (total_rows)
+    double* r;     // refinement residual (total_rows), FP32_IR only
+};
+
+struct FactorArgs {
+    int32_t count;
+    const int64_t* offsets;
+    const int32_t* order;
+    const double* band;
+    const uint8_t* pinned;
+    void* rec;
+    int32_t* status;
+};
+
+struct SolveArgs {
+    int32_t count;
+    const int64_t* offsets;
+    const int32_t* order;
+    const uint8_t* pinned;
+    void* rec;
+    const double* rhs;
+    double* x;
+};
+
+int dispatch_lcp(int q, const LcpArgs& a, int prec, hipStream_t s);
+int dispatch_factor(int q, const FactorArgs& a, hipStream_t s);
+int dispatch_solve(int q, const SolveArgs& a, hipStream_t s);
+int record_stride(int q, bool with_w);
+
+}  // namespace pq

@@ -1,0 +1,117 @@
+"""Torch-facing wrappers of the PAQIF entry points (marshalling only).
+
+Inputs are CUDA (HIP) tensors; the library works on the current torch
+stream and never allocates: workspaces are allocated here with torch and
+passed in.  Band layout: ``band[i, d] = a(i, i+d-q)`` for the concatenated
+rows of all systems, ``offsets`` the int64 row offsets (count+1 entries).
+"""
+import ctypes
+
+import torch
+
+from . import _binding as B
+
+_HANDLES = {}
+
+
+def handle(device=None):
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    h = _HANDLES.get(dev)
+    if h is None:
+        with torch.cuda.device(dev):
+            hv = ctypes.c_void_p()
+            B.check(B.lib().paqif_create(ctypes.byref(hv)), "paqif_create")
+        h = hv.value
+        _HANDLES[dev] = h
+    return h
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+class Batch:
+    """Host + device description of a batch of band systems (one q)."""
+
+    def __init__(self, offsets, q, device=None, order=None):
+        offs = torch.as_tensor(offsets, dtype=torch.int64).cpu()
+        self.count = int(offs.numel() - 1)
+        self.q = int(q)
+        sizes = offs[1:] - offs[:-1]
+        self.max_n = int(sizes.max()) if self.count > 0 else 0
+        self.total_rows = int(offs[-1]) if self.count > 0 else 0
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.offsets = offs.to(device)
+        if order == "lpt":  # largest systems first
+            order = torch.argsort(sizes, descending=True, stable=True).to(torch.int32)
+        self.order = None if order is None else torch.as_tensor(order, dtype=torch.int32).to(device)
+        self.sizes = sizes
+        self.c = B.PaqifBatch(self.count, self.q, self.offsets.data_ptr(), self.max_n,
+                              self.total_rows,
+                              self.order.data_ptr() if self.order is not None else None)
+
+    def workspace_bytes(self, prec=B.PREC_FP64, mode=B.LCP_EXACT):
+        n = B.lib().paqif_workspace_bytes(handle(), ctypes.byref(self.c), prec, mode)
+        if n == 0 and self.count > 0:
+            raise ValueError("invalid batch description")
+        return int(n)
+
+    def workspace(self, prec=B.PREC_FP64, mode=B.LCP_EXACT):
+        return torch.empty(self.workspace_bytes(prec, mode), dtype=torch.uint8,
+                           device=self.offsets.device)
+
+
+def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
+              refine_tol=1e-10, max_iter=64, workspace=None, want_w=True, want_active=True):
+    """PAQIF solve of the banded LCP for every system of ``batch``.
+
+    Returns dict(u, w, active, status, iters) (device tensors)."""
+    _need(band, torch.float64, "band")
+    _need(b, torch.float64, "b")
+    if bounded is not None:
+        _need(bounded, torch.uint8, "bounded")
+    dev = band.device
+    n = batch.total_rows
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    w = torch.empty(n, dtype=torch.float64, device=dev) if want_w else None
+    act = torch.empty(n, dtype=torch.uint8, device=dev) if want_active else None
+    st = torch.empty(batch.count, dtype=torch.int32, device=dev)
+    it = torch.empty(batch.count, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = batch.workspace(prec, mode)
+    code = B.lib().paqif_solve_lcp(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
+                                   _ptr(bounded), mode, prec, refine_tol, max_iter, _ptr(u),
+                                   _ptr(w), _ptr(act), _ptr(st), _ptr(it), _ptr(workspace),
+                                   _stream())
+    B.check(code, "paqif_solve_lcp")
+    return dict(u=u, w=w, active=act, status=st, iters=it)
+
+
+def factor(batch, band, pinned=None, factors=None):
+    """A = W0 Z0 for every system; returns (factors, status)."""
+    _need(band, torch.float64, "band")
+    if factors is None:
+        factors = batch.workspace(B.PREC_FP64, B.LCP_LINEAR)
+    st = torch.empty(batch.count, dtype=torch.int32, device=band.device)
+    code = B.lib().paqif_factor(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(pinned),
+                                B.PREC_FP64, _ptr(factors), _ptr(st), _stream())
+    B.check(code, "paqif_factor")
+    return factors, st
+
+
+def solve_factored(batch, factors, rhs, pinned=None):
+    _need(rhs, torch.float64, "rhs")
+    x = torch.empty_like(rhs)
+    code = B.lib().paqif_solve_factored(handle(), ctypes.byref(batch.c), _ptr(factors),
+                                        _ptr(pinned), _ptr(rhs), _ptr(x), _stream())
+    B.check(code, "paqif_solve_factored")
+    return x
