@@ -9,6 +9,12 @@
 // Pointer into LDS (address space 3), so that out-of-line device functions
 // still emit ds_* instructions.
 #define LDS_PTR(T) __attribute__((address_space(3))) T*
+// Pointer into global memory (address space 1): out-of-line device functions
+// then emit global_* instead of flat_* memory instructions (flat accesses
+// also count against the LDS wait counter and would serialise the
+// per-level LDS exchange behind outstanding prefetch loads).
+#define GLB_PTR(T) __attribute__((address_space(1))) T*
+#define GLB(T, p) ((GLB_PTR(T))(p))
 
 namespace pq {
 

@@ -60,6 +60,24 @@ struct Geo {
     static constexpr int WREC = 4 * Q;               // W0 part of a record
 };
 
+// Opaque copy of a lane-varying value: the compiler must recompute what is
+// derived from it after this point, so per-lane constants of one phase are
+// not hoisted out of the outer active-set loop (which would keep them live,
+// in registers, across every other phase).
+PQ_DEV int launder(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+PQ_DEV int64_t uniform64(int64_t x)
+{
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Number of level records of a system of order n: ceil(n/2).
 PQ_DEV int64_t level_base(int64_t row_offset, int sys) { return (row_offset + sys) >> 1; }
 
@@ -68,9 +86,9 @@ struct SysView {
     int npair;  // number of 2x2 levels
     bool odd;
     int P1_0, P2_0;  // pivots of the first 2x2 level
-    const double* band;
-    const uint8_t* pin;
-    const double* rhs;
+    GLB_PTR(const double) band;
+    GLB_PTR(const uint8_t) pin;
+    GLB_PTR(const double) rhs;
 };
 
 PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8_t* pin,
@@ -90,9 +108,9 @@ PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8
         v.P1_0 = s - 1;
         v.P2_0 = s;
     }
-    v.band = band + off * bw;
-    v.pin = pin ? pin + off : nullptr;
-    v.rhs = rhs ? rhs + off : nullptr;
+    v.band = GLB(const double, band + off * bw);
+    v.pin = pin ? GLB(const uint8_t, pin + off) : nullptr;
+    v.rhs = rhs ? GLB(const double, rhs + off) : nullptr;
     return v;
 }
 
@@ -107,7 +125,7 @@ PQ_DEV double aeff(const SysView& v, int i, int j)
     return v.band[(int64_t)i * (2 * Q + 1) + (d + Q)];
 }
 
-PQ_DEV double beff(const SysView& v, const double* rhs, int i)
+PQ_DEV double beff(const SysView& v, GLB_PTR(const double) rhs, int i)
 {
     if (i < 0 || i >= v.n) return 0.0;
     if (v.pin && v.pin[i]) return 0.0;
@@ -145,7 +163,8 @@ PQ_DEV int slot_index_init(int c, const SysView& v)
 // 0..6q-1, one block ahead, and published through LDS at the block start.
 // --------------------------------------------------------------------------
 template <int Q>
-PQ_DEV double level_extra(const SysView& v, const double* rhs, bool fused, int k, int e)
+PQ_DEV double level_extra(const SysView& v, GLB_PTR(const double) rhs, bool fused, int k,
+                          int e)
 {
     const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
     const int g1 = p1k - Q, g2 = p2k + Q;
@@ -169,10 +188,11 @@ PQ_DEV double level_new(const SysView& v, int k, int a, int b)
 }
 
 template <int Q, typename FT, bool STORE_W, bool FUSED>
-__device__ __noinline__ bool factor_system(const SysView& v, bool live, FT* __restrict__ rec,
+PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec,
                                            int stride, LDS_PTR(FT) lF, LDS_PTR(FT) lY,
                                            LDS_PTR(FT) lX, int ls, int kmax)
 {
+    ls = launder(ls);
     using G = Geo<Q>;
     constexpr int N2 = G::N2;
     constexpr int EPL = G::EPL;
@@ -187,7 +207,7 @@ __device__ __noinline__ bool factor_system(const SysView& v, bool live, FT* __re
 
     bool bad = false;
     FT f[EPL], y[EPL];
-    const double* rhs = v.rhs;
+    GLB_PTR(const double) rhs = v.rhs;
 
     // ---- initial frontier (and the odd-n centre level) ------------------
     const int ib0 = slot_index_init<Q>(b, v);
@@ -365,9 +385,11 @@ __device__ __noinline__ bool factor_system(const SysView& v, bool live, FT* __re
 // system hold the running right-hand side of their frontier slot.
 // --------------------------------------------------------------------------
 template <int Q, typename FT>
-__device__ __noinline__ void wsolve_system(const SysView& v, bool live, const double* __restrict__ rhs,
-                          FT* __restrict__ rec, int stride, int ls, int kmax, int gbase)
+PQ_DEV void wsolve_system(SysView v, bool live, GLB_PTR(const double) rhs,
+                                           GLB_PTR(FT) rec, int stride, int ls, int kmax,
+                                           int gbase)
 {
+    ls = launder(ls);
     constexpr int N2 = 2 * Q;
     const bool mine = ls < N2;
     const int c = mine ? ls : 0;
@@ -417,10 +439,11 @@ __device__ __noinline__ void wsolve_system(const SysView& v, bool live, const do
 // LDS.  If ADD, x += solution instead of x = solution.
 // --------------------------------------------------------------------------
 template <int Q, typename FT, bool ADD>
-__device__ __noinline__ void back_system(const SysView& v, bool live, const FT* __restrict__ rec0,
-                                         int stride, double* __restrict__ x, LDS_PTR(FT) lB,
-                                         int ls, int kmax)
+PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
+                                         int stride, GLB_PTR(double) x, LDS_PTR(FT) lB, int ls,
+                                         int kmax)
 {
+    ls = launder(ls);
     using G = Geo<Q>;
     constexpr int N2 = 2 * Q;
     constexpr int LPS = G::LPS;
@@ -430,7 +453,7 @@ __device__ __noinline__ void back_system(const SysView& v, bool live, const FT* 
     const int per_lane = (blk + LPS - 1) / LPS;  // <= MAXPL
     constexpr int MAXPL = (Q * (8 * Q + 6) + LPS - 1) / LPS;
     double xs = 0.0;
-    const FT* recp = rec0 + (v.odd ? stride : 0);  // first 2x2 level record
+    GLB_PTR(const FT) recp = rec0 + (v.odd ? stride : 0);  // first 2x2 level record
     const int kb_last = kmax > 0 ? ((kmax - 1) / Q) * Q : -Q;
     const int64_t lim = live ? (int64_t)v.npair * stride : 0;  // valid elements from recp
 
@@ -485,7 +508,7 @@ __device__ __noinline__ void back_system(const SysView& v, bool live, const FT* 
         wave_sync();
     }
     if (v.odd && live) {
-        const FT* r = rec0;
+        GLB_PTR(const FT) r = rec0;
         const double z = (double)r[c];
         const double s = group_sum<N2>(mine ? z * xs : 0.0);
         const double xm = (double)r[4 * Q] * ((double)r[4 * Q + 4] - s);
@@ -519,14 +542,18 @@ PQ_DEV LDS_PTR(T) as_lds(T* p)
 // Residual pass over one system: w = A u - b with the original band.
 // Returns (in *changes) the number of active-set changes for LCP_EXACT.
 template <int Q>
-__device__ __noinline__ void residual_update(const SysView& v, bool live, const LcpArgs& A, int64_t off, int ls,
+PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off, int ls,
                             bool update, bool write_w, int& changes, int& nonfinite)
 {
+    ls = launder(ls);
     using G = Geo<Q>;
     constexpr int BW = G::BW;
-    const double* u = A.u + off;
-    const double* bb = A.b + off;
-    const double* band = A.band + off * BW;
+    GLB_PTR(const double) u = GLB(const double, A.u + off);
+    GLB_PTR(const double) bb = GLB(const double, A.b + off);
+    GLB_PTR(const double) band = GLB(const double, A.band + off * BW);
+    GLB_PTR(double) wout = A.w ? GLB(double, A.w + off) : nullptr;
+    GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
+    GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
     int ch = 0, nf = 0;
     if (live) {
         for (int i = ls; i < v.n; i += G::LPS) {
@@ -539,13 +566,13 @@ __device__ __noinline__ void residual_update(const SysView& v, bool live, const 
             const double wi = s - bb[i];
             const double ui = u[i];
             if (!isfinite(ui)) nf = 1;
-            if (write_w && A.w) A.w[off + i] = wi;
+            if (write_w && wout) wout[i] = wi;
             if (update) {
-                const int bnd = A.bounded ? (A.bounded[off + i] != 0) : 1;
-                const int cur = A.act[off + i];
+                const int bnd = bnds ? (bnds[i] != 0) : 1;
+                const int cur = act[i];
                 const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
                 ch += (nxt != cur);
-                A.act[off + i] = (uint8_t)nxt;
+                act[i] = (uint8_t)nxt;
             }
         }
     }
@@ -556,10 +583,11 @@ __device__ __noinline__ void residual_update(const SysView& v, bool live, const 
 // Effective residual r = b_eff - A_eff u on one system (for refinement);
 // returns the group max |r| and max |b_eff|.
 template <int Q>
-__device__ __noinline__ void eff_residual(const SysView& v, bool live, const double* __restrict__ bsys,
-                         const double* __restrict__ u, double* __restrict__ r, int ls,
-                         double& rmax, double& bmax)
+PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
+                                          GLB_PTR(const double) u, GLB_PTR(double) r, int ls,
+                                          double& rmax, double& bmax)
 {
+    ls = launder(ls);
     using G = Geo<Q>;
     double rm = 0.0, bm = 0.0;
     if (live) {
@@ -595,9 +623,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const int gbase = grp * G::LPS;
     const int slot = blockIdx.x * G::SPW + grp;
     const bool live = slot < A.count;
-    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
-    const int64_t off = live ? A.offsets[sys] : 0;
-    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    int64_t off = live ? A.offsets[sys] : 0;
+    int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    if constexpr (G::SPW == 1) {  // one system per wave: keep its scalars in SGPRs
+        sys = __builtin_amdgcn_readfirstlane(sys);
+        off = uniform64(off);
+        n = uniform64(n);
+    }
     SysView v = make_view(off, n, A.band, A.act, A.b, G::BW);
     if (!live) {
         v.n = 0;
@@ -606,7 +639,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     int kmax = group_max_int<64>(v.npair);  // whole wave loops to the largest system
     constexpr bool MIXED = sizeof(FT) == 4;
     constexpr int stride = MIXED ? (G::ZREC + G::WREC) : G::ZREC;
-    FT* rec = reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride;
+    GLB_PTR(FT) rec = GLB(FT, reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride);
 
     // clear the working active set
     if (live)
@@ -626,7 +659,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
                                                     as_lds(lds.F[grp]), as_lds(lds.Y[grp]),
                                                     as_lds(lds.X[grp]), ls, kmax);
             __syncthreads();
-            back_system<Q, FT, false>(v, live && !done, rec, stride, A.u + off,
+            back_system<Q, FT, false>(v, live && !done, rec, stride, GLB(double, A.u + off),
                                       as_lds(lds.B[grp]), ls, kmax);
         } else {
             bad = factor_system<Q, FT, true, false>(v, live && !done, rec, stride,
@@ -641,17 +674,21 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
             int steps = 0;
             bool conv = false;
             for (;;) {
-                eff_residual<Q>(v, live && !done, A.b + off, A.u + off, A.r + off, ls, rmax, bmax);
+                eff_residual<Q>(v, live && !done, GLB(const double, A.b + off),
+                                GLB(const double, A.u + off), GLB(double, A.r + off), ls, rmax,
+                                bmax);
                 const double tol = A.refine_tol * fmax(bmax, 1.0);
                 const bool ok_here = !(live && !done) || (rmax <= tol) || bad;
                 const int need = group_max_int<64>(ok_here ? 0 : 1);
                 conv = ok_here;
                 if (need == 0 || steps >= 8) break;
                 __syncthreads();
-                wsolve_system<Q, FT>(v, live && !done && !ok_here, A.r + off, rec, stride, ls,
+                wsolve_system<Q, FT>(v, live && !done && !ok_here, GLB(const double, A.r + off),
+                                     rec, stride, ls,
                                      kmax, gbase);
                 __syncthreads();
-                back_system<Q, FT, true>(v, live && !done && !ok_here, rec, stride, A.u + off,
+                back_system<Q, FT, true>(v, live && !done && !ok_here, rec, stride,
+                                         GLB(double, A.u + off),
                                          as_lds(lds.B[grp]), ls, kmax);
                 __syncthreads();
                 steps++;
@@ -719,9 +756,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const int ls = lane % G::LPS;
     const int slot = blockIdx.x * G::SPW + grp;
     const bool live = slot < A.count;
-    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
-    const int64_t off = live ? A.offsets[sys] : 0;
-    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    int64_t off = live ? A.offsets[sys] : 0;
+    int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    if constexpr (G::SPW == 1) {  // one system per wave: keep its scalars in SGPRs
+        sys = __builtin_amdgcn_readfirstlane(sys);
+        off = uniform64(off);
+        n = uniform64(n);
+    }
     SysView v = make_view(off, n, A.band, A.pinned, nullptr, G::BW);
     if (!live) {
         v.n = 0;
@@ -729,7 +771,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     }
     const int kmax = group_max_int<64>(v.npair);
     constexpr int stride = G::ZREC + G::WREC;
-    double* rec = reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride;
+    GLB_PTR(double) rec =
+        GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride);
     bool bad = factor_system<Q, double, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
                                                      as_lds(lds.Y[grp]), as_lds(lds.X[grp]), ls,
                                                      kmax);
@@ -749,9 +792,14 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
     const int gbase = grp * G::LPS;
     const int slot = blockIdx.x * G::SPW + grp;
     const bool live = slot < A.count;
-    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
-    const int64_t off = live ? A.offsets[sys] : 0;
-    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    int64_t off = live ? A.offsets[sys] : 0;
+    int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    if constexpr (G::SPW == 1) {  // one system per wave: keep its scalars in SGPRs
+        sys = __builtin_amdgcn_readfirstlane(sys);
+        off = uniform64(off);
+        n = uniform64(n);
+    }
     SysView v = make_view(off, n, nullptr, A.pinned, nullptr, G::BW);
     if (!live) {
         v.n = 0;
@@ -759,10 +807,13 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
     }
     const int kmax = group_max_int<64>(v.npair);
     constexpr int stride = G::ZREC + G::WREC;
-    double* rec = reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride;
-    wsolve_system<Q, double>(v, live, A.rhs + off, rec, stride, ls, kmax, gbase);
+    GLB_PTR(double) rec =
+        GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride);
+    wsolve_system<Q, double>(v, live, GLB(const double, A.rhs + off), rec, stride, ls, kmax,
+                             gbase);
     __syncthreads();
-    back_system<Q, double, false>(v, live, rec, stride, A.x + off, as_lds(lds.B[grp]), ls, kmax);
+    back_system<Q, double, false>(v, live, rec, stride, GLB(double, A.x + off),
+                                  as_lds(lds.B[grp]), ls, kmax);
 }
 
 // --------------------------------------------------------------------------
