@@ -157,6 +157,99 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch *batch, const double 
                     double refine_tol, int max_iter, double *u, double *w, uint8_t *active_out,
                     int32_t *sys_status, int32_t *sys_iters, void *workspace, void *stream);
 
+
+/* ------------------------------------------------------------------------
+ * Elastohydrodynamic lubrication (Sec. 3.3 of the paper)
+ * ------------------------------------------------------------------------ */
+
+/* Uniform grid: nx x ny nodes on [x0, x1] x [y0, y1]; ny == 1 is a line
+ * contact (y0, y1 ignored).  Line contact requires 5 <= nx <= 8192. */
+typedef struct {
+    int32_t nx, ny;
+    double x0, x1, y0, y1;
+} ehl_grid;
+
+/* Moes dimensionless load M and material parameter L of one instance.
+ * Line contact: alpha_bar = L sqrt(M / 2 pi), lam = 3 pi^2 / (8 M^2),
+ * p_h = alpha_bar / alpha with alpha = 1.7e-8 1/Pa, p0 = 1.98e8 Pa,
+ * z = 0.68 (appendix of the paper; line-contact forms derived from the
+ * Hertzian half width). */
+typedef struct {
+    double M, L;
+} ehl_params;
+
+/* Options of the hybrid Newton line iteration (Lhs1, eqs. 60-75). */
+typedef struct {
+    double omega;        /* relaxation of the pressure change, (0, 1]          */
+    double c_h0;         /* load-balance relaxation c of eq. 75                */
+    double switch_ratio; /* hybrid switch threshold on eps/h (paper: 0.6)      */
+    double tol;          /* convergence: max|dP| <= tol max(1,|P|), |load err| <= tol */
+    int32_t max_newton;  /* iteration cap (then SYS_NEWTON_NOT_CONVERGED)       */
+    int32_t kernel_terms;/* elastic coupling kept in the band: |k - j| <= 1 or 2 */
+    int32_t lcp_max_iter;/* active-set cap of the linearised LCP per step       */
+    int32_t deform_prec; /* PREC_FP64, PREC_FP32 or PREC_SPLIT_BF16 for K P;
+                            a low-precision run is finished by FP64 steps       */
+    int32_t lcp_prec;    /* PREC_FP64 or PREC_FP32_IR for the band LCP          */
+    int32_t steps_per_graph; /* Newton steps per captured HIP graph replay    */
+    int32_t start_rule;  /* 1: Hertzian P and H0 = 0.4/sqrt(M) - min_{|X|<=1}
+                            (X^2/2 + H_el); 0: use P and H0 as given           */
+} ehl_opts;
+
+/*
+ * ehl_deformation -- elastic film contribution H_el of B pressure fields on
+ * one grid (Sec. 3.3.1).  Line (ny == 1): H_el = K P with
+ * K[i][j] = -(1/pi) * integral of ln|x_i - x'| over the cell of node j;
+ * P, H_el: DEVICE, nx x B column major (P[i + nx*b]).  Point (ny > 1):
+ * H_el[i][j] = (2/pi^2) sum k2[|i-i'|][|j-j'|] P[i'][j'] with the closed-form
+ * 1/r cell integrals; P, H_el: DEVICE, B blocks of nx*ny, row major in x
+ * (P[b*nx*ny + i*ny + j]).
+ * prec: PREC_FP64 (MFMA f64), PREC_FP32 (MFMA f32) or PREC_SPLIT_BF16.
+ * workspace: DEVICE, ehl_deformation_workspace_bytes(grid, B) bytes.
+ */
+size_t ehl_deformation_workspace_bytes(const ehl_grid *grid, int B);
+int ehl_deformation(paqif_handle handle, const ehl_grid *grid, const double *P, int B, int prec,
+                    double *H_el, void *workspace, void *stream);
+
+/*
+ * ehl_jacobian_assemble -- line contact: residual R of the TVD
+ * finite-volume Reynolds operator (eqs. 62-65; van Leer limited flux) and
+ * the band Jacobian of the hybrid change (eq. 60: direct change where
+ * eps/h > switch_ratio and next to cavitation, weighted change e_i -
+ * (e_{i-1}+e_{i+1})/2 elsewhere; the distributed elastic kernel kept for
+ * |k - j| <= kernel_terms, eqs. 66-67, 74), returned as the linearised
+ * complementarity problem of each instance:  band = -dR/dsigma (rows of the
+ * nx-2 interior nodes, half-bandwidth 4, layout of paqif_solve_lcp), rhs =
+ * band * P + R, bounded = 1 where the node and both neighbours are direct.
+ *  params: DEVICE ehl_params[B];  P, H_el: DEVICE nx x B;  H0: DEVICE [B];
+ *  rough: DEVICE nx x B or NULL (added to the film);  R, rhs: DEVICE
+ *  (nx-2) x B (R may be NULL);  band: DEVICE (nx-2)*B*9;  bounded: DEVICE
+ *  uint8 (nx-2) x B;  direct: DEVICE uint8 nx x B or NULL.
+ */
+int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid *grid, const ehl_params *params,
+                          int B, const ehl_opts *opts, const double *P, const double *H_el,
+                          const double *H0, const double *rough, double *R, double *band,
+                          double *rhs, uint8_t *bounded, uint8_t *direct, void *stream);
+
+/*
+ * ehl_newton_tvd -- line contact: the hybrid Newton line iteration (Lhs1)
+ * for B instances on one grid until each converges or hits max_newton:
+ * deformation (MFMA), assembly, PAQIF solve of the linearised LCP (exact
+ * active set), P <- max(0, P + omega D (v - P)), H0 <- H0 - c (pi/2 -
+ * h sum P) (eq. 75).  Steps are captured in HIP graphs of steps_per_graph
+ * steps; the host reads the per-instance done flags after every replay
+ * (this call synchronises the stream).
+ *  P: DEVICE nx x B, in: start (ignored with start_rule 1), out: solution.
+ *  H0: DEVICE [B], in/out.  H: DEVICE nx x B out (film).  Hmin: DEVICE [B].
+ *  status: DEVICE int32[B] (SYS_OK, SYS_NEWTON_NOT_CONVERGED,
+ *  SYS_NEGATIVE_FILM, SYS_NONFINITE).  iters: DEVICE int32[B].
+ *  workspace: DEVICE, ehl_newton_workspace_bytes(handle, grid, B, opts).
+ */
+size_t ehl_newton_workspace_bytes(paqif_handle handle, const ehl_grid *grid, int B,
+                                  const ehl_opts *opts);
+int ehl_newton_tvd(paqif_handle handle, const ehl_grid *grid, const ehl_params *params, int B,
+                   const ehl_opts *opts, const double *rough, double *P, double *H0, double *H,
+                   double *Hmin, int32_t *status, int32_t *iters, void *workspace, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,5 +9,6 @@ from ._binding import (LCP_CLIP, LCP_EXACT, LCP_LINEAR, PREC_FP32, PREC_FP32_IR,
                        SYS_NEWTON_NOT_CONVERGED, SYS_NONFINITE, SYS_OK, SYS_REFINE_STALLED,
                        SYS_ZERO_PIVOT, LibraryMissing, lib)
 from . import paqif
+from . import ehl
 
-__all__ = ["lib", "paqif", "LibraryMissing"]
+__all__ = ["lib", "paqif", "ehl", "LibraryMissing"]

@@ -26,6 +26,24 @@ class PaqifBatch(ctypes.Structure):
                 ("total_rows", ctypes.c_int64), ("order", ctypes.c_void_p)]
 
 
+class EhlGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double)]
+
+
+class EhlParams(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_double), ("L", ctypes.c_double)]
+
+
+class EhlOpts(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("c_h0", ctypes.c_double),
+                ("switch_ratio", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_newton", ctypes.c_int32), ("kernel_terms", ctypes.c_int32),
+                ("lcp_max_iter", ctypes.c_int32), ("deform_prec", ctypes.c_int32),
+                ("lcp_prec", ctypes.c_int32), ("steps_per_graph", ctypes.c_int32),
+                ("start_rule", ctypes.c_int32)]
+
+
 class LibraryMissing(RuntimeError):
     pass
 
@@ -56,6 +74,17 @@ def lib():
         "paqif_solve_factored": ([vp, bp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_solve_lcp": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                              vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "ehl_deformation_workspace_bytes": ([ctypes.POINTER(EhlGrid), ctypes.c_int],
+                                            ctypes.c_size_t),
+        "ehl_deformation": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int, ctypes.c_int, vp, vp,
+                             vp], ctypes.c_int),
+        "ehl_jacobian_assemble": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int,
+                                   ctypes.POINTER(EhlOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                   vp], ctypes.c_int),
+        "ehl_newton_workspace_bytes": ([vp, ctypes.POINTER(EhlGrid), ctypes.c_int,
+                                        ctypes.POINTER(EhlOpts)], ctypes.c_size_t),
+        "ehl_newton_tvd": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int, ctypes.POINTER(EhlOpts),
+                            vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -5,11 +5,6 @@
 
 #include "paqif_args.h"
 
-struct paqif_handle_s {
-    int device;
-    int cu_count;
-};
-
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool valid_batch(const paqif_batch* b)
@@ -162,6 +157,7 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double*
     a.rec = ws;
     a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
     a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
+    a.skip = nullptr;
     return pq::dispatch_lcp(batch->q, a, prec, (hipStream_t)stream);
 }
 

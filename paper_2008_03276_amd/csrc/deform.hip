@@ -1,0 +1,367 @@
+// Elastic deformation on MFMA (gfx950).
+//
+// Line contact (Sec. 3.3.1, case 1): H_el = K P with K[i][j] = k[|i-j|],
+//   k[m] = -(1/pi) * (F((m + 1/2) h) - F((m - 1/2) h)),  F(t) = t ln|t| - t,
+// the exact integral of ln|x - x'| over the cell of node j (P piecewise
+// constant).  P holds B instances on the same grid (column major, N x B), so
+// the evaluation is a dense N x N by N x B contraction.  The Toeplitz matrix
+// is never stored: the kernel vector (N doubles) is staged in LDS and every
+// MFMA A-operand element is k[|i - j|].
+//
+// Point contact (case 2): H_el[i][j] = sum_{i',j'} k2[|i-i'|][|j-j'|] P[i'][j'],
+// k2 = (2/pi^2) * (cell integral of 1/r, closed form with asinh terms).  For
+// a fixed row offset d = i - i' the j-sum is a Toeplitz product, so an
+// output tile (16 j x 16 i) accumulates MFMAs with A = T_|d| (16 j x 4 j') and
+// B = P[i - d][j'] (4 j' x 16 i) over all d and j'.  The d range is split over
+// workgroups (fixed partition, partial sums reduced in a fixed order), so the
+// result is deterministic.
+//
+// Precisions: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32),
+// and split BF16: every operand x is split as x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi); hi*hi + hi*lo + lo*hi are accumulated in FP32 by
+// v_mfma_f32_16x16x16bf16_1k.
+#include "common.h"
+#include "ehl_internal.h"
+
+namespace pq {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+PQ_DEV double cell_log(double d, double h)
+{
+    auto F = [](double t) { return t == 0.0 ? 0.0 : t * log(fabs(t)) - t; };
+    return F(d + 0.5 * h) - F(d - 0.5 * h);
+}
+
+PQ_DEV double asinh_term(double a, double b) { return a == 0.0 ? 0.0 : fabs(a) * asinh(b / a); }
+
+PQ_DEV double cell_inv_r(double dx, double dy, double hx, double hy)
+{
+    const double xp = dx + 0.5 * hx, xm = dx - 0.5 * hx;
+    const double yp = dy + 0.5 * hy, ym = dy - 0.5 * hy;
+    return asinh_term(xp, yp) + asinh_term(yp, xp) - asinh_term(xm, yp) - asinh_term(yp, xm) -
+           asinh_term(xp, ym) - asinh_term(ym, xp) + asinh_term(xm, ym) + asinh_term(ym, xm);
+}
+
+// k[m], m = 0..N-1
+__global__ void line_kernel_vec(int N, double h, double* __restrict__ k)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < N) k[m] = -cell_log((double)m * h, h) / M_PI;
+}
+
+// k2[a][b], a < Nx, b < Ny (row major, stride Ny)
+__global__ void point_kernel_tab(int Nx, int Ny, double hx, double hy, double* __restrict__ k2)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < Nx * Ny) {
+        const int a = idx / Ny, b = idx % Ny;
+        k2[idx] = 2.0 / (M_PI * M_PI) * cell_inv_r(a * hx, b * hy, hx, hy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA helpers: one 16x16 accumulator tile, K-step 4 (FP64/FP32) or 16 (BF16).
+// Operand layout (16x16x4): lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// (BF16 16x16x16: four consecutive k per lane, k = 4*(l/16) + e).  Result
+// element r of lane l holds D[4*(l/16) + r][l%16] for the FP32 forms and
+// D[4*r + l/16][l%16] for the FP64 form (checked on the device).
+// ---------------------------------------------------------------------------
+PQ_DEV f64x4 mfma_f64(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+PQ_DEV f32x4 mfma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+PQ_DEV f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+PQ_DEV short to_bf16(float x)
+{
+    // round to nearest even
+    uint32_t u = __float_as_uint(x);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (short)(u >> 16);
+}
+
+PQ_DEV float from_bf16(short s) { return __uint_as_float(((uint32_t)(uint16_t)s) << 16); }
+
+PQ_DEV void split_bf16(float x, short& hi, short& lo)
+{
+    hi = to_bf16(x);
+    lo = to_bf16(x - from_bf16(hi));
+}
+
+// ---------------------------------------------------------------------------
+// Line contact: out[i + N*b] = sum_j k[|i-j|] P[j + N*b].
+// Workgroup = 4 waves; a wave owns 16 rows i and 32 columns b (two 16x16
+// accumulators); the workgroup covers 64 rows.  The whole kernel vector is
+// staged in LDS (N <= LINE_LDS_MAX).
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void __launch_bounds__(256) line_deform_kernel(int N, int B,
+                                                          const double* __restrict__ kvec,
+                                                          const double* __restrict__ P,
+                                                          double* __restrict__ out)
+{
+    extern __shared__ double sk[];  // N doubles
+    for (int t = threadIdx.x; t < N; t += blockDim.x) sk[t] = kvec[t];
+    __syncthreads();
+    const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int i0 = (blockIdx.x * 4 + wave) * 16;
+    const int b0 = blockIdx.y * 32;
+    const int li = l % 16, lk = l / 16;
+    const int i = i0 + li;  // A row of this lane
+    if (i0 >= N) return;    // whole wave out of range (uniform)
+    if constexpr (PREC == PREC_FP64) {
+        f64x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+        const int bA = b0 + li, bB = b0 + 16 + li;
+        const double* PA = P + (int64_t)bA * N;
+        const double* PB = P + (int64_t)bB * N;
+        for (int j0 = 0; j0 < N; j0 += 4) {
+            const int j = j0 + lk;
+            const bool jin = j < N;
+            const double a = (i < N && jin) ? sk[abs(i - j)] : 0.0;
+            const double x0 = (jin && bA < B) ? PA[j] : 0.0;
+            const double x1 = (jin && bB < B) ? PB[j] : 0.0;
+            c0 = mfma_f64(a, x0, c0);
+            c1 = mfma_f64(a, x1, c1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int io = i0 + 4 * r + lk;  // f64 result: row 4*r + l/16
+            if (io < N) {
+                if (b0 + li < B) out[(int64_t)(b0 + li) * N + io] = c0[r];
+                if (b0 + 16 + li < B) out[(int64_t)(b0 + 16 + li) * N + io] = c1[r];
+            }
+        }
+    } else if constexpr (PREC == PREC_FP32) {
+        f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+        const int bA = b0 + li, bB = b0 + 16 + li;
+        const double* PA = P + (int64_t)bA * N;
+        const double* PB = P + (int64_t)bB * N;
+        for (int j0 = 0; j0 < N; j0 += 4) {
+            const int j = j0 + lk;
+            const bool jin = j < N;
+            const float a = (i < N && jin) ? (float)sk[abs(i - j)] : 0.0f;
+            const float x0 = (jin && bA < B) ? (float)PA[j] : 0.0f;
+            const float x1 = (jin && bB < B) ? (float)PB[j] : 0.0f;
+            c0 = mfma_f32(a, x0, c0);
+            c1 = mfma_f32(a, x1, c1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int io = i0 + 4 * lk + r;
+            if (io < N) {
+                if (b0 + li < B) out[(int64_t)(b0 + li) * N + io] = c0[r];
+                if (b0 + 16 + li < B) out[(int64_t)(b0 + 16 + li) * N + io] = c1[r];
+            }
+        }
+    } else {  // split BF16, K-step 16: lane supplies k-indices 4*lk .. 4*lk+3
+        f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+        const int bA = b0 + li, bB = b0 + 16 + li;
+        const double* PA = P + (int64_t)bA * N;
+        const double* PB = P + (int64_t)bB * N;
+        for (int j0 = 0; j0 < N; j0 += 16) {
+            bf16x4 ah, al, xh0, xl0, xh1, xl1;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int j = j0 + 4 * lk + e;
+                const bool jin = j < N;
+                const float a = (i < N && jin) ? (float)sk[abs(i - j)] : 0.0f;
+                const float x0 = (jin && bA < B) ? (float)PA[j] : 0.0f;
+                const float x1 = (jin && bB < B) ? (float)PB[j] : 0.0f;
+                short h, lo;
+                split_bf16(a, h, lo);
+                ah[e] = h;
+                al[e] = lo;
+                split_bf16(x0, h, lo);
+                xh0[e] = h;
+                xl0[e] = lo;
+                split_bf16(x1, h, lo);
+                xh1[e] = h;
+                xl1[e] = lo;
+            }
+            c0 = mfma_bf16(ah, xh0, c0);
+            c0 = mfma_bf16(ah, xl0, c0);
+            c0 = mfma_bf16(al, xh0, c0);
+            c1 = mfma_bf16(ah, xh1, c1);
+            c1 = mfma_bf16(ah, xl1, c1);
+            c1 = mfma_bf16(al, xh1, c1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int io = i0 + 4 * lk + r;
+            if (io < N) {
+                if (b0 + li < B) out[(int64_t)(b0 + li) * N + io] = c0[r];
+                if (b0 + 16 + li < B) out[(int64_t)(b0 + 16 + li) * N + io] = c1[r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Point contact, one instance per blockIdx.z.  P, out: Nx x Ny row major
+// (P[i*Ny + j]).  Tile: 16 j (MFMA rows) x 16 i (MFMA columns) per wave,
+// 4 waves per workgroup along i.  blockIdx.y = segment s of the d range;
+// partial sums go to part[s][inst][Nx*Ny] and are reduced by
+// point_reduce_kernel.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void __launch_bounds__(256) point_deform_kernel(int Nx, int Ny, int nseg, int B,
+                                                           const double* __restrict__ k2,
+                                                           const double* __restrict__ P,
+                                                           double* __restrict__ part)
+{
+    const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int li = l % 16, lk = l / 16;
+    const int ntj = (Ny + 15) / 16;
+    const int tj = blockIdx.x % ntj;
+    const int ti = (blockIdx.x / ntj) * 4 + wave;
+    const int j0 = tj * 16, i0 = ti * 16;
+    const int s = blockIdx.y, inst = blockIdx.z;
+    if (i0 >= Nx) return;
+    const double* Pi = P + (int64_t)inst * Nx * Ny;
+    // d range covering i - i' for i in [i0, i0+16), i' in [0, Nx)
+    const int dlo = i0 - (Nx - 1), dhi = i0 + 15;
+    const int span = dhi - dlo + 1;
+    const int per = (span + nseg - 1) / nseg;
+    const int ds0 = dlo + s * per, ds1 = min(dhi, ds0 + per - 1);
+    const int jrow = j0 + li;  // A row (output j) of this lane
+    const int icol = i0 + li;  // B column (output i) of this lane
+    f64x4 c64 = {0, 0, 0, 0};
+    f32x4 c32 = {0, 0, 0, 0};
+    for (int d = ds0; d <= ds1; d++) {
+        const int ad = abs(d);
+        if (ad >= Nx) continue;
+        const double* krow = k2 + (int64_t)ad * Ny;
+        const int ip = icol - d;  // P row for this lane's B column
+        const bool iok = icol < Nx && ip >= 0 && ip < Nx;
+        const double* prow = Pi + (int64_t)(iok ? ip : 0) * Ny;
+        if constexpr (PREC == PREC_FP64 || PREC == PREC_FP32) {
+            for (int jp0 = 0; jp0 < Ny; jp0 += 4) {
+                const int jp = jp0 + lk;
+                const bool jok = jp < Ny;
+                const double a = (jrow < Ny && jok) ? krow[abs(jrow - jp)] : 0.0;
+                const double x = (iok && jok) ? prow[jp] : 0.0;
+                if constexpr (PREC == PREC_FP64)
+                    c64 = mfma_f64(a, x, c64);
+                else
+                    c32 = mfma_f32((float)a, (float)x, c32);
+            }
+        } else {
+            for (int jp0 = 0; jp0 < Ny; jp0 += 16) {
+                bf16x4 ah, al, xh, xl;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int jp = jp0 + 4 * lk + e;
+                    const bool jok = jp < Ny;
+                    const float a = (jrow < Ny && jok) ? (float)krow[abs(jrow - jp)] : 0.0f;
+                    const float x = (iok && jok) ? (float)prow[jp] : 0.0f;
+                    short h, lo;
+                    split_bf16(a, h, lo);
+                    ah[e] = h;
+                    al[e] = lo;
+                    split_bf16(x, h, lo);
+                    xh[e] = h;
+                    xl[e] = lo;
+                }
+                c32 = mfma_bf16(ah, xh, c32);
+                c32 = mfma_bf16(ah, xl, c32);
+                c32 = mfma_bf16(al, xh, c32);
+            }
+        }
+    }
+    double* dst = part + ((int64_t)s * B + inst) * Nx * Ny;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        // D row (output j): f64 result row 4*r + l/16, f32 result row 4*(l/16) + r
+        const int jo = j0 + (PREC == PREC_FP64 ? 4 * r + lk : 4 * lk + r);
+        const int io = i0 + li;  // D column = output i
+        if (jo < Ny && io < Nx)
+            dst[(int64_t)io * Ny + jo] = PREC == PREC_FP64 ? c64[r] : (double)c32[r];
+    }
+}
+
+__global__ void point_reduce_kernel(int64_t count, int nseg, const double* __restrict__ part,
+                                    double* __restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    double s = 0.0;
+    for (int g = 0; g < nseg; g++) s += part[(int64_t)g * count + idx];
+    out[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int launch_line_kernel_vec(int N, double h, double* k, hipStream_t s)
+{
+    hipLaunchKernelGGL(line_kernel_vec, dim3((N + 255) / 256), dim3(256), 0, s, N, h, k);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+int launch_point_kernel_tab(int Nx, int Ny, double hx, double hy, double* k2, hipStream_t s)
+{
+    hipLaunchKernelGGL(point_kernel_tab, dim3((Nx * Ny + 255) / 256), dim3(256), 0, s, Nx, Ny, hx,
+                       hy, k2);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+int launch_line_deform(int N, int B, int prec, const double* k, const double* P, double* out,
+                       hipStream_t s)
+{
+    if (N <= 0 || B <= 0) return PAQIF_OK;
+    dim3 grid((N + 63) / 64, (B + 31) / 32), block(256);
+    const size_t lds = (size_t)N * sizeof(double);
+    if (prec == PREC_FP64)
+        hipLaunchKernelGGL((line_deform_kernel<PREC_FP64>), grid, block, lds, s, N, B, k, P, out);
+    else if (prec == PREC_FP32)
+        hipLaunchKernelGGL((line_deform_kernel<PREC_FP32>), grid, block, lds, s, N, B, k, P, out);
+    else
+        hipLaunchKernelGGL((line_deform_kernel<PREC_SPLIT_BF16>), grid, block, lds, s, N, B, k, P,
+                           out);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+int point_segments(int Nx) { return Nx >= 128 ? 8 : 1; }
+
+size_t point_workspace_doubles(int Nx, int Ny, int B)
+{
+    return (size_t)Nx * Ny + (size_t)point_segments(Nx) * B * Nx * Ny;
+}
+
+int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const double* P,
+                        double* out, double* part, hipStream_t s)
+{
+    if (Nx <= 0 || Ny <= 0 || B <= 0) return PAQIF_OK;
+    const int nseg = point_segments(Nx);
+    const int ntj = (Ny + 15) / 16, nti = (Nx + 15) / 16;
+    dim3 grid(ntj * ((nti + 3) / 4), nseg, B), block(256);
+    if (prec == PREC_FP64)
+        hipLaunchKernelGGL((point_deform_kernel<PREC_FP64>), grid, block, 0, s, Nx, Ny, nseg, B,
+                           k2, P, part);
+    else if (prec == PREC_FP32)
+        hipLaunchKernelGGL((point_deform_kernel<PREC_FP32>), grid, block, 0, s, Nx, Ny, nseg, B,
+                           k2, P, part);
+    else
+        hipLaunchKernelGGL((point_deform_kernel<PREC_SPLIT_BF16>), grid, block, 0, s, Nx, Ny, nseg,
+                           B, k2, P, part);
+    if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    const int64_t count = (int64_t)B * Nx * Ny;
+    hipLaunchKernelGGL(point_reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       count, nseg, part, out);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+}  // namespace pq

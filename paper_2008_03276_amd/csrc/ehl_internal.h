@@ -1,0 +1,66 @@
+// Internal declarations of the EHL kernels (deformation, assembly, update).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "paqif_ehl.h"
+
+namespace pq {
+
+// deform.hip
+int launch_line_kernel_vec(int N, double h, double* k, hipStream_t s);
+int launch_point_kernel_tab(int Nx, int Ny, double hx, double hy, double* k2, hipStream_t s);
+int launch_line_deform(int N, int B, int prec, const double* k, const double* P, double* out,
+                       hipStream_t s);
+size_t point_workspace_doubles(int Nx, int Ny, int B);
+int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const double* P,
+                        double* out, double* part, hipStream_t s);
+
+// ehl_line.hip
+struct LineAssembleArgs {
+    int N, B, kterms;
+    double h, x0, switch_ratio;
+    const ehl_params* params;  // device, B
+    const double* kvec;        // N (device) or null: use kap
+    double kap[4];             // k[0..3] when kvec is null
+    const double* P;           // N x B
+    const double* Hel;         // N x B
+    const double* H0;          // B
+    const double* rough;       // N x B or null
+    const uint8_t* skip;       // B or null
+    double* R;                 // (N-2) x B or null
+    double* band;              // (N-2) x 9 per instance
+    double* rhs;               // (N-2) x B
+    uint8_t* bounded;          // (N-2) x B
+    uint8_t* direct;           // N x B or null
+};
+int launch_line_assemble(const LineAssembleArgs& a, hipStream_t s);
+
+struct LineUpdateArgs {
+    int N, B;
+    double h, omega, c_h0, tol, load_target;
+    const double* v;     // (N-2) x B, LCP solution (new pressure before weighting)
+    const uint8_t* direct;  // N x B
+    double* P;           // N x B
+    double* H0;          // B
+    uint8_t* done;       // B
+    int32_t* status;     // B
+    int32_t* iters;      // B
+    double* dP;          // B (last max change)
+    double* load_err;    // B
+};
+int launch_line_update_ws(const LineUpdateArgs& a, double* Pnew, hipStream_t s);
+
+struct LineInitArgs {
+    int N, B;
+    double h, x0;
+    double* P;  // N x B (Hertzian start written)
+};
+int launch_line_hertz(const LineInitArgs& a, hipStream_t s);
+int launch_line_h0_rule(int N, int B, double h, double x0, const ehl_params* params,
+                        const double* Hel, double* H0, hipStream_t s);
+int launch_line_film(int N, int B, double h, double x0, const double* Hel, const double* H0,
+                     const double* rough, double* H, double* Hmin, int32_t* argmin,
+                     hipStream_t s);
+
+}  // namespace pq

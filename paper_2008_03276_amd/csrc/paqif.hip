@@ -622,8 +622,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const int ls = lane % G::LPS;
     const int gbase = grp * G::LPS;
     const int slot = blockIdx.x * G::SPW + grp;
-    const bool live = slot < A.count;
+    bool live = slot < A.count;
     int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    if (live && A.skip && A.skip[sys]) live = false;
     int64_t off = live ? A.offsets[sys] : 0;
     int64_t n = live ? A.offsets[sys + 1] - off : 0;
     if constexpr (G::SPW == 1) {  // one system per wave: keep its scalars in SGPRs

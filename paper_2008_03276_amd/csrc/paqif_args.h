@@ -4,6 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Library handle (device properties).
+struct paqif_handle_s {
+    int device;
+    int cu_count;
+};
+
 namespace pq {
 
 struct LcpArgs {
@@ -24,6 +30,7 @@ struct LcpArgs {
     void* rec;     // level records
     uint8_t* act;  // working active flags (total_rows)
     double* r;     // refinement residual (total_rows), FP32_IR only
+    const uint8_t* skip;  // per system: nonzero = leave untouched (may be null)
 };
 
 struct FactorArgs {
