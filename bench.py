@@ -46,6 +46,54 @@ def cpu_baseline(batches, sample, nthreads):
     return solves / t_total
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def ehl_legs(P, torch, synth, dev, args):
+    """EHL solves/s: config 1 (N=257, M=20, L=10, one instance, time to
+    solution) and a batched line-contact sweep (N=1025, M log-uniform in
+    [10,1000], L uniform in [5,20]); FP64 and FP32-deformation (+FP64
+    refresh) variants; iterations and statuses reported."""
+    import time as _t
+    out = {}
+    # config 1
+    P.ehl.solve_line([20.0], [10.0], 257)  # warm-up (graph instantiation etc.)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    r = P.ehl.solve_line([20.0], [10.0], 257)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t0
+    log(f"ehl config1 done in {dt:.3f} s")
+    out["config1"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 3),
+                          status=int(r["status"][0]), newton_steps=int(r["iters"][0]),
+                          H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]))
+    # sweep
+    nb = args.ehl_sweep
+    M, L = synth.ehl_sweep_params(nb, seed=args.seed)
+    res = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("fp32_deform", P.PREC_FP32)):
+        opts = P.ehl.default_opts(deform_prec=prec, max_newton=2000, lcp_max_iter=16)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        r = P.ehl.solve_line(M, L, 1025, opts=opts)
+        torch.cuda.synchronize()
+        dt = _t.perf_counter() - t0
+        st = r["status"].cpu().numpy()
+        res[name] = dict(seconds=round(dt, 3), solves_per_s=round(nb / dt, 3),
+                         converged=int((st == 0).sum()), instances=nb,
+                         mean_newton_steps=float(r["iters"].float().mean()))
+        res[name]["_P"] = r["P"]
+        log(f"ehl sweep {name}: {dt:.2f} s, converged {res[name]['converged']}/{nb}")
+    d = (res["fp32_deform"]["_P"] - res["fp64"]["_P"]).abs().max() / \
+        res["fp64"]["_P"].abs().max()
+    for v in res.values():
+        v.pop("_P")
+    res["max_rel_diff_fp32_vs_fp64"] = float(d)
+    out["sweep_N1025"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +102,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-ehl", action="store_true")
+    ap.add_argument("--ehl-sweep", type=int, default=32,
+                    help="instances of the line-contact sweep leg (N=1025)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "
@@ -88,9 +139,11 @@ def main():
                                        refine_tol=1e-10)
         return out
 
+    log("inputs resident; warm-up")
     for _ in range(args.warmup):
         step(P.PREC_FP64)
     torch.cuda.synchronize()
+    log("timed LCP steps")
 
     # timed region: K steps, events per solve on the launching stream
     ev = {q: [] for q in QS}
@@ -126,6 +179,7 @@ def main():
                         active_frac=float(r["active"].float().mean().item()),
                         gbs=bytes_alg / (avg_ms / 1e3) / 1e9, bytes=bytes_alg)
 
+    log(f"LCP fp64: {ms_per_step:.2f} ms/step")
     # mixed precision (FP32 factors + FP64 refinement): same workload
     for _ in range(max(1, args.warmup // 2)):
         step(P.PREC_FP32_IR)
@@ -145,13 +199,17 @@ def main():
                                          max(1.0, float(u64.abs().max()))))
         mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
 
+    ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
+
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
     roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
                 kernel=f"paqif_lcp_kernel<{dom},double>")
 
+    log(f"LCP mixed: {ms_mixed:.2f} ms/step")
     cpu = None
     if not args.no_cpu:
+        log("cpu baseline (oracle)")
         nthreads = os.cpu_count() or 1
         v = cpu_baseline(batches, args.cpu_sample, nthreads)
         cpu = dict(value=round(v, 2), unit="LCP solves/s", cores=nthreads, kind="oracle",
@@ -181,6 +239,7 @@ def main():
                           "speedup_vs_fp64": round(ms_per_step / ms_mixed, 4),
                           "max_rel_err_vs_fp64": mixed_err,
                           "active_set_match": mixed_active_match},
+        "ehl": ehl,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
