@@ -139,6 +139,15 @@ def main():
                                        refine_tol=1e-10)
         return out
 
+    tune = {}
+    for q in QS:
+        g = gpu[q]
+        for prec, ws in ((P.PREC_FP64, "ws64"), (P.PREC_FP32_IR, "ws32")):
+            chosen, times = P.paqif.autotune(g["bt"], g["band"], g["f"], prec=prec,
+                                             workspace=g[ws])
+            tune[f"q{q}_{'fp64' if prec == P.PREC_FP64 else 'fp32ir'}"] = dict(
+                layout=chosen, ms=[round(t, 3) for t in times])
+    log(f"autotuned layouts: {tune}")
     log("inputs resident; warm-up")
     for _ in range(args.warmup):
         step(P.PREC_FP64)
@@ -239,6 +248,7 @@ def main():
                           "speedup_vs_fp64": round(ms_per_step / ms_mixed, 4),
                           "max_rel_err_vs_fp64": mixed_err,
                           "active_set_match": mixed_active_match},
+        "autotune": tune,
         "ehl": ehl,
         "roofline": roof,
         "cpu_baseline": cpu,

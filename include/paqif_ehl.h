@@ -158,6 +158,27 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch *batch, const double 
                     int32_t *sys_status, int32_t *sys_iters, void *workspace, void *stream);
 
 
+/*
+ * Lane layouts of the PAQIF LCP kernel (how many frontier elements a lane
+ * owns and how many systems share a wavefront; see the library source).
+ * paqif_layout_count(q): number of layouts for half-bandwidth q (0 if q is
+ * unsupported).  paqif_set_layout / paqif_get_layout: the layout used by
+ * paqif_solve_lcp (and the EHL Newton driver) for (q, prec) on this handle;
+ * PAQIF_EINVAL for an unknown q, prec or layout.
+ * paqif_autotune: times every layout on the caller's batch (one warm-up and
+ * one timed solve each, HIP events on `stream`, which it synchronises),
+ * stores the fastest in the handle and, if times_ms (host, float[count]) is
+ * not NULL, the measured times.  Arguments as for paqif_solve_lcp; u,
+ * sys_status and workspace are used as scratch.
+ */
+int paqif_layout_count(int q);
+int paqif_set_layout(paqif_handle handle, int q, int prec, int layout);
+int paqif_get_layout(paqif_handle handle, int q, int prec);
+int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *band,
+                   const double *b, const uint8_t *bounded, int mode, int prec, int max_iter,
+                   double *u, int32_t *sys_status, void *workspace, void *stream,
+                   float *times_ms);
+
 /* ------------------------------------------------------------------------
  * Elastohydrodynamic lubrication (Sec. 3.3 of the paper)
  * ------------------------------------------------------------------------ */

@@ -74,6 +74,11 @@ def lib():
         "paqif_solve_factored": ([vp, bp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_solve_lcp": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                              vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "paqif_layout_count": ([ctypes.c_int], ctypes.c_int),
+        "paqif_set_layout": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "paqif_get_layout": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "paqif_autotune": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
+                            vp, vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "ehl_deformation_workspace_bytes": ([ctypes.POINTER(EhlGrid), ctypes.c_int],
                                             ctypes.c_size_t),
         "ehl_deformation": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int, ctypes.c_int, vp, vp,

@@ -51,9 +51,13 @@ int paqif_create(paqif_handle* handle)
         return PAQIF_EHIP;
     }
     h->cu_count = 0;
+    for (int qi = 0; qi < 3; qi++)
+        for (int p = 0; p < 2; p++) h->layout[qi][p] = 0;
     if (hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) !=
         hipSuccess)
         h->cu_count = 0;
+    for (int qi = 0; qi < 3; qi++)
+        for (int p = 0; p < 2; p++) h->layout[qi][p] = 0;
     *handle = h;
     return PAQIF_OK;
 }
@@ -158,7 +162,68 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double*
     a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
     a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
     a.skip = nullptr;
-    return pq::dispatch_lcp(batch->q, a, prec, (hipStream_t)stream);
+    return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
+                            (hipStream_t)stream);
+}
+
+int paqif_layout_count(int q) { return pq::layouts_for(q); }
+
+int paqif_set_layout(paqif_handle handle, int q, int prec, int layout)
+{
+    if (!handle || pq::layouts_for(q) == 0) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if (layout < 0 || layout >= pq::layouts_for(q)) return PAQIF_EINVAL;
+    handle->layout[pq::q_index(q)][prec != 0] = layout;
+    return PAQIF_OK;
+}
+
+int paqif_get_layout(paqif_handle handle, int q, int prec)
+{
+    if (!handle || pq::layouts_for(q) == 0) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    return handle->layout[pq::q_index(q)][prec != 0];
+}
+
+int paqif_autotune(paqif_handle handle, const paqif_batch* batch, const double* band,
+                   const double* b, const uint8_t* bounded, int mode, int prec, int max_iter,
+                   double* u, int32_t* sys_status, void* workspace, void* stream,
+                   float* times_ms)
+{
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    const int nl = pq::layouts_for(batch->q);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return PAQIF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PAQIF_EHIP;
+    }
+    int best = 0;
+    float best_ms = 0.0f;
+    int st = PAQIF_OK;
+    for (int l = 0; l < nl && st == PAQIF_OK; l++) {
+        handle->layout[pq::q_index(batch->q)][prec != 0] = l;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == PAQIF_OK; rep++) {  // warm-up, then timed
+            if (hipEventRecord(e0, s) != hipSuccess) st = PAQIF_EHIP;
+            if (st == PAQIF_OK)
+                st = paqif_solve_lcp(handle, batch, band, b, bounded, mode, prec, 1e-10, max_iter,
+                                     u, nullptr, nullptr, sys_status, nullptr, workspace, stream);
+            if (st == PAQIF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                   hipEventSynchronize(e1) != hipSuccess ||
+                                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = PAQIF_EHIP;
+        }
+        if (times_ms) times_ms[l] = ms;
+        if (st == PAQIF_OK && (l == 0 || ms < best_ms)) {
+            best = l;
+            best_ms = ms;
+        }
+    }
+    handle->layout[pq::q_index(batch->q)][prec != 0] = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 }  // extern "C"

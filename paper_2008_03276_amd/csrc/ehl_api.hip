@@ -321,7 +321,9 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
         int e;
         if ((e = pq::launch_line_deform(N, B, dprec, kvec, P, hel, s))) return e;
         if ((e = pq::launch_line_assemble(aa, s))) return e;
-        if ((e = pq::dispatch_lcp(4, la, opts->lcp_prec, s))) return e;
+        if ((e = pq::dispatch_lcp(4, la, opts->lcp_prec,
+                                  handle->layout[1][opts->lcp_prec == PREC_FP32_IR], s)))
+            return e;
         return pq::launch_line_update_ws(ua, pn, s);
     };
 

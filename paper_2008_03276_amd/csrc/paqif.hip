@@ -48,16 +48,34 @@
 
 namespace pq {
 
-template <int Q>
+// Lane layouts: each lane owns a TR x TC tile of the 2q x 2q frontier; a
+// superblock of S blocks of q levels is prefetched one superblock ahead; WPE
+// is the occupancy the launch of 4096 systems needs.
+//   q=2: L0 1x1 (16 lanes/system, 4 per wave)   L1 1x2 (8 lanes, 8 per wave)
+//   q=4: L0 1x1 (64 lanes, 1 per wave)          L1 1x2 (32 lanes, 2 per wave)
+//        L2 2x2 (16 lanes, 4 per wave)
+//   q=8: L0 2x2 (64 lanes, 1 per wave)          L1 2x4 (32 lanes, 2 per wave)
+//        L2 1x4 (64 lanes, 1 per wave)
+constexpr int layout_count(int q) { return q == 2 ? 2 : 3; }
+
+template <int Q, int L>
 struct Geo {
     static constexpr int N2 = 2 * Q;
     static constexpr int E = N2 * N2;
-    static constexpr int EPL = E > 64 ? E / 64 : 1;  // frontier elements per lane
-    static constexpr int LPS = E > 64 ? 64 : E;      // lanes per system
-    static constexpr int SPW = 64 / LPS;             // systems per wave
-    static constexpr int BW = 2 * Q + 1;             // band width
-    static constexpr int ZREC = 4 * Q + 6;           // record without W0
-    static constexpr int WREC = 4 * Q;               // W0 part of a record
+    static constexpr int TR = Q == 8 ? (L == 2 ? 1 : 2) : (Q == 4 && L == 2 ? 2 : 1);
+    static constexpr int TC = Q == 8 ? (L == 1 ? 4 : (L == 2 ? 4 : 2)) : (L == 0 ? 1 : 2);
+    static constexpr int LPS = E / (TR * TC);  // lanes per system
+    static constexpr int SPW = 64 / LPS;       // systems per wave
+    static constexpr int CT = N2 / TC;         // column tiles per tile row
+    static constexpr int S = Q == 8 ? 1 : 16 / Q;  // blocks of q levels per prefetch superblock
+    static constexpr int SB = S * Q;               // levels per superblock
+    static constexpr int WPE = SPW == 1 ? 4 : (SPW == 2 ? 2 : 1);
+    static constexpr int BW = 2 * Q + 1;       // band width
+    static constexpr int ZREC = 4 * Q + 6;     // record without W0
+    static constexpr int WREC = 4 * Q;         // W0 part of a record
+    static_assert(LPS <= 64 && 64 % LPS == 0, "lanes per system");
+    static_assert(LPS >= N2, "back solve needs 2q lanes");
+    static_assert(N2 % TC == 0 && N2 % TR == 0, "tile");
 };
 
 // Opaque copy of a lane-varying value: the compiler must recompute what is
@@ -187,53 +205,65 @@ PQ_DEV double level_new(const SysView& v, int k, int a, int b)
     return aeff<Q>(v, slot_index_post<Q>(a, j, p1k, p2k), slot_index_post<Q>(b, j, p1k, p2k));
 }
 
-template <int Q, typename FT, bool STORE_W, bool FUSED>
-PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec,
-                                           int stride, LDS_PTR(FT) lF, LDS_PTR(FT) lY,
-                                           LDS_PTR(FT) lX, int ls, int kmax)
+template <int Q, int L, typename FT, bool STORE_W, bool FUSED>
+PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS_PTR(FT) lF,
+                          LDS_PTR(FT) lY, LDS_PTR(FT) lX, int ls, int kmax)
 {
     ls = launder(ls);
-    using G = Geo<Q>;
+    using G = Geo<Q, L>;
     constexpr int N2 = G::N2;
-    constexpr int EPL = G::EPL;
-    const int b = ls % N2;
-    const int jc = b & (Q - 1);
-    int a[EPL], jr[EPL];
+    constexpr int TR = G::TR;
+    constexpr int TC = G::TC;
+    const int ta = ls / G::CT, tb = ls % G::CT;
+    int a[TR], jr[TR], b[TC], jc[TC];
 #pragma unroll
-    for (int t = 0; t < EPL; t++) {
-        a[t] = (ls + 64 * t) / N2;
-        jr[t] = a[t] & (Q - 1);
+    for (int u = 0; u < TR; u++) {
+        a[u] = ta * TR + u;
+        jr[u] = a[u] & (Q - 1);
+    }
+#pragma unroll
+    for (int w = 0; w < TC; w++) {
+        b[w] = tb * TC + w;
+        jc[w] = b[w] & (Q - 1);
     }
 
     bool bad = false;
-    FT f[EPL], y[EPL];
+    FT f[TR][TC], y[TR];
     GLB_PTR(const double) rhs = v.rhs;
 
     // ---- initial frontier (and the odd-n centre level) ------------------
-    const int ib0 = slot_index_init<Q>(b, v);
+    int ib[TC];
+#pragma unroll
+    for (int w = 0; w < TC; w++) ib[w] = slot_index_init<Q>(b[w], v);
     if (v.odd) {
         const int m = v.npair;  // centre index (n = 2m+1)
         const double amm = live ? aeff<Q>(v, m, m) : 1.0;
         if (!(amm != 0.0 && isfinite(amm))) bad = true;
         const double ramm = 1.0 / amm;
         const double bm = (FUSED && live) ? beff(v, rhs, m) : 0.0;
-        const double amb = aeff<Q>(v, m, ib0);
+        double amb[TC];
 #pragma unroll
-        for (int t = 0; t < EPL; t++) {
-            const int ia = slot_index_init<Q>(a[t], v);
-            double aim = aeff<Q>(v, ia, m) * ramm;
-            f[t] = (FT)(aeff<Q>(v, ia, ib0) - aim * amb);
-            y[t] = FUSED ? (FT)(beff(v, rhs, ia) - aim * bm) : (FT)0;
-            if (STORE_W && live && b == 0) {
-                rec[4 * Q + 6 + 2 * a[t]] = (FT)aim;
-                rec[4 * Q + 6 + 2 * a[t] + 1] = (FT)0;
+        for (int w = 0; w < TC; w++) amb[w] = aeff<Q>(v, m, ib[w]);
+#pragma unroll
+        for (int u = 0; u < TR; u++) {
+            const int ia = slot_index_init<Q>(a[u], v);
+            const double aim = aeff<Q>(v, ia, m) * ramm;
+#pragma unroll
+            for (int w = 0; w < TC; w++) f[u][w] = (FT)(aeff<Q>(v, ia, ib[w]) - aim * amb[w]);
+            y[u] = FUSED ? (FT)(beff(v, rhs, ia) - aim * bm) : (FT)0;
+            if (STORE_W && live && tb == 0) {
+                rec[4 * Q + 6 + 2 * a[u]] = (FT)aim;
+                rec[4 * Q + 6 + 2 * a[u] + 1] = (FT)0;
             }
         }
         if (live) {
             // centre record: Z0 row m over the frontier slots, 1x1 pivot
-            if (ls < N2) {
-                rec[ls] = (FT)amb;
-                rec[N2 + ls] = (FT)0;
+            if (ta == 0) {
+#pragma unroll
+                for (int w = 0; w < TC; w++) {
+                    rec[b[w]] = (FT)amb[w];
+                    rec[N2 + b[w]] = (FT)0;
+                }
             }
             if (ls == 0) {
                 rec[4 * Q + 0] = (FT)ramm;
@@ -247,80 +277,99 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec,
         rec += stride;
     } else {
 #pragma unroll
-        for (int t = 0; t < EPL; t++) {
-            const int ia = slot_index_init<Q>(a[t], v);
-            f[t] = (FT)aeff<Q>(v, ia, ib0);
-            y[t] = FUSED ? (FT)beff(v, rhs, ia) : (FT)0;
+        for (int u = 0; u < TR; u++) {
+            const int ia = slot_index_init<Q>(a[u], v);
+#pragma unroll
+            for (int w = 0; w < TC; w++) f[u][w] = (FT)aeff<Q>(v, ia, ib[w]);
+            y[u] = FUSED ? (FT)beff(v, rhs, ia) : (FT)0;
         }
     }
 
-    // ---- prefetch for block 0 ------------------------------------------
-    FT nR[EPL], nC[EPL], nX;
-    {
+    // ---- prefetch: within each block of q levels element (a, b) is refilled
+    // at j = a mod q (row) and at j = b mod q (column); the values of a whole
+    // superblock of S blocks are loaded one superblock ahead -----------------
+    constexpr int S = G::S;
+    constexpr int SB = G::SB;
+    FT nR[S][TR][TC], nC[S][TR][TC];
+    constexpr int XPL = (6 * SB + G::LPS - 1) / G::LPS;  // extras per lane
+    FT nX[XPL];
+    auto load_super = [&](int kn) {
 #pragma unroll
-        for (int t = 0; t < EPL; t++) {
-            const int kr = jr[t] + 1, kc = jc + 1;
-            nR[t] = (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[t], b) : 0.0);
-            nC[t] = (FT)((live && kc <= v.npair && jc != jr[t]) ? level_new<Q>(v, kc, a[t], b)
-                                                                 : 0.0);
+        for (int sb = 0; sb < S; sb++)
+#pragma unroll
+            for (int u = 0; u < TR; u++)
+#pragma unroll
+                for (int w = 0; w < TC; w++) {
+                    const int kr = kn + sb * Q + jr[u] + 1, kc = kn + sb * Q + jc[w] + 1;
+                    nR[sb][u][w] =
+                        (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[u], b[w]) : 0.0);
+                    nC[sb][u][w] = (FT)((live && kc <= v.npair && jc[w] != jr[u])
+                                            ? level_new<Q>(v, kc, a[u], b[w])
+                                            : 0.0);
+                }
+#pragma unroll
+        for (int x = 0; x < XPL; x++) {
+            const int e = ls + x * G::LPS;
+            const int kx = kn + e / 6 + 1;
+            nX[x] = (FT)((live && e < 6 * SB && kx <= v.npair)
+                             ? level_extra<Q>(v, rhs, FUSED, kx, e % 6)
+                             : 0.0);
         }
-        const int kx = ls / 6 + 1;
-        nX = (FT)((live && ls < 6 * Q && kx <= v.npair)
-                      ? level_extra<Q>(v, rhs, FUSED, kx, ls % 6)
-                      : 0.0);
-    }
+    };
+    load_super(0);
 
-    // ---- level loop, unrolled by Q ----------------------------------------
-    for (int kb = 0; kb < kmax; kb += Q) {
-        // current block's prefetched values; issue loads for the next block
-        FT vR[EPL], vC[EPL];
+    // ---- level loop, unrolled by a superblock of S*q levels ---------------
+    for (int kb = 0; kb < kmax; kb += SB) {
+        FT vR[S][TR][TC], vC[S][TR][TC];
 #pragma unroll
-        for (int t = 0; t < EPL; t++) {
-            vR[t] = nR[t];
-            vC[t] = nC[t];
+        for (int sb = 0; sb < S; sb++)
+#pragma unroll
+            for (int u = 0; u < TR; u++)
+#pragma unroll
+                for (int w = 0; w < TC; w++) {
+                    vR[sb][u][w] = nR[sb][u][w];
+                    vC[sb][u][w] = nC[sb][u][w];
+                }
+#pragma unroll
+        for (int x = 0; x < XPL; x++) {
+            const int e = ls + x * G::LPS;
+            if (e < 6 * SB) lX[e] = nX[x];
         }
-        if (ls < 6 * Q) lX[ls] = nX;
-        {
-            const int kn = kb + Q;
+        load_super(kb + SB);
 #pragma unroll
-            for (int t = 0; t < EPL; t++) {
-                const int kr = kn + jr[t] + 1, kc = kn + jc + 1;
-                nR[t] = (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[t], b) : 0.0);
-                nC[t] = (FT)((live && kc <= v.npair && jc != jr[t])
-                                 ? level_new<Q>(v, kc, a[t], b)
-                                 : 0.0);
-            }
-            const int kx = kn + ls / 6 + 1;
-            nX = (FT)((live && ls < 6 * Q && kx <= v.npair)
-                          ? level_extra<Q>(v, rhs, FUSED, kx, ls % 6)
-                          : 0.0);
-        }
-#pragma unroll
-        for (int j = 0; j < Q; j++) {
-            const int k = kb + j + 1;  // level number (1-based)
+        for (int jj = 0; jj < SB; jj++) {
+            const int j = jj % Q;        // pivot slot
+            const int sb = jj / Q;       // block within the superblock
+            const int k = kb + jj + 1;  // level number (1-based)
             if (k > kmax) break;
             const bool act = live && (k <= v.npair);
 
-            // publish frontier and rhs column
+            // publish the tile and the rhs column
 #pragma unroll
-            for (int t = 0; t < EPL; t++) lF[a[t] * N2 + b] = f[t];
-            if (b == 0) {
+            for (int u = 0; u < TR; u++)
 #pragma unroll
-                for (int t = 0; t < EPL; t++) lY[a[t]] = y[t];
+                for (int w = 0; w < TC; w++) lF[a[u] * N2 + b[w]] = f[u][w];
+            if (tb == 0) {
+#pragma unroll
+                for (int u = 0; u < TR; u++) lY[a[u]] = y[u];
             }
             wave_sync();
             const FT P11 = lF[j * N2 + j], P12 = lF[j * N2 + Q + j];
             const FT P21 = lF[(Q + j) * N2 + j], P22 = lF[(Q + j) * N2 + Q + j];
             const FT y1 = lY[j], y2 = lY[Q + j];
-            const FT c1 = lF[j * N2 + b], c2 = lF[(Q + j) * N2 + b];
-            FT r1[EPL], r2[EPL];
+            FT c1[TC], c2[TC], r1[TR], r2[TR];
 #pragma unroll
-            for (int t = 0; t < EPL; t++) {
-                r1[t] = lF[a[t] * N2 + j];
-                r2[t] = lF[a[t] * N2 + Q + j];
+            for (int w = 0; w < TC; w++) {
+                c1[w] = lF[j * N2 + b[w]];
+                c2[w] = lF[(Q + j) * N2 + b[w]];
             }
-            const FT E0 = lX[6 * j + 0], E1 = lX[6 * j + 1], E2 = lX[6 * j + 2];
-            const FT E3 = lX[6 * j + 3], E4 = lX[6 * j + 4], E5 = lX[6 * j + 5];
+#pragma unroll
+            for (int u = 0; u < TR; u++) {
+                r1[u] = lF[a[u] * N2 + j];
+                r2[u] = lF[a[u] * N2 + Q + j];
+            }
+            const FT E0 = lX[6 * jj + 0], E1 = lX[6 * jj + 1], E2 = lX[6 * jj + 2];
+            const FT E3 = lX[6 * jj + 3], E4 = lX[6 * jj + 4], E5 = lX[6 * jj + 5];
             wave_sync();
 
             const FT det = P11 * P22 - P12 * P21;
@@ -331,11 +380,16 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec,
             // record: Z0 rows p1, p2 over the slots after this level
             if (act) {
 #pragma unroll
-                for (int t = 0; t < EPL; t++) {
-                    if (a[t] == j) rec[b] = (b == j) ? E0 : ((b == Q + j) ? (FT)0 : f[t]);
-                    if (a[t] == Q + j)
-                        rec[N2 + b] = (b == j) ? (FT)0 : ((b == Q + j) ? E2 : f[t]);
-                }
+                for (int u = 0; u < TR; u++)
+#pragma unroll
+                    for (int w = 0; w < TC; w++) {
+                        if (a[u] == j)
+                            rec[b[w]] =
+                                (b[w] == j) ? E0 : ((b[w] == Q + j) ? (FT)0 : f[u][w]);
+                        if (a[u] == Q + j)
+                            rec[N2 + b[w]] =
+                                (b[w] == j) ? (FT)0 : ((b[w] == Q + j) ? E2 : f[u][w]);
+                    }
                 if (ls == 0) {
                     rec[4 * Q + 0] = i11;
                     rec[4 * Q + 1] = i12;
@@ -346,31 +400,39 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec,
                 }
             }
 
-            // pivot-row values at this lane's column (after the shift)
-            const FT cA = (b == j) ? E0 : ((b == Q + j) ? (FT)0 : c1);
-            const FT cB = (b == j) ? (FT)0 : ((b == Q + j) ? E2 : c2);
+            // pivot-row values at this lane's columns (after the shift)
+            FT cA[TC], cB[TC];
 #pragma unroll
-            for (int t = 0; t < EPL; t++) {
+            for (int w = 0; w < TC; w++) {
+                cA[w] = (b[w] == j) ? E0 : ((b[w] == Q + j) ? (FT)0 : c1[w]);
+                cB[w] = (b[w] == j) ? (FT)0 : ((b[w] == Q + j) ? E2 : c2[w]);
+            }
+#pragma unroll
+            for (int u = 0; u < TR; u++) {
                 FT w1, w2;
-                if (a[t] == j) {
+                if (a[u] == j) {
                     w1 = E1 * i11;
                     w2 = E1 * i12;
-                } else if (a[t] == Q + j) {
+                } else if (a[u] == Q + j) {
                     w1 = E3 * i21;
                     w2 = E3 * i22;
                 } else {
-                    w1 = r1[t] * i11 + r2[t] * i21;
-                    w2 = r1[t] * i12 + r2[t] * i22;
+                    w1 = r1[u] * i11 + r2[u] * i21;
+                    w2 = r1[u] * i12 + r2[u] * i22;
                 }
-                const FT base = (jr[t] == j) ? vR[t] : ((jc == j) ? vC[t] : f[t]);
-                f[t] = base - (w1 * cA + w2 * cB);
+#pragma unroll
+                for (int w = 0; w < TC; w++) {
+                    const FT base = (jr[u] == j) ? vR[sb][u][w]
+                                                 : ((jc[w] == j) ? vC[sb][u][w] : f[u][w]);
+                    f[u][w] = base - (w1 * cA[w] + w2 * cB[w]);
+                }
                 if (FUSED) {
-                    const FT yb = (a[t] == j) ? E4 : ((a[t] == Q + j) ? E5 : y[t]);
-                    y[t] = yb - (w1 * y1 + w2 * y2);
+                    const FT yb = (a[u] == j) ? E4 : ((a[u] == Q + j) ? E5 : y[u]);
+                    y[u] = yb - (w1 * y1 + w2 * y2);
                 }
-                if (STORE_W && act && b == 0) {
-                    rec[4 * Q + 6 + 2 * a[t]] = w1;
-                    rec[4 * Q + 6 + 2 * a[t] + 1] = w2;
+                if (STORE_W && act && tb == 0) {
+                    rec[4 * Q + 6 + 2 * a[u]] = w1;
+                    rec[4 * Q + 6 + 2 * a[u] + 1] = w2;
                 }
             }
             rec += stride;
@@ -438,23 +500,24 @@ PQ_DEV void wsolve_system(SysView v, bool live, GLB_PTR(const double) rhs,
 // block (going inwards) into registers while the current one is solved from
 // LDS.  If ADD, x += solution instead of x = solution.
 // --------------------------------------------------------------------------
-template <int Q, typename FT, bool ADD>
+template <int Q, int L, typename FT, bool ADD>
 PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
                                          int stride, GLB_PTR(double) x, LDS_PTR(FT) lB, int ls,
                                          int kmax)
 {
     ls = launder(ls);
-    using G = Geo<Q>;
+    using G = Geo<Q, L>;
     constexpr int N2 = 2 * Q;
     constexpr int LPS = G::LPS;
+    constexpr int SB = G::SB;
     const bool mine = ls < N2;
     const int c = mine ? ls : 0;
-    const int blk = Q * stride;                  // elements per block of records
+    const int blk = SB * stride;                 // elements per superblock of records
     const int per_lane = (blk + LPS - 1) / LPS;  // <= MAXPL
-    constexpr int MAXPL = (Q * (8 * Q + 6) + LPS - 1) / LPS;
+    constexpr int MAXPL = (SB * (8 * Q + 6) + LPS - 1) / LPS;
     double xs = 0.0;
     GLB_PTR(const FT) recp = rec0 + (v.odd ? stride : 0);  // first 2x2 level record
-    const int kb_last = kmax > 0 ? ((kmax - 1) / Q) * Q : -Q;
+    const int kb_last = kmax > 0 ? ((kmax - 1) / SB) * SB : -SB;
     const int64_t lim = live ? (int64_t)v.npair * stride : 0;  // valid elements from recp
 
     FT nb[MAXPL];
@@ -467,16 +530,17 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
         }
     };
     load_block(kb_last);
-    for (int kb = kb_last; kb >= 0; kb -= Q) {
+    for (int kb = kb_last; kb >= 0; kb -= SB) {
 #pragma unroll
         for (int r = 0; r < MAXPL; r++) {
             const int e = ls + LPS * r;
             if (r < per_lane && e < blk) lB[e] = nb[r];
         }
         wave_sync();
-        load_block(kb - Q);
+        load_block(kb - SB);
 #pragma unroll
-        for (int jj = Q - 1; jj >= 0; jj--) {
+        for (int jj = SB - 1; jj >= 0; jj--) {
+            const int j = jj % Q;
             const int k = kb + jj + 1;
             if (k > kmax) continue;
             const bool act = live && (k <= v.npair);
@@ -491,8 +555,8 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
             const double x1 = i11 * r1 + i12 * r2;
             const double x2 = i21 * r1 + i22 * r2;
             if (act) {
-                if (c == jj && mine) xs = x1;
-                if (c == Q + jj && mine) xs = x2;
+                if (c == j && mine) xs = x1;
+                if (c == Q + j && mine) xs = x2;
                 const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
                 if (ls == 0) {
                     if (ADD) {
@@ -525,12 +589,12 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
 // Kernels
 // --------------------------------------------------------------------------
 
-template <int Q, typename FT>
+template <int Q, int L, typename FT>
 struct LdsBlock {
-    FT F[Geo<Q>::SPW][Geo<Q>::E];
-    FT Y[Geo<Q>::SPW][Geo<Q>::N2];
-    FT X[Geo<Q>::SPW][6 * Q];
-    FT B[Geo<Q>::SPW][Q * (8 * Q + 6)];
+    FT F[Geo<Q, L>::SPW][Geo<Q, L>::E];
+    FT Y[Geo<Q, L>::SPW][Geo<Q, L>::N2];
+    FT X[Geo<Q, L>::SPW][6 * Geo<Q, L>::SB];
+    FT B[Geo<Q, L>::SPW][Geo<Q, L>::SB * (8 * Q + 6)];
 };
 
 template <typename T>
@@ -541,12 +605,12 @@ PQ_DEV LDS_PTR(T) as_lds(T* p)
 
 // Residual pass over one system: w = A u - b with the original band.
 // Returns (in *changes) the number of active-set changes for LCP_EXACT.
-template <int Q>
+template <int Q, int L>
 PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off, int ls,
                             bool update, bool write_w, int& changes, int& nonfinite)
 {
     ls = launder(ls);
-    using G = Geo<Q>;
+    using G = Geo<Q, L>;
     constexpr int BW = G::BW;
     GLB_PTR(const double) u = GLB(const double, A.u + off);
     GLB_PTR(const double) bb = GLB(const double, A.b + off);
@@ -582,13 +646,13 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
 
 // Effective residual r = b_eff - A_eff u on one system (for refinement);
 // returns the group max |r| and max |b_eff|.
-template <int Q>
+template <int Q, int L>
 PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
                                           GLB_PTR(const double) u, GLB_PTR(double) r, int ls,
                                           double& rmax, double& bmax)
 {
     ls = launder(ls);
-    using G = Geo<Q>;
+    using G = Geo<Q, L>;
     double rm = 0.0, bm = 0.0;
     if (live) {
         for (int i = ls; i < v.n; i += G::LPS) {
@@ -612,11 +676,12 @@ PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
 }
 
 // Whole LCP solve, one wave per SPW systems.
-template <int Q, typename FT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) paqif_lcp_kernel(LcpArgs A)
+template <int Q, int L, typename FT>
+__global__ void __launch_bounds__(64)
+    __attribute__((amdgpu_waves_per_eu(Geo<Q, L>::WPE, 8))) paqif_lcp_kernel(LcpArgs A)
 {
-    using G = Geo<Q>;
-    __shared__ LdsBlock<Q, FT> lds;
+    using G = Geo<Q, L>;
+    __shared__ LdsBlock<Q, L, FT> lds;
     const int lane = threadIdx.x;
     const int grp = lane / G::LPS;
     const int ls = lane % G::LPS;
@@ -656,14 +721,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
         // ---- factor (+ forward) and back solve ----------------------------
         bool bad;
         if constexpr (!MIXED) {
-            bad = factor_system<Q, FT, false, true>(v, live && !done, rec, stride,
+            bad = factor_system<Q, L, FT, false, true>(v, live && !done, rec, stride,
                                                     as_lds(lds.F[grp]), as_lds(lds.Y[grp]),
                                                     as_lds(lds.X[grp]), ls, kmax);
             __syncthreads();
-            back_system<Q, FT, false>(v, live && !done, rec, stride, GLB(double, A.u + off),
+            back_system<Q, L, FT, false>(v, live && !done, rec, stride, GLB(double, A.u + off),
                                       as_lds(lds.B[grp]), ls, kmax);
         } else {
-            bad = factor_system<Q, FT, true, false>(v, live && !done, rec, stride,
+            bad = factor_system<Q, L, FT, true, false>(v, live && !done, rec, stride,
                                                     as_lds(lds.F[grp]), as_lds(lds.Y[grp]),
                                                     as_lds(lds.X[grp]), ls, kmax);
             __syncthreads();
@@ -675,7 +740,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
             int steps = 0;
             bool conv = false;
             for (;;) {
-                eff_residual<Q>(v, live && !done, GLB(const double, A.b + off),
+                eff_residual<Q, L>(v, live && !done, GLB(const double, A.b + off),
                                 GLB(const double, A.u + off), GLB(double, A.r + off), ls, rmax,
                                 bmax);
                 const double tol = A.refine_tol * fmax(bmax, 1.0);
@@ -688,7 +753,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
                                      rec, stride, ls,
                                      kmax, gbase);
                 __syncthreads();
-                back_system<Q, FT, true>(v, live && !done && !ok_here, rec, stride,
+                back_system<Q, L, FT, true>(v, live && !done && !ok_here, rec, stride,
                                          GLB(double, A.u + off),
                                          as_lds(lds.B[grp]), ls, kmax);
                 __syncthreads();
@@ -717,7 +782,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
             }
         }
         __syncthreads();
-        residual_update<Q>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
+        residual_update<Q, L>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
         __syncthreads();
         if (live && !done) {
             if (nonfinite) {
@@ -748,10 +813,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // Factor only (records with W0), no right-hand side.
 
 template <int Q>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) paqif_factor_kernel(FactorArgs A)
+__global__ void __launch_bounds__(64)
+    __attribute__((amdgpu_waves_per_eu(Geo<Q, 0>::WPE, 8))) paqif_factor_kernel(FactorArgs A)
 {
-    using G = Geo<Q>;
-    __shared__ LdsBlock<Q, double> lds;
+    constexpr int L = 0;
+    using G = Geo<Q, L>;
+    __shared__ LdsBlock<Q, L, double> lds;
     const int lane = threadIdx.x;
     const int grp = lane / G::LPS;
     const int ls = lane % G::LPS;
@@ -774,7 +841,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     constexpr int stride = G::ZREC + G::WREC;
     GLB_PTR(double) rec =
         GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride);
-    bool bad = factor_system<Q, double, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
+    bool bad = factor_system<Q, L, double, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
                                                      as_lds(lds.Y[grp]), as_lds(lds.X[grp]), ls,
                                                      kmax);
     const int badg = group_max_int<G::LPS>(bad ? 1 : 0);
@@ -785,8 +852,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 template <int Q>
 __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
 {
-    using G = Geo<Q>;
-    __shared__ LdsBlock<Q, double> lds;
+    constexpr int L = 0;
+    using G = Geo<Q, L>;
+    __shared__ LdsBlock<Q, L, double> lds;
     const int lane = threadIdx.x;
     const int grp = lane / G::LPS;
     const int ls = lane % G::LPS;
@@ -813,29 +881,41 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
     wsolve_system<Q, double>(v, live, GLB(const double, A.rhs + off), rec, stride, ls, kmax,
                              gbase);
     __syncthreads();
-    back_system<Q, double, false>(v, live, rec, stride, GLB(double, A.x + off),
+    back_system<Q, L, double, false>(v, live, rec, stride, GLB(double, A.x + off),
                                   as_lds(lds.B[grp]), ls, kmax);
 }
 
 // --------------------------------------------------------------------------
 // Host launchers
 // --------------------------------------------------------------------------
-template <int Q>
-static int launch_lcp(const LcpArgs& a, int prec, hipStream_t s)
+template <int Q, int L>
+static int launch_lcp_l(const LcpArgs& a, int prec, hipStream_t s)
 {
-    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    const int grid = (a.count + Geo<Q, L>::SPW - 1) / Geo<Q, L>::SPW;
     if (grid == 0) return PAQIF_OK;
     if (prec == PREC_FP32_IR)
-        hipLaunchKernelGGL((paqif_lcp_kernel<Q, float>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((paqif_lcp_kernel<Q, L, float>), dim3(grid), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((paqif_lcp_kernel<Q, double>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((paqif_lcp_kernel<Q, L, double>), dim3(grid), dim3(64), 0, s, a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+template <int Q>
+static int launch_lcp(const LcpArgs& a, int prec, int layout, hipStream_t s)
+{
+    switch (layout) {
+    case 1: return launch_lcp_l<Q, 1>(a, prec, s);
+    case 2:
+        if constexpr (layout_count(Q) > 2) return launch_lcp_l<Q, 2>(a, prec, s);
+        return PAQIF_EINVAL;
+    default: return launch_lcp_l<Q, 0>(a, prec, s);
+    }
 }
 
 template <int Q>
 static int launch_factor(const FactorArgs& a, hipStream_t s)
 {
-    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    const int grid = (a.count + Geo<Q, 0>::SPW - 1) / Geo<Q, 0>::SPW;
     if (grid == 0) return PAQIF_OK;
     hipLaunchKernelGGL((paqif_factor_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
@@ -844,7 +924,7 @@ static int launch_factor(const FactorArgs& a, hipStream_t s)
 template <int Q>
 static int launch_solve(const SolveArgs& a, hipStream_t s)
 {
-    const int grid = (a.count + Geo<Q>::SPW - 1) / Geo<Q>::SPW;
+    const int grid = (a.count + Geo<Q, 0>::SPW - 1) / Geo<Q, 0>::SPW;
     if (grid == 0) return PAQIF_OK;
     hipLaunchKernelGGL((paqif_solve_factored_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
@@ -852,12 +932,14 @@ static int launch_solve(const SolveArgs& a, hipStream_t s)
 
 int record_stride(int q, bool with_w) { return (4 * q + 6) + (with_w ? 4 * q : 0); }
 
-int dispatch_lcp(int q, const LcpArgs& a, int prec, hipStream_t s)
+int layouts_for(int q) { return (q == 2 || q == 4 || q == 8) ? layout_count(q) : 0; }
+
+int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s)
 {
     switch (q) {
-    case 2: return launch_lcp<2>(a, prec, s);
-    case 4: return launch_lcp<4>(a, prec, s);
-    case 8: return launch_lcp<8>(a, prec, s);
+    case 2: return launch_lcp<2>(a, prec, layout, s);
+    case 4: return launch_lcp<4>(a, prec, layout, s);
+    case 8: return launch_lcp<8>(a, prec, layout, s);
     default: return PAQIF_EINVAL;
     }
 }

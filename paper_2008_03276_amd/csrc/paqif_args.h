@@ -4,13 +4,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Library handle (device properties).
+// Library handle: device properties and the tuned lane layout of the
+// PAQIF kernel per half-bandwidth (q = 2, 4, 8) and precision (FP64, FP32+IR).
 struct paqif_handle_s {
     int device;
     int cu_count;
+    int layout[3][2];
 };
 
+
+
 namespace pq {
+
+inline int q_index(int q) { return q == 2 ? 0 : (q == 4 ? 1 : 2); }
 
 struct LcpArgs {
     int32_t count;
@@ -53,7 +59,8 @@ struct SolveArgs {
     double* x;
 };
 
-int dispatch_lcp(int q, const LcpArgs& a, int prec, hipStream_t s);
+int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s);
+int layouts_for(int q);
 int dispatch_factor(int q, const FactorArgs& a, hipStream_t s);
 int dispatch_solve(int q, const SolveArgs& a, hipStream_t s);
 int record_stride(int q, bool with_w);

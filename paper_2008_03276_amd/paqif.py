@@ -115,3 +115,33 @@ def solve_factored(batch, factors, rhs, pinned=None):
                                         _ptr(pinned), _ptr(rhs), _ptr(x), _stream())
     B.check(code, "paqif_solve_factored")
     return x
+
+
+def layout_count(q):
+    return B.lib().paqif_layout_count(int(q))
+
+
+def set_layout(q, prec, layout):
+    B.check(B.lib().paqif_set_layout(handle(), int(q), int(prec), int(layout)), "paqif_set_layout")
+
+
+def get_layout(q, prec=B.PREC_FP64):
+    return B.lib().paqif_get_layout(handle(), int(q), int(prec))
+
+
+def autotune(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None, max_iter=64,
+             workspace=None):
+    """Time every lane layout of the LCP kernel on this batch; the fastest is
+    kept in the handle for (q, prec).  Returns (chosen, times_ms)."""
+    _need(band, torch.float64, "band")
+    _need(b, torch.float64, "b")
+    nl = layout_count(batch.q)
+    times = (ctypes.c_float * nl)()
+    u = torch.empty(batch.total_rows, dtype=torch.float64, device=band.device)
+    st = torch.empty(batch.count, dtype=torch.int32, device=band.device)
+    if workspace is None:
+        workspace = batch.workspace(prec, mode)
+    B.check(B.lib().paqif_autotune(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
+                                   _ptr(bounded), mode, prec, max_iter, _ptr(u), _ptr(st),
+                                   _ptr(workspace), _stream(), times), "paqif_autotune")
+    return get_layout(batch.q, prec), [float(t) for t in times]

@@ -150,3 +150,41 @@ def test_full_size_sampled(gpu, q):
         assert o["status"] == 0
         assert (o["active"] == act[a:b]).all()
         assert _relerr(u[a:b], o["u"]) < 1e-12
+
+
+@pytest.mark.parametrize("q", [2, 4, 8])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_lane_layout(gpu, q, prec):
+    """Each lane layout of the LCP kernel (selected by the autotuner at run
+    time) gives the oracle's solution."""
+    P = gpu
+    sizes = [1, 2, 5, 8, 17, 64, 129, 300, 513, 1000]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=21, sizes=sizes)
+    o = oracle.lcp_batch(q, offs, band, f, mode=2)
+    bt = P.paqif.Batch(offs, q, order="lpt")
+    dev = torch.device("cuda")
+    band_d, f_d = torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev)
+    keep = P.paqif.get_layout(q, prec)
+    try:
+        for lay in range(P.paqif.layout_count(q)):
+            P.paqif.set_layout(q, prec, lay)
+            r = P.paqif.solve_lcp(bt, band_d, f_d, mode=2, prec=prec)
+            torch.cuda.synchronize()
+            assert (r["status"].cpu().numpy() == 0).all(), lay
+            assert (r["active"].cpu().numpy() == o["active"]).all(), lay
+            tol = 1e-12 if prec == 0 else 1e-9
+            assert _relerr(r["u"].cpu().numpy(), o["u"]) < tol, lay
+    finally:
+        P.paqif.set_layout(q, prec, keep)
+
+
+def test_autotune_picks_a_layout(gpu):
+    P = gpu
+    offs, band, f = synth.lcp_batch(64, 4, seed=5)
+    bt = P.paqif.Batch(offs, 4, order="lpt")
+    dev = torch.device("cuda")
+    chosen, times = P.paqif.autotune(bt, torch.as_tensor(band, device=dev),
+                                     torch.as_tensor(f, device=dev))
+    assert 0 <= chosen < P.paqif.layout_count(4)
+    assert len(times) == P.paqif.layout_count(4) and min(times) > 0
+    assert times[chosen] == min(times)
