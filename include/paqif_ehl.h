@@ -53,7 +53,8 @@ enum {
     SYS_LCP_NOT_CONVERGED = 3,   /* active-set iteration hit max_iter */
     SYS_REFINE_STALLED = 4,      /* iterative refinement did not reach the tolerance */
     SYS_NEGATIVE_FILM = 5,       /* EHL: film thickness H <= 0 somewhere */
-    SYS_NEWTON_NOT_CONVERGED = 6 /* EHL: Newton iteration hit max_newton */
+    SYS_NEWTON_NOT_CONVERGED = 6, /* EHL: Newton iteration hit max_newton */
+    SYS_ADJOINT_NOT_CONVERGED = 7 /* EHL adjoint: the transposed solve missed its tolerance */
 };
 
 /* arithmetic of the band factorisation */
@@ -270,6 +271,43 @@ size_t ehl_newton_workspace_bytes(paqif_handle handle, const ehl_grid *grid, int
 int ehl_newton_tvd(paqif_handle handle, const ehl_grid *grid, const ehl_params *params, int B,
                    const ehl_opts *opts, const double *rough, double *P, double *H0, double *H,
                    double *Hmin, int32_t *status, int32_t *iters, void *workspace, void *stream);
+
+
+/*
+ * ehl_adjoint_solve -- line contact: gradients of a scalar output of the
+ * converged solution (P, H0) with respect to M, L and the roughness profile.
+ * The paper has no adjoint; this is the exact derivative of its discrete
+ * equations at the fixed point of Sec. 3.3 (Reynolds residual with the TVD
+ * flux of eqs. 62-65 on the pressurised nodes, load balance of eq. 75), with
+ * the cavitated set, the limiter branches and the film's arg-min held fixed.
+ * The caller supplies the cotangents of the output,
+ *    gP (d out / d P), gH0 (d out / d H0), gH (d out / d H, H the film),
+ * e.g. gH0 = 1 for out = H0, or gH = e_m at the arg-min m for out = Hmin.
+ * The transposed bordered Jacobian is solved for both right-hand sides of its
+ * Schur split by GMRES(40), right-preconditioned with a PAQIF solve of the
+ * transposed Newton band (cavitated rows pinned); the dense part K (dR/dH)^T
+ * v is the FP64 MFMA deformation product.
+ *  params: DEVICE ehl_params[B];  rough: DEVICE nx x B or NULL (as in the
+ *  forward solve);  P: DEVICE nx x B, H0: DEVICE [B] -- the converged state
+ *  (P > 0 marks the pressurised nodes).
+ *  gP, gH: DEVICE nx x B or NULL (zero);  gH0: DEVICE [B] or NULL.
+ *  rtol: relative residual target of the transposed solves (0 < rtol < 1);
+ *  max_iter: cap on Arnoldi steps per solve.
+ *  dM, dL: DEVICE [B];  drough: DEVICE nx x B (d out / d roughness_m).
+ *  status: DEVICE int32[B] (SYS_OK, SYS_ADJOINT_NOT_CONVERGED: the residual
+ *  stalled above max(1e-8, rtol), SYS_NONFINITE);  iters: DEVICE int32[B],
+ *  Arnoldi steps of the two solves together.
+ *  opts: switch_ratio and kernel_terms select the preconditioning band (use
+ *  the forward solve's options).
+ *  workspace: DEVICE, ehl_adjoint_workspace_bytes(handle, grid, B).  The
+ *  call synchronises the stream (convergence checks on the host).
+ */
+size_t ehl_adjoint_workspace_bytes(paqif_handle handle, const ehl_grid *grid, int B);
+int ehl_adjoint_solve(paqif_handle handle, const ehl_grid *grid, const ehl_params *params, int B,
+                      const ehl_opts *opts, const double *rough, const double *P,
+                      const double *H0, const double *gP, const double *gH0, const double *gH,
+                      double rtol, int max_iter, double *dM, double *dL, double *drough,
+                      int32_t *status, int32_t *iters, void *workspace, void *stream);
 
 #ifdef __cplusplus
 }

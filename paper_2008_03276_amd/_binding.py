@@ -16,6 +16,7 @@ _LIB = None
 PAQIF_OK, PAQIF_EINVAL, PAQIF_EWORKSPACE, PAQIF_EHIP = 0, -1, -2, -3
 SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE, SYS_LCP_NOT_CONVERGED = 0, 1, 2, 3
 SYS_REFINE_STALLED, SYS_NEGATIVE_FILM, SYS_NEWTON_NOT_CONVERGED = 4, 5, 6
+SYS_ADJOINT_NOT_CONVERGED = 7
 PREC_FP64, PREC_FP32_IR, PREC_SPLIT_BF16, PREC_FP32 = 0, 1, 2, 3
 LCP_LINEAR, LCP_CLIP, LCP_EXACT = 0, 1, 2
 
@@ -90,6 +91,11 @@ def lib():
                                         ctypes.POINTER(EhlOpts)], ctypes.c_size_t),
         "ehl_newton_tvd": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int, ctypes.POINTER(EhlOpts),
                             vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "ehl_adjoint_workspace_bytes": ([vp, ctypes.POINTER(EhlGrid), ctypes.c_int],
+                                        ctypes.c_size_t),
+        "ehl_adjoint_solve": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int,
+                               ctypes.POINTER(EhlOpts), vp, vp, vp, vp, vp, vp, d, ctypes.c_int,
+                               vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

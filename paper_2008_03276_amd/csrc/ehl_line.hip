@@ -15,32 +15,15 @@
 // entries of dR/dsigma through the chain rule on that window.
 #include "common.h"
 #include "ehl_internal.h"
+#include "ehl_model.h"
 
 namespace pq {
 
 namespace {
-constexpr double ALPHA = 1.7e-8;
-constexpr double P0R = 1.98e8;
-constexpr double ZR = 0.68;
-constexpr double RHO_A = 0.59e9;
-constexpr double RHO_B = 1.34;
 constexpr int TILE = 256;
 constexpr int HALO = 5;
 constexpr int WIN = TILE + 2 * HALO;
 }  // namespace
-
-struct LineConst {
-    double lam, ph;
-};
-
-PQ_DEV LineConst line_const(double M, double L)
-{
-    LineConst c;
-    const double abar = L * sqrt(M / (2.0 * M_PI));
-    c.lam = 3.0 * M_PI * M_PI / (8.0 * M * M);
-    c.ph = abar / ALPHA;
-    return c;
-}
 
 __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
 {
@@ -68,21 +51,13 @@ __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
             const double x = a.x0 + h * m;
             Pm = P[m];
             Hm = H0 + 0.5 * x * x + Hel[m] + (rough ? rough[m] : 0.0);
-            const double s = lc.ph / P0R;
-            const double base = 1.0 + s * Pm;
-            const double cc = ALPHA * P0R / ZR;
-            const double lneta = cc * (-1.0 + pow(base, ZR));
-            const double dlneta = cc * ZR * pow(base, ZR - 1.0) * s;
-            const double den = RHO_A + lc.ph * Pm;
-            rho = (RHO_A + RHO_B * lc.ph * Pm) / den;
-            const double drho =
-                (RHO_B * lc.ph * den - (RHO_A + RHO_B * lc.ph * Pm) * lc.ph) / (den * den);
-            const double lam_eta = exp(lneta) * lc.lam;
-            eps = rho * Hm * Hm * Hm / lam_eta;
-            rH = rho * Hm;
-            eP = drho * Hm * Hm * Hm / lam_eta - eps * dlneta;
-            eH = 3.0 * rho * Hm * Hm / lam_eta;
-            drhoH = drho * Hm;
+            const NodeState q = node_state(Pm, Hm, lc);
+            eps = q.eps;
+            rH = q.rH;
+            eP = q.eP;
+            eH = q.eH;
+            rho = q.rho;
+            drhoH = q.drhoH;
         }
         sP[w] = Pm;
         sH[w] = Hm;
@@ -163,15 +138,7 @@ __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
     };
     // limiter at node tt (1 <= tt <= N-2)
     auto limiter = [&](int tt, double& psi, double& pa, double& pb) {
-        const double dm = rHn(tt) - rHn(tt - 1), dp = rHn(tt + 1) - rHn(tt);
-        if (dm * dp > 0.0) {
-            const double den = dp + dm;
-            psi = 2.0 * dp * dm / den;
-            pa = 2.0 * dm * dm / (den * den);
-            pb = 2.0 * dp * dp / (den * den);
-        } else {
-            psi = pa = pb = 0.0;
-        }
+        van_leer(rHn(tt) - rHn(tt - 1), rHn(tt + 1) - rHn(tt), psi, pa, pb);
     };
     // residual
     const double eph = 0.5 * (epsn(i) + epsn(i + 1));

@@ -109,3 +109,72 @@ def solve_line(M, L, N, opts=None, rough=None, P=None, H0=None, device=None, str
     torch.cuda.current_stream(device).wait_stream(s)
     B.check(code, "ehl_newton_tvd")
     return dict(P=P, H0=H0, H=H, Hmin=Hmin, status=status, iters=iters)
+
+
+def adjoint(M, L, N, P, H0, gP=None, gH0=None, gH=None, rough=None, opts=None, rtol=1e-12,
+            max_iter=400):
+    """Gradients of a scalar output of converged line-contact solutions.
+
+    (P, H0): the converged state, (B, N) and (B,).  gP, gH: (B, N) cotangents
+    of the pressure and the film, gH0: (B,) of the offset (None = zero).
+    Returns dict(dM, dL, drough, status, iters) as device tensors."""
+    opts = opts or default_opts()
+    _need(P, torch.float64, "P")
+    _need(H0, torch.float64, "H0")
+    nb = P.shape[0]
+    dev = P.device
+    for t, name in ((gP, "gP"), (gH0, "gH0"), (gH, "gH"), (rough, "rough")):
+        if t is not None:
+            _need(t, torch.float64, name)
+    grid = line_grid(N)
+    params = params_tensor(M, L, dev)
+    dM = torch.empty(nb, dtype=torch.float64, device=dev)
+    dL = torch.empty(nb, dtype=torch.float64, device=dev)
+    drough = torch.empty(nb, N, dtype=torch.float64, device=dev)
+    status = torch.empty(nb, dtype=torch.int32, device=dev)
+    iters = torch.empty(nb, dtype=torch.int32, device=dev)
+    nbytes = B.lib().ehl_adjoint_workspace_bytes(handle(), ctypes.byref(grid), nb)
+    if nbytes == 0:
+        raise ValueError("invalid EHL grid")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    B.check(B.lib().ehl_adjoint_solve(handle(), ctypes.byref(grid), _ptr(params), nb,
+                                      ctypes.byref(opts), _ptr(rough), _ptr(P), _ptr(H0),
+                                      _ptr(gP), _ptr(gH0), _ptr(gH), float(rtol), int(max_iter),
+                                      _ptr(dM), _ptr(dL), _ptr(drough), _ptr(status),
+                                      _ptr(iters), _ptr(ws), _stream()), "ehl_adjoint_solve")
+    return dict(dM=dM, dL=dL, drough=drough, status=status, iters=iters)
+
+
+class LineEHL(torch.autograd.Function):
+    """Converged line-contact solve as a differentiable function.
+
+    ``P, H0, H, status = LineEHL.apply(M, L, rough, N, opts)`` with M, L of
+    shape (B,) and rough (B, N) or None; the backward pass is the hand-written
+    adjoint (ehl_adjoint_solve) and gives gradients for M, L and rough.  An
+    output such as Hmin = H.min(dim=1).values is differentiated by torch into
+    the film cotangent at the arg-min."""
+
+    @staticmethod
+    def forward(ctx, M, L, rough, N, opts=None):
+        ctx.set_materialize_grads(False)
+        dev = rough.device if rough is not None else torch.device("cuda",
+                                                                  torch.cuda.current_device())
+        Mv = M.detach().to(torch.float64).cpu()
+        Lv = L.detach().to(torch.float64).cpu()
+        rg = None if rough is None else rough.detach().to(torch.float64).contiguous()
+        r = solve_line(Mv, Lv, N, opts=opts, rough=rg, device=dev)
+        ctx.save_for_backward(r["P"], r["H0"])
+        ctx.args = (Mv, Lv, rg, N, opts, M.device, L.device)
+        ctx.mark_non_differentiable(r["status"])
+        return r["P"], r["H0"], r["H"], r["status"]
+
+    @staticmethod
+    def backward(ctx, gP, gH0, gH, gstatus):
+        P, H0 = ctx.saved_tensors
+        Mv, Lv, rg, N, opts, mdev, ldev = ctx.args
+        c = lambda t: None if t is None else t.to(torch.float64).contiguous()
+        a = adjoint(Mv, Lv, N, P, H0, gP=c(gP), gH0=c(gH0), gH=c(gH), rough=rg, opts=opts)
+        if (a["status"] != B.SYS_OK).any():
+            raise RuntimeError(f"ehl_adjoint_solve: instance status {a['status'].tolist()}")
+        drough = a["drough"] if rg is not None else None
+        return a["dM"].to(mdev), a["dL"].to(ldev), drough, None, None
