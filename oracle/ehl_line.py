@@ -32,7 +32,9 @@ limiter equals psi above.  The flow is in +X.
 
 Iteration (the paper's hybrid Newton line method Lhs1, eqs. 60, 62-68, 75):
   * band Jacobian J = dR/dP of the local terms, with the elastic kernel
-    coupling dH_k/dP_j kept only for |k - j| <= 1 (eq. 67);
+    coupling dH_k/dP_j kept only for |k - j| <= kterms (eq. 67 keeps three
+    terms, kterms = 1; the default here keeps five, kterms = 2, without which
+    the iteration diverges from the Hertzian start on grids of 2049 nodes);
   * hybrid switch (eq. 60): node i takes a direct change (Ls1) when
     eps_i / h > 0.6, else a weighted (distributive) change (Ls4): the change
     vector is delta = D sigma where column i of D is e_i for a direct node
@@ -135,7 +137,7 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1):
     e_{j+1})/2 for a distributive one; boundary nodes stay fixed).
 
     The film reacts to sigma_j through the distributed kernel (K D); as in
-    eqs. 66-67 and 74 it is kept for the three nodes m = j-1, j, j+1 only.
+    eqs. 66-67 and 74 it is kept for the nodes |m - j| <= kterms only.
     With every node direct this is dR/dP with the kernel cut to |k-j| <= 1.
     Returns J with J[r, s+4] = dR_{r+1}/dsigma_{r+1+s}, s = -4..4 (nonzero
     offsets -3..2)."""
@@ -275,7 +277,7 @@ def hybrid_direct(P, eps, h):
     return direct | near
 
 
-def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=1):
+def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2):
     """One Lhs1 step; returns (P_new, H0_new, info)."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
@@ -324,7 +326,7 @@ def lcp_exact(A, b, bounded):
     return r["u"], r["status"]
 
 
-def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=1, max_newton=2000, tol=1e-13,
+def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
                rough=None, P=None, H0=None):
     """Run the hybrid Newton line iteration to convergence.
 

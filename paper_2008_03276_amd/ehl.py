@@ -23,7 +23,7 @@ def point_grid(Nx, Ny, x0=XA, x1=XB, y0=-3.0, y1=3.0):
 
 
 def default_opts(**kw):
-    o = dict(omega=0.5, c_h0=0.1, switch_ratio=0.6, tol=1e-13, max_newton=4000, kernel_terms=1,
+    o = dict(omega=0.5, c_h0=0.1, switch_ratio=0.6, tol=1e-13, max_newton=4000, kernel_terms=2,
              lcp_max_iter=64, deform_prec=B.PREC_FP64, lcp_prec=B.PREC_FP64, steps_per_graph=16,
              start_rule=1)
     o.update(kw)
@@ -105,6 +105,66 @@ def solve_line(M, L, N, opts=None, rough=None, P=None, H0=None, device=None, str
         code = B.lib().ehl_newton_tvd(handle(), ctypes.byref(grid), _ptr(params), nb,
                                       ctypes.byref(opts), _ptr(rough), _ptr(P), _ptr(H0),
                                       _ptr(H), _ptr(Hmin), _ptr(status), _ptr(iters), _ptr(ws),
+                                      ctypes.c_void_p(s.cuda_stream))
+    torch.cuda.current_stream(device).wait_stream(s)
+    B.check(code, "ehl_newton_tvd")
+    return dict(P=P, H0=H0, H=H, Hmin=Hmin, status=status, iters=iters)
+
+
+def point_sweep_assemble(grid, params, P, Hel, H0, axis, color, opts=None):
+    """Band systems of one colour of one sweep direction of the point
+    contact (P, Hel: (B, Nx, Ny)).  Returns dict(band (B*lines, n, 9), rhs,
+    bounded, direct (B, Nx, Ny))."""
+    opts = opts or default_opts()
+    for t, name in ((P, "P"), (Hel, "Hel"), (H0, "H0"), (params, "params")):
+        _need(t, torch.float64, name)
+    nb, Nx, Ny = P.shape
+    nl, n = (Ny, Nx - 2) if axis == 0 else (Nx, Ny - 2)
+    first = 1 if color == 1 else 2
+    nlc = (nl - 2 - first) // 2 + 1 if first <= nl - 2 else 0
+    dev = P.device
+    band = torch.empty(nb * nlc, n, 9, dtype=torch.float64, device=dev)
+    rhs = torch.empty(nb * nlc, n, dtype=torch.float64, device=dev)
+    bounded = torch.empty(nb * nlc, n, dtype=torch.uint8, device=dev)
+    direct = torch.empty(nb, Nx, Ny, dtype=torch.uint8, device=dev)
+    ws = torch.empty(B.lib().ehl_point_assemble_workspace_bytes(ctypes.byref(grid), nb),
+                     dtype=torch.uint8, device=dev)
+    B.check(B.lib().ehl_point_sweep_assemble(handle(), ctypes.byref(grid), _ptr(params), nb,
+                                             ctypes.byref(opts), int(axis), int(color), _ptr(P),
+                                             _ptr(Hel), _ptr(H0), _ptr(band), _ptr(rhs),
+                                             _ptr(bounded), _ptr(direct), _ptr(ws), _stream()),
+            "ehl_point_sweep_assemble")
+    return dict(band=band, rhs=rhs, bounded=bounded, direct=direct)
+
+
+def solve_point(M, L, Nx, Ny, opts=None, P=None, H0=None, device=None, stream=None):
+    """Alternating x/y line sweeps for B = len(M) point contacts on one grid
+    (ehl_newton_tvd on a 2D grid).  Returns dict(P (B, Nx, Ny), H0, H, Hmin,
+    status, iters)."""
+    opts = opts or default_opts()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    grid = point_grid(Nx, Ny)
+    params = params_tensor(M, L, device)
+    nb = params.shape[0]
+    P = torch.zeros(nb, Nx, Ny, dtype=torch.float64, device=device) if P is None else \
+        P.clone().contiguous()
+    H0 = torch.zeros(nb, dtype=torch.float64, device=device) if H0 is None else \
+        torch.as_tensor(H0, dtype=torch.float64, device=device).clone()
+    H = torch.empty(nb, Nx, Ny, dtype=torch.float64, device=device)
+    Hmin = torch.empty(nb, dtype=torch.float64, device=device)
+    status = torch.empty(nb, dtype=torch.int32, device=device)
+    iters = torch.empty(nb, dtype=torch.int32, device=device)
+    nbytes = B.lib().ehl_newton_workspace_bytes(handle(), ctypes.byref(grid), nb,
+                                                ctypes.byref(opts))
+    if nbytes == 0:
+        raise ValueError("invalid EHL grid/options")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = stream or torch.cuda.Stream(device=device)
+    s.wait_stream(torch.cuda.current_stream(device))
+    with torch.cuda.stream(s):
+        code = B.lib().ehl_newton_tvd(handle(), ctypes.byref(grid), _ptr(params), nb,
+                                      ctypes.byref(opts), None, _ptr(P), _ptr(H0), _ptr(H),
+                                      _ptr(Hmin), _ptr(status), _ptr(iters), _ptr(ws),
                                       ctypes.c_void_p(s.cuda_stream))
     torch.cuda.current_stream(device).wait_stream(s)
     B.check(code, "ehl_newton_tvd")
