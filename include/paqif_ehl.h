@@ -253,6 +253,29 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid *grid, const ehl_p
                           double *rhs, uint8_t *bounded, uint8_t *direct, void *stream);
 
 /*
+ * ehl_point_sweep_assemble -- point contact: the band systems of one colour
+ * of one sweep direction of the alternating line method (Sec. 3.3, eqs. 60,
+ * 62-65, 66-67, 69-70, 74): for every line of the colour (axis 0: x-lines,
+ * one per interior y index j with j % 2 == color; axis 1: y-lines, one per
+ * interior x index i), rows = interior positions along the line, band =
+ * -dR/dsigma (half-bandwidth 4, layout of paqif_solve_lcp, system = b *
+ * lines + line slot, slots in increasing line index), rhs = band * P + R,
+ * bounded = 1 where the node and both along-line neighbours are direct.  The
+ * film responds through the distributed kernel cut to |k - i| <=
+ * kernel_terms; on y-lines the rows of weighted-change nodes are v = P.
+ *  grid: 2D (ny > 1), nx, ny >= 5;  P, H_el: DEVICE B x nx x ny (node (i, j)
+ *  at (b*nx + i)*ny + j);  H0: DEVICE [B];  band: DEVICE rows*9, rhs: DEVICE
+ *  rows, bounded: DEVICE uint8 rows (rows = B * lines * (line length - 2));
+ *  direct: DEVICE uint8 B x nx x ny out or NULL;  workspace: DEVICE,
+ *  ehl_point_assemble_workspace_bytes(grid, B).
+ */
+size_t ehl_point_assemble_workspace_bytes(const ehl_grid *grid, int B);
+int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid *grid, const ehl_params *params,
+                             int B, const ehl_opts *opts, int axis, int color, const double *P,
+                             const double *H_el, const double *H0, double *band, double *rhs,
+                             uint8_t *bounded, uint8_t *direct, void *workspace, void *stream);
+
+/*
  * ehl_newton_tvd -- line contact: the hybrid Newton line iteration (Lhs1)
  * for B instances on one grid until each converges or hits max_newton:
  * deformation (MFMA), assembly, PAQIF solve of the linearised LCP (exact
@@ -265,6 +288,13 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid *grid, const ehl_p
  *  status: DEVICE int32[B] (SYS_OK, SYS_NEWTON_NOT_CONVERGED,
  *  SYS_NEGATIVE_FILM, SYS_NONFINITE).  iters: DEVICE int32[B].
  *  workspace: DEVICE, ehl_newton_workspace_bytes(handle, grid, B, opts).
+ * Point contact (grid with ny > 1; nx, ny >= 5): alternating x/y line sweeps,
+ * each sweep direction in two colours of lines (odd line index, then even,
+ * the film re-evaluated in between), every colour one batched PAQIF solve of
+ * its lines; weighted change with quarter weights to the four neighbours
+ * (eq. 69); y-lines change the direct nodes only; H0 <- H0 - c (2 pi/3 -
+ * hx hy sum P) after each direction (eq. 75); convergence tested after each
+ * x+y step.  P, H: DEVICE B x nx x ny; rough must be NULL.
  */
 size_t ehl_newton_workspace_bytes(paqif_handle handle, const ehl_grid *grid, int B,
                                   const ehl_opts *opts);

@@ -91,6 +91,11 @@ def lib():
                                         ctypes.POINTER(EhlOpts)], ctypes.c_size_t),
         "ehl_newton_tvd": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int, ctypes.POINTER(EhlOpts),
                             vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "ehl_point_assemble_workspace_bytes": ([ctypes.POINTER(EhlGrid), ctypes.c_int],
+                                               ctypes.c_size_t),
+        "ehl_point_sweep_assemble": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int,
+                                      ctypes.POINTER(EhlOpts), ctypes.c_int, ctypes.c_int, vp, vp,
+                                      vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "ehl_adjoint_workspace_bytes": ([vp, ctypes.POINTER(EhlGrid), ctypes.c_int],
                                         ctypes.c_size_t),
         "ehl_adjoint_solve": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int,

@@ -150,6 +150,302 @@ __global__ void final_status_kernel(int B, const uint8_t* done, const double* Hm
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Point contact (2D grid): workspace and driver.
+// ---------------------------------------------------------------------------
+struct PointLayout {
+    size_t dws, hel, nodes, direct, q, pstart, band, rhs, v, bounded, done, offs[4], lst, lit, lcp,
+        total;
+    int nlc[4], nrow[4];  // (axis, colour) -> lines per instance, rows per line
+};
+
+PointLayout point_layout(const ehl_grid* g, int B, const ehl_opts* o)
+{
+    PointLayout L;
+    const size_t cells = (size_t)g->nx * g->ny * B;
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p += a256(bytes);
+        return at;
+    };
+    L.dws = take(deform_ws_bytes(g, B));
+    L.hel = take(cells * sizeof(double));
+    L.nodes = take(6 * cells * sizeof(double));
+    L.direct = take(cells);
+    L.q = take(cells * sizeof(double));
+    L.pstart = take(cells * sizeof(double));
+    size_t rows_max = 0;
+    int cnt_max = 0, n_max = 0;
+    for (int ax = 0; ax < 2; ax++)
+        for (int c = 0; c < 2; c++) {
+            const int k = 2 * ax + c;
+            L.nlc[k] = pq::point_color_lines(g->nx, g->ny, ax, c);
+            L.nrow[k] = (ax == 0 ? g->nx : g->ny) - 2;
+            rows_max = std::max(rows_max, (size_t)L.nlc[k] * L.nrow[k] * B);
+            cnt_max = std::max(cnt_max, L.nlc[k] * B);
+            n_max = std::max(n_max, L.nrow[k]);
+        }
+    L.band = take(rows_max * 9 * sizeof(double));
+    L.rhs = take(rows_max * sizeof(double));
+    L.v = take(rows_max * sizeof(double));
+    L.bounded = take(rows_max);
+    L.done = take(B);
+    for (int k = 0; k < 4; k++) L.offs[k] = take((size_t)(L.nlc[k] * B + 1) * sizeof(int64_t));
+    L.lst = take((size_t)cnt_max * sizeof(int32_t));
+    L.lit = take((size_t)cnt_max * sizeof(int32_t));
+    L.lcp = take(lcp_ws_bytes(cnt_max, n_max, o ? o->lcp_prec : PREC_FP64));
+    L.total = p;
+    return L;
+}
+
+__global__ void point_init_kernel(int B, uint8_t* done, int32_t* status, int32_t* iters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) {
+        done[i] = 0;
+        status[i] = SYS_NEWTON_NOT_CONVERGED;
+        iters[i] = 0;
+    }
+}
+
+__global__ void point_offsets_kernel(int count, int n, int64_t* offs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= count) offs[i] = (int64_t)i * n;
+}
+
+int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* params, int B,
+                 const ehl_opts* opts, double* P, double* H0, double* H, double* Hmin,
+                 int32_t* status, int32_t* iters, char* ws, hipStream_t s, bool capture)
+{
+    const PointLayout L = point_layout(grid, B, opts);
+    const int Nx = grid->nx, Ny = grid->ny;
+    const double hx = hx_of(grid), hy = hy_of(grid);
+    const size_t cells = (size_t)Nx * Ny * B;
+    double* dws = reinterpret_cast<double*>(ws + L.dws);  // k2 table first
+    double* hel = reinterpret_cast<double*>(ws + L.hel);
+    double* nodes = reinterpret_cast<double*>(ws + L.nodes);
+    uint8_t* direct = reinterpret_cast<uint8_t*>(ws + L.direct);
+    double* Q = reinterpret_cast<double*>(ws + L.q);
+    double* Pst = reinterpret_cast<double*>(ws + L.pstart);
+    double* band = reinterpret_cast<double*>(ws + L.band);
+    double* rhs = reinterpret_cast<double*>(ws + L.rhs);
+    double* v = reinterpret_cast<double*>(ws + L.v);
+    uint8_t* bounded = reinterpret_cast<uint8_t*>(ws + L.bounded);
+    uint8_t* done = reinterpret_cast<uint8_t*>(ws + L.done);
+    int32_t* lst = reinterpret_cast<int32_t*>(ws + L.lst);
+    int32_t* lit = reinterpret_cast<int32_t*>(ws + L.lit);
+    char* lcpws = ws + L.lcp;
+    int st;
+    // kernel table, offsets, flags, start
+    if ((st = run_deformation(grid, P, B, PREC_FP64, hel, ws + L.dws, false, s))) return st;
+    for (int k = 0; k < 4; k++) {
+        const int cnt = L.nlc[k] * B;
+        hipLaunchKernelGGL(point_offsets_kernel, dim3((cnt + 256) / 256), dim3(256), 0, s, cnt,
+                           L.nrow[k], reinterpret_cast<int64_t*>(ws + L.offs[k]));
+    }
+    hipLaunchKernelGGL(point_init_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done, status,
+                       iters);
+    if (opts->start_rule) {
+        if ((st = pq::launch_point_start(Nx, Ny, B, grid->x0, grid->y0, hx, hy, P, s))) return st;
+        if ((st = run_deformation(grid, P, B, PREC_FP64, hel, ws + L.dws, true, s))) return st;
+        if ((st = pq::launch_point_h0_rule(Nx, Ny, B, grid->x0, grid->y0, hx, hy, params, hel, H0,
+                                           s)))
+            return st;
+    }
+    if (hipMemcpyAsync(Pst, P, cells * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return PAQIF_EHIP;
+
+    pq::PointNodeArgs na;
+    na.Nx = Nx;
+    na.Ny = Ny;
+    na.B = B;
+    na.x0 = grid->x0;
+    na.y0 = grid->y0;
+    na.hx = hx;
+    na.hy = hy;
+    na.switch_ratio = opts->switch_ratio;
+    na.params = params;
+    na.Hel = hel;
+    na.H0 = H0;
+    na.skip = done;
+    na.eps = nodes;
+    na.rH = nodes + cells;
+    na.rho = nodes + 2 * cells;
+    na.drhoH = nodes + 3 * cells;
+    na.eP = nodes + 4 * cells;
+    na.eH = nodes + 5 * cells;
+    na.direct = direct;
+
+    pq::PointAssembleArgs pa;
+    pa.Nx = Nx;
+    pa.Ny = Ny;
+    pa.B = B;
+    pa.kterms = opts->kernel_terms;
+    pa.hx = hx;
+    pa.hy = hy;
+    pa.k2 = dws;
+    pa.eps = na.eps;
+    pa.rH = na.rH;
+    pa.rho = na.rho;
+    pa.drhoH = na.drhoH;
+    pa.eP = na.eP;
+    pa.eH = na.eH;
+    pa.direct = direct;
+    pa.skip = done;
+    pa.band = band;
+    pa.rhs = rhs;
+    pa.bounded = bounded;
+
+    pq::LcpArgs la;
+    la.order = nullptr;
+    la.band = band;
+    la.b = rhs;
+    la.bounded = bounded;
+    la.mode = LCP_EXACT;
+    la.max_iter = opts->lcp_max_iter;
+    la.refine_tol = 1e-12;
+    la.u = v;
+    la.w = nullptr;
+    la.active_out = nullptr;
+    la.status = lst;
+    la.iters = lit;
+    la.rec = lcpws;
+    {
+        int cnt_max = 0, n_max = 0;
+        for (int k = 0; k < 4; k++) {
+            cnt_max = std::max(cnt_max, L.nlc[k] * B);
+            n_max = std::max(n_max, L.nrow[k]);
+        }
+        const size_t recs = (size_t)(((int64_t)cnt_max * n_max + cnt_max) / 2 + 1);
+        const size_t elt = opts->lcp_prec == PREC_FP32_IR ? sizeof(float) : sizeof(double);
+        const size_t rb = a256(recs * (size_t)pq::record_stride(4, true) * elt);
+        la.act = reinterpret_cast<uint8_t*>(lcpws + rb);
+        la.r = opts->lcp_prec == PREC_FP32_IR
+                   ? reinterpret_cast<double*>(lcpws + rb + a256((size_t)cnt_max * n_max))
+                   : nullptr;
+    }
+    la.skip = nullptr;
+
+    pq::PointUpdateArgs ua;
+    ua.Nx = Nx;
+    ua.Ny = Ny;
+    ua.B = B;
+    ua.omega = opts->omega;
+    ua.v = v;
+    ua.direct = direct;
+    ua.skip = done;
+
+    pq::PointH0Args ha;
+    ha.Nx = Nx;
+    ha.Ny = Ny;
+    ha.B = B;
+    ha.hx = hx;
+    ha.hy = hy;
+    ha.c_h0 = opts->c_h0;
+    ha.load_target = 2.0 * M_PI / 3.0;
+    ha.Pstart = Pst;
+    ha.H0 = H0;
+    ha.done = done;
+    ha.status = status;
+    ha.iters = iters;
+
+    const int layout = handle->layout[1][opts->lcp_prec == PREC_FP32_IR];
+    auto one_step = [&](int dprec) -> int {
+        int e;
+        double* cur = P;
+        double* nxt = Q;
+        for (int ax = 0; ax < 2; ax++) {
+            for (int c = 1; c >= 0; c--) {
+                const int k = 2 * ax + c;
+                if ((e = run_deformation(grid, cur, B, dprec, hel, ws + L.dws, true, s))) return e;
+                na.P = cur;
+                if ((e = pq::launch_point_nodes(na, s))) return e;
+                pa.axis = ax;
+                pa.color = c;
+                pa.P = cur;
+                if ((e = pq::launch_point_assemble(pa, s))) return e;
+                la.count = L.nlc[k] * B;
+                la.offsets = reinterpret_cast<const int64_t*>(ws + L.offs[k]);
+                if (la.count > 0 && (e = pq::dispatch_lcp(4, la, opts->lcp_prec, layout, s)))
+                    return e;
+                ua.axis = ax;
+                ua.color = c;
+                ua.P = cur;
+                ua.Pout = nxt;
+                if ((e = pq::launch_point_update(ua, s))) return e;
+                std::swap(cur, nxt);
+            }
+            ha.P = cur;
+            ha.tol = opts->tol;
+            if ((e = pq::launch_point_h0(ha, ax == 1 ? 1 : 0, s))) return e;
+        }
+        return PAQIF_OK;  // four colour updates: the state is back in P
+    };
+
+    std::vector<uint8_t> hdone(B);
+    const int K = opts->steps_per_graph;
+    const int dprec = opts->deform_prec;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = capture;
+    if (use_graph) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            use_graph = false;
+        else {
+            int e = 0;
+            for (int k = 0; k < K && !e; k++) e = one_step(dprec);
+            const hipError_t ce = hipStreamEndCapture(s, &graph);
+            if (e || ce != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                use_graph = false;
+            } else {
+                if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                    exec = nullptr;
+                    use_graph = false;
+                }
+                (void)hipGraphDestroy(graph);
+            }
+        }
+    }
+    int steps = 0;
+    while (steps < opts->max_newton) {
+        if (use_graph) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return PAQIF_EHIP;
+            }
+        } else {
+            for (int k = 0; k < K; k++)
+                if ((st = one_step(dprec))) return st;
+        }
+        steps += K;
+        if (hipMemcpyAsync(hdone.data(), done, B, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            return PAQIF_EHIP;
+        }
+        if (std::all_of(hdone.begin(), hdone.end(), [](uint8_t d) { return d != 0; })) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if ((st = run_deformation(grid, P, B, PREC_FP64, hel, ws + L.dws, true, s))) return st;
+    if ((st = pq::launch_point_film(Nx, Ny, B, grid->x0, grid->y0, hx, hy, hel, H0, H, Hmin, s)))
+        return st;
+    hipLaunchKernelGGL(final_status_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done, Hmin,
+                       status);
+    return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+// node arrays + kernel table for the standalone point assembly
+size_t point_assemble_ws(const ehl_grid* g, int B)
+{
+    return a256(deform_ws_bytes(g, B)) + a256(6 * (size_t)g->nx * g->ny * B * sizeof(double)) +
+           a256((size_t)g->nx * g->ny * B);
+}
+
 }  // namespace
 
 extern "C" {
@@ -210,7 +506,9 @@ size_t ehl_newton_workspace_bytes(paqif_handle handle, const ehl_grid* grid, int
                                   const ehl_opts* opts)
 {
     (void)handle;
-    if (!valid_line(grid) || B <= 0 || !valid_opts(opts)) return 0;
+    if (B <= 0 || !valid_opts(opts)) return 0;
+    if (valid_point(grid)) return point_layout(grid, B, opts).total;
+    if (!valid_line(grid)) return 0;
     return newton_layout(grid, B, opts).total;
 }
 
@@ -218,10 +516,17 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
                    const ehl_opts* opts, const double* rough, double* P, double* H0, double* H,
                    double* Hmin, int32_t* status, int32_t* iters, void* workspace, void* stream)
 {
-    if (!handle || !valid_line(grid) || B < 0 || !valid_opts(opts)) return PAQIF_EINVAL;
+    if (!handle || B < 0 || !valid_opts(opts)) return PAQIF_EINVAL;
+    if (!valid_line(grid) && !(valid_point(grid) && grid->nx >= 5 && grid->ny >= 5))
+        return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H0 || !Hmin || !status || !iters || !workspace) return PAQIF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (valid_point(grid)) {
+        if (rough) return PAQIF_EINVAL;  // roughness is a line-contact input
+        return point_newton(handle, grid, params, B, opts, P, H0, H, Hmin, status, iters,
+                            static_cast<char*>(workspace), s, stream != nullptr);
+    }
     const NewtonLayout L = newton_layout(grid, B, opts);
     char* ws = static_cast<char*>(workspace);
     const int N = grid->nx, n = N - 2;
@@ -393,6 +698,82 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     hipLaunchKernelGGL(final_status_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done, Hmin,
                        status);
     return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+size_t ehl_point_assemble_workspace_bytes(const ehl_grid* grid, int B)
+{
+    if (!valid_point(grid) || B <= 0) return 0;
+    return point_assemble_ws(grid, B);
+}
+
+int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_params* params,
+                             int B, const ehl_opts* opts, int axis, int color, const double* P,
+                             const double* H_el, const double* H0, double* band, double* rhs,
+                             uint8_t* bounded, uint8_t* direct, void* workspace, void* stream)
+{
+    if (!handle || !valid_point(grid) || grid->nx < 5 || grid->ny < 5 || B < 0 || !opts)
+        return PAQIF_EINVAL;
+    if ((axis != 0 && axis != 1) || (color != 0 && color != 1)) return PAQIF_EINVAL;
+    if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
+    if (B == 0) return PAQIF_OK;
+    if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded || !workspace)
+        return PAQIF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int Nx = grid->nx, Ny = grid->ny;
+    const size_t cells = (size_t)Nx * Ny * B;
+    char* ws = static_cast<char*>(workspace);
+    double* k2 = reinterpret_cast<double*>(ws);
+    double* nodes = reinterpret_cast<double*>(ws + a256(deform_ws_bytes(grid, B)));
+    uint8_t* dir = direct ? direct
+                          : reinterpret_cast<uint8_t*>(ws + a256(deform_ws_bytes(grid, B)) +
+                                                       a256(6 * cells * sizeof(double)));
+    int st;
+    if ((st = pq::launch_point_kernel_tab(Nx, Ny, hx_of(grid), hy_of(grid), k2, s))) return st;
+    pq::PointNodeArgs na;
+    na.Nx = Nx;
+    na.Ny = Ny;
+    na.B = B;
+    na.x0 = grid->x0;
+    na.y0 = grid->y0;
+    na.hx = hx_of(grid);
+    na.hy = hy_of(grid);
+    na.switch_ratio = opts->switch_ratio;
+    na.params = params;
+    na.P = P;
+    na.Hel = H_el;
+    na.H0 = H0;
+    na.skip = nullptr;
+    na.eps = nodes;
+    na.rH = nodes + cells;
+    na.rho = nodes + 2 * cells;
+    na.drhoH = nodes + 3 * cells;
+    na.eP = nodes + 4 * cells;
+    na.eH = nodes + 5 * cells;
+    na.direct = dir;
+    if ((st = pq::launch_point_nodes(na, s))) return st;
+    pq::PointAssembleArgs pa;
+    pa.Nx = Nx;
+    pa.Ny = Ny;
+    pa.B = B;
+    pa.axis = axis;
+    pa.color = color;
+    pa.kterms = opts->kernel_terms;
+    pa.hx = na.hx;
+    pa.hy = na.hy;
+    pa.k2 = k2;
+    pa.P = P;
+    pa.eps = na.eps;
+    pa.rH = na.rH;
+    pa.rho = na.rho;
+    pa.drhoH = na.drhoH;
+    pa.eP = na.eP;
+    pa.eH = na.eH;
+    pa.direct = dir;
+    pa.skip = nullptr;
+    pa.band = band;
+    pa.rhs = rhs;
+    pa.bounded = bounded;
+    return pq::launch_point_assemble(pa, s);
 }
 
 }  // extern "C"

@@ -63,4 +63,56 @@ int launch_line_film(int N, int B, double h, double x0, const double* Hel, const
                      const double* rough, double* H, double* Hmin, int32_t* argmin,
                      hipStream_t s);
 
+
+// ehl_point.hip (point contact, alternating line sweeps in two colours)
+struct PointNodeArgs {
+    int Nx, Ny, B;
+    double x0, y0, hx, hy, switch_ratio;
+    const ehl_params* params;
+    const double *P, *Hel, *H0;
+    const uint8_t* skip;  // B or null
+    double *eps, *rH, *rho, *drhoH, *eP, *eH;
+    uint8_t* direct;
+};
+int launch_point_nodes(const PointNodeArgs& a, hipStream_t s);
+
+struct PointAssembleArgs {
+    int Nx, Ny, B, axis, color, kterms;
+    double hx, hy;
+    const double* k2;  // Nx x Ny kernel table
+    const double *P, *eps, *rH, *rho, *drhoH, *eP, *eH;
+    const uint8_t* direct;
+    const uint8_t* skip;
+    double *band, *rhs;
+    uint8_t* bounded;
+};
+int point_color_lines(int Nx, int Ny, int axis, int color);
+int launch_point_assemble(const PointAssembleArgs& a, hipStream_t s);
+
+struct PointUpdateArgs {
+    int Nx, Ny, B, axis, color;
+    double omega;
+    const double *P, *v;
+    const uint8_t* direct;
+    const uint8_t* skip;
+    double* Pout;
+};
+int launch_point_update(const PointUpdateArgs& a, hipStream_t s);
+
+struct PointH0Args {
+    int Nx, Ny, B;
+    double hx, hy, c_h0, tol, load_target;
+    const double* P;
+    double *Pstart, *H0;
+    uint8_t* done;
+    int32_t *status, *iters;
+};
+int launch_point_h0(const PointH0Args& a, int check, hipStream_t s);
+int launch_point_start(int Nx, int Ny, int B, double x0, double y0, double hx, double hy,
+                       double* P, hipStream_t s);
+int launch_point_h0_rule(int Nx, int Ny, int B, double x0, double y0, double hx, double hy,
+                         const ehl_params* params, const double* Hel, double* H0, hipStream_t s);
+int launch_point_film(int Nx, int Ny, int B, double x0, double y0, double hx, double hy,
+                      const double* Hel, const double* H0, double* H, double* Hmin, hipStream_t s);
+
 }  // namespace pq

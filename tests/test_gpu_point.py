@@ -1,0 +1,117 @@
+"""EHL point contact on the GPU vs the FP64 oracle.
+
+  * sweep assembly (both directions, both colours): band, rhs and masks of
+    every line against the oracle's sweep systems, FP64 elementwise formulas
+    in another evaluation order: 1e-11 of the row scale plus 1e-14 of the
+    instance scale (the line-contact assembly bound), masks exact;
+  * converged alternating-sweep solution on 33 x 33 nodes: P, H0, Hmin
+    within 1e-9 relative (both sides stop at max |dP| <= 1e-12 per step;
+    with a contraction of about 0.97 per step each is within ~3e-11 of the
+    fixed point);
+  * the 257 x 257 contact (M = 200, L = 10): converged, load balance, y-mirror
+    symmetry and complementarity of the oracle's residual on the GPU
+    solution.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import deform as odef
+from oracle import ehl_line as OL
+from oracle import ehl_point as OP
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda")
+
+
+def _state(Nx, Ny, seed):
+    X, Y, hx, hy = OP.grid(Nx, Ny)
+    rng = np.random.default_rng(seed)
+    P = OP.hertz_start(X, Y) * (1 + 0.2 * rng.random((Nx, Ny)))
+    P[0, :] = P[-1, :] = P[:, 0] = P[:, -1] = 0.0
+    P[int(0.75 * Nx):int(0.75 * Nx) + 2, Ny // 3:Ny // 2] = 0.0   # a cavitated patch
+    return X, Y, hx, hy, P
+
+
+@pytest.mark.parametrize("Nx,Ny", [(17, 13), (33, 33)])
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("kterms", [1, 2])
+def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms):
+    E = gpu.ehl
+    Ms, Ls, H0s = [20.0, 200.0], [10.0, 8.0], [-0.5, -0.9]
+    X, Y, hx, hy, _ = _state(Nx, Ny, 0)
+    Ps = np.stack([_state(Nx, Ny, s)[4] for s in (1, 2)])
+    Hel = np.stack([odef.point_deformation(Ps[b], hx, hy) for b in range(2)])
+    k2 = odef.point_kernel(Nx, Ny, hx, hy)
+    opts = E.default_opts(kernel_terms=kterms)
+    grid = E.point_grid(Nx, Ny)
+    for color in (1, 0):
+        g = E.point_sweep_assemble(grid, E.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
+                                   torch.as_tensor(Hel, device=DEV),
+                                   torch.as_tensor(H0s, dtype=torch.float64, device=DEV), axis,
+                                   color, opts)
+        g = {k: v.cpu().numpy() for k, v in g.items()}
+        nl = Ny if axis == 0 else Nx
+        lines = [l for l in range(1, nl - 1) if l % 2 == color]
+        for b in range(2):
+            _, lam, ph = OP.moes_point(Ms[b], Ls[b])
+            H = H0s[b] + 0.5 * X[:, None] ** 2 + 0.5 * Y[None, :] ** 2 + Hel[b]
+            st = OL.state(Ps[b], H, ph, lam)
+            direct = OP.classify(Ps[b], st["eps"], hx, hy)
+            A, rhs, bounded = OP.sweep_systems(Ps[b], H, st, ph, lam, hx, hy, k2, direct, axis,
+                                               kterms)
+            assert (g["direct"][b] == direct.astype(np.uint8)).all()
+            inst = np.abs(A).max()
+            for slot, l in enumerate(lines):
+                sys_ = b * len(lines) + slot
+                ref = A[l - 1]
+                scale = np.abs(ref).max(axis=1, keepdims=True)
+                assert (np.abs(g["band"][sys_] - ref) <= 1e-11 * scale + 1e-14 * inst).all(), \
+                    (b, color, l)
+                assert (g["bounded"][sys_] == bounded[l - 1]).all()
+                rs = max(1.0, np.abs(rhs[l - 1]).max())
+                assert np.abs(g["rhs"][sys_] - rhs[l - 1]).max() <= 1e-11 * rs + 1e-14 * inst
+
+
+@pytest.fixture(scope="module")
+def oracle_33():
+    r = OP.solve_point(20.0, 10.0, 33, 33, tol=1e-12, max_steps=1500)
+    assert r["status"] == 0
+    return r
+
+
+def test_point_newton_matches_oracle(gpu, oracle_33):
+    E = gpu.ehl
+    o = oracle_33
+    r = E.solve_point([20.0], [10.0], 33, 33, opts=E.default_opts(tol=1e-12, max_newton=1500))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    P = r["P"][0].cpu().numpy()
+    assert np.abs(P - o["P"]).max() <= 1e-9 * np.abs(o["P"]).max()
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-9 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-9 * abs(o["Hmin"])
+
+
+def test_point_config5_properties(gpu):
+    """257 x 257, M = 200, L = 10: properties of the GPU solution checked with
+    the oracle's residual."""
+    E = gpu.ehl
+    N = 257
+    r = E.solve_point([200.0], [10.0], N, N, opts=E.default_opts(tol=1e-10, max_newton=6000))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0, (int(r["status"][0]), int(r["iters"][0]))
+    P = r["P"][0].cpu().numpy()
+    H0 = float(r["H0"][0])
+    X, Y, hx, hy = OP.grid(N, N)
+    assert abs(hx * hy * P.sum() - OP.LOAD) <= 1e-9
+    assert np.abs(P - P[:, ::-1]).max() <= 1e-9 * P.max()
+    assert (P >= 0).all()
+    _, lam, ph = OP.moes_point(200.0, 10.0)
+    H = OP.film(P, H0, X, Y, hx, hy)
+    R, st = OP.residual(P, H, ph, lam, hx, hy)
+    Pi = P[1:-1, 1:-1]
+    scale = np.abs(st["rH"]).max() / hx          # size of the flux term
+    press = Pi > 1e-8
+    assert np.abs(R[press]).max() <= 1e-6 * scale
+    assert (-R[~press] >= -1e-6 * scale).all()
