@@ -73,7 +73,7 @@ def ehl_legs(P, torch, synth, dev, args):
     M, L = synth.ehl_sweep_params(nb, seed=args.seed)
     res = {}
     for name, prec in (("fp64", P.PREC_FP64), ("fp32_deform", P.PREC_FP32)):
-        opts = P.ehl.default_opts(deform_prec=prec, max_newton=2000, lcp_max_iter=16)
+        opts = P.ehl.default_opts(deform_prec=prec, max_newton=3000, lcp_max_iter=16)
         torch.cuda.synchronize()
         t0 = _t.perf_counter()
         r = P.ehl.solve_line(M, L, 1025, opts=opts)
@@ -91,7 +91,71 @@ def ehl_legs(P, torch, synth, dev, args):
         v.pop("_P")
     res["max_rel_diff_fp32_vs_fp64"] = float(d)
     out["sweep_N1025"] = res
+    if not args.no_adjoint:
+        out["adjoint_N2049"] = adjoint_leg(P, torch, synth, args)
+    if not args.no_point:
+        out["point_257"] = point_leg(P, torch, args)
     return out
+
+
+def adjoint_leg(P, torch, synth, args):
+    """Adjoint of the line contact: N=2049, 64 instances, M log-uniform in
+    [20, 500], L = 10, roughness A sin(2 pi X / 0.25).  Forward solve, then
+    the hand-written adjoint for out = H0 (gH0 = 1) and out = Hmin (film
+    cotangent at the arg-min); gradients dM, dL and d(roughness)."""
+    import time as _t
+    NN, B = 2049, 64
+    M, L = synth.ehl_adjoint_params(B, seed=args.seed)
+    x = -4.5 + 6.0 * np.arange(NN) / (NN - 1)
+    dev = torch.device("cuda", 0)
+    rg = torch.as_tensor(np.stack([synth.roughness(x, amplitude=args.rough_amp)] * B), device=dev)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    r = P.ehl.solve_line(M, L, NN, rough=rg)
+    torch.cuda.synchronize()
+    t_fwd = _t.perf_counter() - t0
+    ok = (r["status"] == 0)
+    gH = torch.zeros_like(r["H"])
+    gH[torch.arange(B, device=dev), torch.argmin(r["H"], dim=1)] = 1.0
+    ones = torch.ones(B, dtype=torch.float64, device=dev)
+    P.ehl.adjoint(M, L, NN, r["P"], r["H0"], gH0=ones, rough=rg)  # warm-up
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    a0 = P.ehl.adjoint(M, L, NN, r["P"], r["H0"], gH0=ones, rough=rg)
+    a1 = P.ehl.adjoint(M, L, NN, r["P"], r["H0"], gH=gH, rough=rg)
+    torch.cuda.synchronize()
+    t_adj = _t.perf_counter() - t0
+    okn = ok.cpu().numpy()
+    st0, st1 = a0["status"].cpu().numpy(), a1["status"].cpu().numpy()
+    log(f"adjoint leg: forward {t_fwd:.2f} s ({int(okn.sum())}/{B} converged), "
+        f"adjoint {t_adj:.3f} s")
+    return dict(forward_seconds=round(t_fwd, 3), converged=int(okn.sum()), instances=B,
+                roughness_amplitude=args.rough_amp,
+                adjoint_seconds_two_outputs=round(t_adj, 4),
+                gradients_per_s=round(2 * B / t_adj, 2),
+                adjoint_status_ok_on_converged=bool((st0[okn] == 0).all() and (st1[okn] == 0).all()),
+                arnoldi_steps_mean=float((a0["iters"].float().mean() + a1["iters"].float().mean()) / 2),
+                example=dict(M=float(M[0]), dH0_dM=float(a0["dM"][0]), dHmin_dL=float(a1["dL"][0])))
+
+
+def point_leg(P, torch, args):
+    """Point contact: 257 x 257 nodes on [-4.5, 1.5] x [-3, 3], M = 200,
+    L = 10, load 2 pi/3; alternating two-colour x/y line sweeps to
+    max |dP| <= 1e-10 per step; time to solution."""
+    import time as _t
+    opts = P.ehl.default_opts(tol=1e-10, max_newton=30000, c_h0=0.02)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    r = P.ehl.solve_point([200.0], [10.0], 257, 257, opts=opts)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t0
+    steps = int(r["iters"][0])
+    Pg = r["P"][0]
+    log(f"point leg: {dt:.1f} s, {steps} steps, status {int(r['status'][0])}")
+    return dict(seconds=round(dt, 3), solves_per_s=round(1.0 / dt, 4), status=int(r["status"][0]),
+                steps=steps, ms_per_step=round(dt * 1e3 / max(1, steps), 4),
+                H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]),
+                y_mirror_max_diff=float((Pg - Pg.flip(1)).abs().max()))
 
 
 def main():
@@ -103,8 +167,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-ehl", action="store_true")
-    ap.add_argument("--ehl-sweep", type=int, default=32,
+    ap.add_argument("--ehl-sweep", type=int, default=512,
                     help="instances of the line-contact sweep leg (N=1025)")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-point", action="store_true")
+    ap.add_argument("--rough-amp", type=float, default=0.005,
+                    help="roughness amplitude of the adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "

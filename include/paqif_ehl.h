@@ -215,6 +215,10 @@ typedef struct {
     int32_t steps_per_graph; /* Newton steps per captured HIP graph replay    */
     int32_t start_rule;  /* 1: Hertzian P and H0 = 0.4/sqrt(M) - min_{|X|<=1}
                             (X^2/2 + H_el); 0: use P and H0 as given           */
+    int32_t limiter_jacobian; /* limiter terms of the Newton matrix (the
+                            residual always has the full limiter): 0 exact
+                            derivatives, 1 ratio phi(r) frozen at the current
+                            iterate (eqs. 64-65), 2 first-order flux           */
 } ehl_opts;
 
 /*

@@ -60,6 +60,7 @@ RHO_A = 0.59e9
 RHO_B = 1.34
 XA, XB = -4.5, 1.5
 SWITCH = 0.6
+LIMJAC = 2   # limiter terms of the Newton matrix (see limiter_jacobian)
 
 
 def moes_line(M, L):
@@ -110,6 +111,22 @@ def vanleer(dm, dp):
     return psi, dpsi_dp, dpsi_dm
 
 
+def limiter_jacobian(dm, dp, mode):
+    """Limiter coefficients (pa = d/dD+, pb = d/dD-) used in the Newton
+    matrix; the residual always uses psi.  mode 0: exact derivatives of psi;
+    1: the ratio frozen at the current iterate, psi = phi(r) D- with r = D+/D-,
+    phi(r) = 2r/(1+r) held fixed (eqs. 64-65 evaluate r from the old film), so
+    pa = 0, pb = phi; 2: first-order upwind flux, pa = pb = 0."""
+    _, pa, pb = vanleer(dm, dp)
+    if mode == 0:
+        return pa, pb
+    same = dm * dp > 0.0
+    phi = np.where(same, 2.0 * dp / np.where(same, dm + dp, 1.0), 0.0)
+    if mode == 1:
+        return np.zeros_like(pa), phi
+    return np.zeros_like(pa), np.zeros_like(pb)
+
+
 def state(P, H, ph, lam):
     rho, drho, lneta, dlneta = lubricant(P, ph)
     eta = np.exp(lneta)
@@ -131,7 +148,7 @@ def residual(P, H, ph, lam, h):
     return R, s
 
 
-def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1):
+def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0):
     """Band of dR_i/dsigma_j (interior rows and columns) for the change
     delta = D sigma (column j of D: e_j for a direct node, e_j - (e_{j-1} +
     e_{j+1})/2 for a distributive one; boundary nodes stay fixed).
@@ -193,7 +210,7 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1):
     epsh = 0.5 * (eps[:-1] + eps[1:])
     dm = rH[1:-1] - rH[:-2]
     dp = rH[2:] - rH[1:-1]
-    psi, pa, pb = vanleer(dm, dp)            # index t -> node t+1
+    pa, pb = limiter_jacobian(dm, dp, limjac)  # index t -> node t+1
     i = np.arange(1, N - 1)
     J = np.zeros((n, 9))
     for s in range(-4, 5):
@@ -277,7 +294,7 @@ def hybrid_direct(P, eps, h):
     return direct | near
 
 
-def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2):
+def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2, limjac=LIMJAC):
     """One Lhs1 step; returns (P_new, H0_new, info)."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
@@ -285,7 +302,7 @@ def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2
     direct_all = hybrid_direct(P, st["eps"], h)
     direct = direct_all[1:-1]
     D = distributive_matrix_band(direct)
-    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms)
+    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac)
     Pi = P[1:-1]
     b = band_matvec(A, Pi) + R
     nb = np.concatenate([[True], direct, [True]])
@@ -327,11 +344,12 @@ def lcp_exact(A, b, bounded):
 
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
-               rough=None, P=None, H0=None):
+               rough=None, P=None, H0=None, limjac=None):
     """Run the hybrid Newton line iteration to convergence.
 
-    Stops when max |P_new - P| <= tol * max(1, |P|_inf) and |pi/2 - h sum P|
-    <= tol (status 0), else status 6 after max_newton steps.  Returns a dict
+    Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
+    <= t, t = max(tol, 4 N eps) (status 0), else status 6 after max_newton
+    steps.  Returns a dict
     with P (N nodes), H0, H, Hmin (min over all nodes, first index), the
     number of steps and the status."""
     x, h = grid(N)
@@ -350,15 +368,19 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
         lcp_bad |= st != 0
         return u
 
+    # the FP64 rounding floor of the change grows with N: stop at
+    # max(tol, 4 N eps), eps = 2^-52
+    tl = max(tol, 4.0 * N * np.finfo(np.float64).eps)
     it = 0
     for it in range(1, max_newton + 1):
-        Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms)
+        Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms,
+                                   LIMJAC if limjac is None else limjac)
         dP = np.abs(Pn - P).max()
         P = Pn
         if not np.isfinite(dP):
             status = 2
             break
-        if dP <= tol * max(1.0, np.abs(P).max()) and abs(np.pi / 2 - h * P.sum()) <= tol:
+        if dP <= tl * max(1.0, np.abs(P).max()) and abs(np.pi / 2 - h * P.sum()) <= tl:
             status = 0
             break
     H = film(P, H0, x, kvec, rough)

@@ -126,7 +126,7 @@ def classify(P, eps, hx, hy):
     return d
 
 
-def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1):
+def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=EL.LIMJAC):
     """Band systems of every interior line of one sweep direction.
 
     axis = 0: x-lines (one per interior j, positions i); axis = 1: y-lines.
@@ -203,13 +203,14 @@ def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1):
     P_up, P_dn, P_c = Pg[lines + 1][:, 1:-1], Pg[lines - 1][:, 1:-1], P_l[:, 1:-1]
     dist_c = dist[lines][:, 1:-1]
     if axis == 0:
-        _, pa, pb = EL.vanleer(rH[lines][:, 1:-1] - rH[lines][:, :-2],
-                               rH[lines][:, 2:] - rH[lines][:, 1:-1])   # node t at [:, t-1]
+        pa, pb = EL.limiter_jacobian(rH[lines][:, 1:-1] - rH[lines][:, :-2],
+                                     rH[lines][:, 2:] - rH[lines][:, 1:-1], limjac)  # node t at [:, t-1]
     else:
         # the x-flux of row j depends on rho H at x-columns l-2 .. l+1; their
         # response to sigma on column l: the -sigma/4 moved to the columns
         # l +- 1 and the distributed kernel at x-offset a
-        _, pa_all, pb_all = EL.vanleer(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1])  # row t-1 -> column t
+        pa_all, pb_all = EL.limiter_jacobian(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1],
+                                             limjac)  # row t-1 -> column t
 
         def kx(a, d):
             return kv(k2[abs(a)], d)
@@ -369,11 +370,11 @@ def start_h0(X, Y, hx, hy, M):
     return 0.4 / np.sqrt(M) - g[inside].min()
 
 
-def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.1, kterms=1, max_steps=400, tol=1e-12,
+def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.02, kterms=2, max_steps=400, tol=1e-12,
                 rough=None, P=None, H0=None, lcp=None):
     """Alternating x/y line sweeps to convergence.  Stops when max |P change|
-    over one x+y step <= tol max(1, |P|_inf) and |2pi/3 - hx hy sum P| <= tol
-    (status 0), else status 6.  Returns dict(P, H0, H, Hmin, iters, status,
+    over one x+y step <= t max(1, |P|_inf) and |2pi/3 - hx hy sum P| <= t,
+    t = max(tol, 4 max(Nx, Ny) eps) (status 0), else status 6.  Returns dict(P, H0, H, Hmin, iters, status,
     X, Y, hx, hy)."""
     X, Y, hx, hy = grid(Nx, Ny)
     k2 = deform.point_kernel(Nx, Ny, hx, hy)
@@ -384,6 +385,7 @@ def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.1, kterms=1, max_steps=400, tol=
     if lcp is None:
         lcp = lambda A, b, bd: EL.lcp_exact(A, b, bd)[0]
     status = 6
+    tl = max(tol, 4.0 * max(Nx, Ny) * np.finfo(np.float64).eps)
     it = 0
     for it in range(1, max_steps + 1):
         P1, H0 = half_sweep(P, H0, X, Y, hx, hy, k2, M, L, 0, omega, c_h0, kterms, lcp, rough)
@@ -393,7 +395,7 @@ def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.1, kterms=1, max_steps=400, tol=
         if not np.isfinite(dP):
             status = 2
             break
-        if dP <= tol * max(1.0, np.abs(P).max()) and abs(LOAD - hx * hy * P.sum()) <= tol:
+        if dP <= tl * max(1.0, np.abs(P).max()) and abs(LOAD - hx * hy * P.sum()) <= tl:
             status = 0
             break
     H = film(P, H0, X, Y, hx, hy, rough)

@@ -58,6 +58,11 @@ void host_kernel_head(double h, double kap[4])
     for (int m = 0; m < 4; m++) kap[m] = -(F((m + 0.5) * h) - F((m - 0.5) * h)) / M_PI;
 }
 
+// Rounding floor of the Newton change in FP64 on a line of n nodes: the
+// stopping test uses max(tol, 4 n eps), eps = 2^-52 (measured floors: about
+// 1.5e-13 at n = 1025 and 6e-13 at n = 2049, which a fixed 1e-13 never meets).
+double fp64_floor(int n) { return 4.0 * n * 2.220446049250313e-16; }
+
 bool valid_opts(const ehl_opts* o)
 {
     return o && o->omega > 0 && o->omega <= 1.0 && o->c_h0 > 0 && o->tol > 0 &&
@@ -66,7 +71,8 @@ bool valid_opts(const ehl_opts* o)
            (o->deform_prec == PREC_FP64 || o->deform_prec == PREC_FP32 ||
             o->deform_prec == PREC_SPLIT_BF16) &&
            (o->lcp_prec == PREC_FP64 || o->lcp_prec == PREC_FP32_IR) &&
-           o->steps_per_graph >= 1 && o->steps_per_graph <= 64;
+           o->steps_per_graph >= 1 && o->steps_per_graph <= 64 && o->limiter_jacobian >= 0 &&
+           o->limiter_jacobian <= 2;
 }
 
 // Newton workspace layout (line contact)
@@ -284,6 +290,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
     pa.Ny = Ny;
     pa.B = B;
     pa.kterms = opts->kernel_terms;
+    pa.limjac = opts->limiter_jacobian;
     pa.hx = hx;
     pa.hy = hy;
     pa.k2 = dws;
@@ -379,7 +386,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                 std::swap(cur, nxt);
             }
             ha.P = cur;
-            ha.tol = opts->tol;
+            ha.tol = std::max(opts->tol, fp64_floor(std::max(Nx, Ny)));
             if ((e = pq::launch_point_h0(ha, ax == 1 ? 1 : 0, s))) return e;
         }
         return PAQIF_OK;  // four colour updates: the state is back in P
@@ -475,6 +482,7 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_p
 {
     if (!handle || !valid_line(grid) || B < 0 || !opts) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
+    if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded) return PAQIF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -483,6 +491,7 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_p
     a.N = N;
     a.B = B;
     a.kterms = opts->kernel_terms;
+    a.limjac = opts->limiter_jacobian;
     a.h = hx_of(grid);
     a.x0 = grid->x0;
     a.switch_ratio = opts->switch_ratio;
@@ -562,6 +571,7 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     aa.N = N;
     aa.B = B;
     aa.kterms = opts->kernel_terms;
+    aa.limjac = opts->limiter_jacobian;
     aa.h = h;
     aa.x0 = grid->x0;
     aa.switch_ratio = opts->switch_ratio;
@@ -643,7 +653,7 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
         // a low-precision deformation only gets the iterate close (its noise
         // floor is far above tol); the FP64 phase finishes the convergence
         const bool low = dprec != PREC_FP64;
-        ua.tol = low ? std::max(opts->tol, 1e-5) : opts->tol;
+        ua.tol = low ? std::max(opts->tol, 1e-5) : std::max(opts->tol, fp64_floor(N));
         const int phase_cap = low ? opts->max_newton / 2 : opts->max_newton;
         if (ph > 0)
             hipLaunchKernelGGL(reopen_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done,
@@ -715,6 +725,7 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
         return PAQIF_EINVAL;
     if ((axis != 0 && axis != 1) || (color != 0 && color != 1)) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
+    if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded || !workspace)
         return PAQIF_EINVAL;
@@ -758,6 +769,7 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
     pa.axis = axis;
     pa.color = color;
     pa.kterms = opts->kernel_terms;
+    pa.limjac = opts->limiter_jacobian;
     pa.hx = na.hx;
     pa.hy = na.hy;
     pa.k2 = k2;

@@ -18,7 +18,7 @@ int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const
 
 // ehl_line.hip
 struct LineAssembleArgs {
-    int N, B, kterms;
+    int N, B, kterms, limjac;
     double h, x0, switch_ratio;
     const ehl_params* params;  // device, B
     const double* kvec;        // N (device) or null: use kap
@@ -77,7 +77,7 @@ struct PointNodeArgs {
 int launch_point_nodes(const PointNodeArgs& a, hipStream_t s);
 
 struct PointAssembleArgs {
-    int Nx, Ny, B, axis, color, kterms;
+    int Nx, Ny, B, axis, color, kterms, limjac;
     double hx, hy;
     const double* k2;  // Nx x Ny kernel table
     const double *P, *eps, *rH, *rho, *drhoH, *eP, *eH;

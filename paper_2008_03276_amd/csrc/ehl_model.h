@@ -73,4 +73,21 @@ PQ_DEV void van_leer(double dm, double dp, double& psi, double& pa, double& pb)
     }
 }
 
+// Limiter coefficients (pa, pb) used in the Newton matrix only (the residual
+// always uses psi itself): mode 0 the exact derivatives of psi; mode 1 the
+// ratio frozen at the current iterate, psi = phi(r) D- with r = D+/D- and
+// phi(r) = 2r/(1+r) held fixed (eqs. 64-65 take r from the old film), so
+// only D- moves: pa = 0, pb = phi; mode 2 the first-order upwind flux
+// (pa = pb = 0).
+PQ_DEV void limiter_jacobian(int mode, double dm, double dp, double& pa, double& pb)
+{
+    if (mode == 0) {
+        double psi;
+        van_leer(dm, dp, psi, pa, pb);
+        return;
+    }
+    pa = 0.0;
+    pb = (mode == 1 && dm * dp > 0.0) ? 2.0 * dp / (dm + dp) : 0.0;
+}
+
 }  // namespace pq

@@ -212,13 +212,16 @@ __global__ void __launch_bounds__(128) point_assemble_kernel(PointAssembleArgs a
     const double epm = 0.5 * (eps(l, p - 1) + eps(l, p));
     const double e_up = 0.5 * (eps(l, p) + eps(l + 1, p));
     const double e_dn = 0.5 * (eps(l, p) + eps(l - 1, p));
-    double pa0 = 0, pb0 = 0, pa1 = 0, pb1 = 0, psi;
+    double pa0 = 0, pb0 = 0, pa1 = 0, pb1 = 0;
+    const int lj = a.limjac;
     if (a.axis == 0) {
-        van_leer(rH(l, p) - rH(l, p - 1), rH(l, p + 1) - rH(l, p), psi, pa0, pb0);
-        if (p - 1 >= 1) van_leer(rH(l, p - 1) - rH(l, p - 2), rH(l, p) - rH(l, p - 1), psi, pa1, pb1);
+        limiter_jacobian(lj, rH(l, p) - rH(l, p - 1), rH(l, p + 1) - rH(l, p), pa0, pb0);
+        if (p - 1 >= 1)
+            limiter_jacobian(lj, rH(l, p - 1) - rH(l, p - 2), rH(l, p) - rH(l, p - 1), pa1, pb1);
     } else {
-        van_leer(rH(l, p) - rH(l - 1, p), rH(l + 1, p) - rH(l, p), psi, pa0, pb0);
-        if (l - 1 >= 1) van_leer(rH(l - 1, p) - rH(l - 2, p), rH(l, p) - rH(l - 1, p), psi, pa1, pb1);
+        limiter_jacobian(lj, rH(l, p) - rH(l - 1, p), rH(l + 1, p) - rH(l, p), pa0, pb0);
+        if (l - 1 >= 1)
+            limiter_jacobian(lj, rH(l - 1, p) - rH(l - 2, p), rH(l, p) - rH(l - 1, p), pa1, pb1);
     }
     double rhs = R;
 #pragma unroll

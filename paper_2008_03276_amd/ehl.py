@@ -25,7 +25,7 @@ def point_grid(Nx, Ny, x0=XA, x1=XB, y0=-3.0, y1=3.0):
 def default_opts(**kw):
     o = dict(omega=0.5, c_h0=0.1, switch_ratio=0.6, tol=1e-13, max_newton=4000, kernel_terms=2,
              lcp_max_iter=64, deform_prec=B.PREC_FP64, lcp_prec=B.PREC_FP64, steps_per_graph=16,
-             start_rule=1)
+             start_rule=1, limiter_jacobian=2)
     o.update(kw)
     return B.EhlOpts(**o)
 
@@ -139,9 +139,11 @@ def point_sweep_assemble(grid, params, P, Hel, H0, axis, color, opts=None):
 
 def solve_point(M, L, Nx, Ny, opts=None, P=None, H0=None, device=None, stream=None):
     """Alternating x/y line sweeps for B = len(M) point contacts on one grid
-    (ehl_newton_tvd on a 2D grid).  Returns dict(P (B, Nx, Ny), H0, H, Hmin,
-    status, iters)."""
-    opts = opts or default_opts()
+    (ehl_newton_tvd on a 2D grid).  The default options take the load
+    relaxation c = 0.02: the 2D load responds about ten times more strongly to
+    H0 than the line load, and c = 0.1 makes the H0 loop oscillate on 257 x 257
+    nodes.  Returns dict(P (B, Nx, Ny), H0, H, Hmin, status, iters)."""
+    opts = opts or default_opts(c_h0=0.02)
     device = device or torch.device("cuda", torch.cuda.current_device())
     grid = point_grid(Nx, Ny)
     params = params_tensor(M, L, device)

@@ -79,14 +79,15 @@ def _state(N, seed):
 
 @pytest.mark.parametrize("N", [9, 65, 257, 700])
 @pytest.mark.parametrize("kterms", [1, 2])
-def test_line_assembly(gpu, N, kterms):
+@pytest.mark.parametrize("limjac", [0, 1, 2])
+def test_line_assembly(gpu, N, kterms, limjac):
     P = gpu.ehl
     Ms, Ls, H0s = [20.0, 100.0, 500.0], [10.0, 5.0, 20.0], [-0.3, -0.55, -0.58]
     x, h, kvec, _ = _state(N, 0)
     Ps = np.stack([_state(N, s)[3] for s in range(3)])
     rough = 0.01 * np.sin(2 * np.pi * x / 0.25)[None, :].repeat(3, 0)
     Hel = np.stack([odef.line_deformation(Ps[b], h) for b in range(3)])
-    opts = P.default_opts(kernel_terms=kterms)
+    opts = P.default_opts(kernel_terms=kterms, limiter_jacobian=limjac)
     r = P.assemble(P.line_grid(N), P.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
                    torch.as_tensor(Hel, device=DEV),
                    torch.as_tensor(H0s, dtype=torch.float64, device=DEV), opts,
@@ -98,7 +99,7 @@ def test_line_assembly(gpu, N, kterms):
         R, st = OE.residual(Ps[b], H, ph, lam, h)
         direct_all = OE.hybrid_direct(Ps[b], st["eps"], h)
         direct = direct_all[1:-1]
-        A = -OE.jacobian_band(Ps[b], H, ph, lam, h, kvec, direct, kterms)
+        A = -OE.jacobian_band(Ps[b], H, ph, lam, h, kvec, direct, kterms, limjac)
         rhs = OE.band_matvec(A, Ps[b][1:-1]) + R
         nb = np.concatenate([[True], direct, [True]])
         bounded = (direct & nb[:-2] & nb[2:]).astype(np.uint8)

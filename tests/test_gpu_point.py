@@ -37,14 +37,15 @@ def _state(Nx, Ny, seed):
 @pytest.mark.parametrize("Nx,Ny", [(17, 13), (33, 33)])
 @pytest.mark.parametrize("axis", [0, 1])
 @pytest.mark.parametrize("kterms", [1, 2])
-def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms):
+@pytest.mark.parametrize("limjac", [0, 1])
+def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms, limjac):
     E = gpu.ehl
     Ms, Ls, H0s = [20.0, 200.0], [10.0, 8.0], [-0.5, -0.9]
     X, Y, hx, hy, _ = _state(Nx, Ny, 0)
     Ps = np.stack([_state(Nx, Ny, s)[4] for s in (1, 2)])
     Hel = np.stack([odef.point_deformation(Ps[b], hx, hy) for b in range(2)])
     k2 = odef.point_kernel(Nx, Ny, hx, hy)
-    opts = E.default_opts(kernel_terms=kterms)
+    opts = E.default_opts(kernel_terms=kterms, limiter_jacobian=limjac)
     grid = E.point_grid(Nx, Ny)
     for color in (1, 0):
         g = E.point_sweep_assemble(grid, E.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
@@ -60,7 +61,7 @@ def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms):
             st = OL.state(Ps[b], H, ph, lam)
             direct = OP.classify(Ps[b], st["eps"], hx, hy)
             A, rhs, bounded = OP.sweep_systems(Ps[b], H, st, ph, lam, hx, hy, k2, direct, axis,
-                                               kterms)
+                                               kterms, limjac)
             assert (g["direct"][b] == direct.astype(np.uint8)).all()
             inst = np.abs(A).max()
             for slot, l in enumerate(lines):
@@ -84,7 +85,8 @@ def oracle_33():
 def test_point_newton_matches_oracle(gpu, oracle_33):
     E = gpu.ehl
     o = oracle_33
-    r = E.solve_point([20.0], [10.0], 33, 33, opts=E.default_opts(tol=1e-12, max_newton=1500))
+    r = E.solve_point([20.0], [10.0], 33, 33,
+                      opts=E.default_opts(tol=1e-12, max_newton=1500, c_h0=0.02))
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 0
     P = r["P"][0].cpu().numpy()
@@ -98,7 +100,8 @@ def test_point_config5_properties(gpu):
     the oracle's residual."""
     E = gpu.ehl
     N = 257
-    r = E.solve_point([200.0], [10.0], N, N, opts=E.default_opts(tol=1e-10, max_newton=6000))
+    r = E.solve_point([200.0], [10.0], N, N,
+                      opts=E.default_opts(tol=1e-10, max_newton=30000, c_h0=0.02))
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 0, (int(r["status"][0]), int(r["iters"][0]))
     P = r["P"][0].cpu().numpy()

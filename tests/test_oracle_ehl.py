@@ -134,7 +134,7 @@ def test_band_jacobian_matches_finite_differences(kterms):
             if abs(m - k) <= kterms:
                 T[m, k] = KD[m, k]
     Jfd = _fd_sigma_jacobian(P, H, ph, lam, h, D, T)
-    J = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms)
+    J = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac=0)
     Jd = np.zeros((n, n))
     for r in range(n):
         for s in range(-4, 5):
