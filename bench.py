@@ -46,6 +46,25 @@ def cpu_baseline(batches, sample, nthreads):
     return solves / t_total
 
 
+def measured_traffic(kernel_q):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "paqif_lcp_q8_hbm_counters.md")
+    if kernel_q != 8 or not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_val = re.search(r"traffic_bytes_per_launch_q8_fp64:\s*([0-9.eE+]+)", txt)
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    if not (m_val and m_sha):
+        return None
+    h = hashlib.sha256()
+    for f in ("paqif.hip", "common.h", "paqif_args.h"):
+        h.update(open(os.path.join(ROOT, "paper_2008_03276_amd", "csrc", f), "rb").read())
+    return float(m_val.group(1)) if h.hexdigest() == m_sha.group(1) else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -94,7 +113,7 @@ def ehl_legs(P, torch, synth, dev, args):
     if not args.no_adjoint:
         out["adjoint_N2049"] = adjoint_leg(P, torch, synth, args)
     if not args.no_point:
-        out["point_257"] = point_leg(P, torch, args)
+        out[f"point_{args.point_n}"] = point_leg(P, torch, args)
     return out
 
 
@@ -139,14 +158,15 @@ def adjoint_leg(P, torch, synth, args):
 
 
 def point_leg(P, torch, args):
-    """Point contact: 257 x 257 nodes on [-4.5, 1.5] x [-3, 3], M = 200,
+    """Point contact: n x n nodes (257 by default) on [-4.5, 1.5] x [-3, 3], M = 200,
     L = 10, load 2 pi/3; alternating two-colour x/y line sweeps to
     max |dP| <= 1e-10 per step; time to solution."""
     import time as _t
     opts = P.ehl.default_opts(tol=1e-10, max_newton=30000, c_h0=0.02)
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
-    r = P.ehl.solve_point([200.0], [10.0], 257, 257, opts=opts)
+    n = args.point_n
+    r = P.ehl.solve_point([200.0], [10.0], n, n, opts=opts)
     torch.cuda.synchronize()
     dt = _t.perf_counter() - t0
     steps = int(r["iters"][0])
@@ -173,6 +193,10 @@ def main():
     ap.add_argument("--no-point", action="store_true")
     ap.add_argument("--rough-amp", type=float, default=0.005,
                     help="roughness amplitude of the adjoint leg")
+    ap.add_argument("--point-n", type=int, default=257,
+                    help="nodes per side of the point-contact leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 256 MiB device copy (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "
@@ -184,6 +208,15 @@ def main():
     import synth
     import paper_2008_03276_amd as P
 
+    if args.copy_calibration:
+        # 2^25 doubles read and written once by torch's copy kernel
+        src = torch.rand(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 8}))
+        return
     P.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -279,9 +312,15 @@ def main():
     ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
 
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
+    tr = measured_traffic(dom)
     roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"paqif_lcp_kernel<{dom},double>")
+                unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
+                traffic=None if tr is None else round(tr / 1e9, 3),
+                kernel=f"paqif_lcp_kernel<{dom},double>",
+                algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
+    if tr is not None:
+        roof["traffic_unit"] = "GB per launch (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)"
+        roof["measured_hbm_gbs"] = round(tr / (per_q[dom]["avg_ms"] / 1e3) / 1e9, 2)
 
     log(f"LCP mixed: {ms_mixed:.2f} ms/step")
     cpu = None
