@@ -357,7 +357,9 @@ static void band_residual(int64_t n, int q, const double *band, const double *u,
  * mode OR_LINEAR: u = A^{-1} f (no projection).
  * mode OR_CLIP:   u = max(0, A^{-1} f) on bounded rows (projection of the
  *                 linear solve, the literal PAQIF step).
- * mode OR_EXACT:  primal-dual active set.  A_0 = {} ; solve with the rows
+ * mode OR_EXACT:  primal-dual active set.  A_0 = {bounded i : f_i <= 0}
+ *                 (the sign of f predicts the active constraints of a
+ *                 diagonally dominant system); solve with the rows
  *                 and columns of A_k replaced by the identity and f = 0
  *                 there; w = A u - f;
  *                 A_{k+1} = {i in A_k : w_i > 0} u {i not in A_k : u_i < 0}
@@ -376,6 +378,8 @@ int or_lcp_solve(int64_t n, int q, const double *band, const double *f, const ui
     int it = 0;
     if (mode == OR_EXACT) {
         st = OR_LCP_NOT_CONVERGED;
+        for (int64_t i = 0; i < n; i++)
+            act[i] = (uint8_t)((bounded ? bounded[i] != 0 : 1) && f[i] <= 0.0);
         while (it < max_iter) {
             int s2 = or_aqif_solve(n, q, band, act, f, u);
             it++;

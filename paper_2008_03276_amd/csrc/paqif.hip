@@ -187,13 +187,32 @@ PQ_DEV double level_extra(const SysView& v, GLB_PTR(const double) rhs, bool fuse
     const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
     const int g1 = p1k - Q, g2 = p2k + Q;
     switch (e) {
-    case 0: return aeff<Q>(v, p1k, g1);
-    case 1: return aeff<Q>(v, g1, p1k);
-    case 2: return aeff<Q>(v, p2k, g2);
-    case 3: return aeff<Q>(v, g2, p2k);
+    case 0: return aeff_sel<Q>(v, p1k, g1);
+    case 1: return aeff_sel<Q>(v, g1, p1k);
+    case 2: return aeff_sel<Q>(v, p2k, g2);
+    case 3: return aeff_sel<Q>(v, g2, p2k);
     case 4: return fused ? beff(v, rhs, g1) : 0.0;
     default: return fused ? beff(v, rhs, g2) : 0.0;
     }
+}
+
+// aeff without branches for a live system (n >= 1): the address is clamped
+// into the system so the load is always valid, then out-of-band and pinned
+// entries are selected away.
+template <int Q>
+PQ_DEV double aeff_sel(const SysView& v, int i, int j)
+{
+    const int d = j - i;
+    const bool in = (i >= 0) & (j >= 0) & (i < v.n) & (j < v.n) & (d >= -Q) & (d <= Q);
+    const int nm = v.n > 0 ? v.n - 1 : 0;
+    const int ic = min(max(i, 0), nm), jc = min(max(j, 0), nm);
+    const int dc = min(max(d + Q, 0), 2 * Q);
+    double val = v.band[(int64_t)ic * (2 * Q + 1) + dc];
+    if (v.pin) {  // uniform
+        const bool pinned = (v.pin[ic] | v.pin[jc]) != 0;
+        val = pinned ? (i == j ? 1.0 : 0.0) : val;
+    }
+    return in ? val : 0.0;
 }
 
 // New entry of element (a, b) at level k (pivot slot j = (k-1) mod q).
@@ -202,7 +221,7 @@ PQ_DEV double level_new(const SysView& v, int k, int a, int b)
 {
     const int j = (k - 1) & (Q - 1);
     const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
-    return aeff<Q>(v, slot_index_post<Q>(a, j, p1k, p2k), slot_index_post<Q>(b, j, p1k, p2k));
+    return aeff_sel<Q>(v, slot_index_post<Q>(a, j, p1k, p2k), slot_index_post<Q>(b, j, p1k, p2k));
 }
 
 template <int Q, int L, typename FT, bool STORE_W, bool FUSED>
@@ -214,6 +233,8 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
     constexpr int N2 = G::N2;
     constexpr int TR = G::TR;
     constexpr int TC = G::TC;
+    constexpr int RLEN = 4 * Q + 6;                    // record without W0
+    constexpr int RPL = (RLEN + G::LPS - 1) / G::LPS;  // record elements per lane
     const int ta = ls / G::CT, tb = ls % G::CT;
     int a[TR], jr[TR], b[TC], jc[TC];
 #pragma unroll
@@ -336,10 +357,13 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             if (e < 6 * SB) lX[e] = nX[x];
         }
         load_super(kb + SB);
+        // blocks of the superblock unrolled (their prefetched registers are
+        // indexed at compile time); the q levels of a block are a real loop
 #pragma unroll
-        for (int jj = 0; jj < SB; jj++) {
-            const int j = jj % Q;        // pivot slot
-            const int sb = jj / Q;       // block within the superblock
+        for (int sb = 0; sb < S; sb++)
+#pragma unroll 1
+        for (int j = 0; j < Q; j++) {    // pivot slot
+            const int jj = sb * Q + j;   // level within the superblock
             const int k = kb + jj + 1;  // level number (1-based)
             if (k > kmax) break;
             const bool act = live && (k <= v.npair);
@@ -370,6 +394,13 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             }
             const FT E0 = lX[6 * jj + 0], E1 = lX[6 * jj + 1], E2 = lX[6 * jj + 2];
             const FT E3 = lX[6 * jj + 3], E4 = lX[6 * jj + 4], E5 = lX[6 * jj + 5];
+            // frontier rows j and q+j as published (the record's Z0 rows)
+            FT rraw[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r++) {
+                const int e = ls + r * G::LPS;
+                rraw[r] = e < N2 ? lF[j * N2 + e] : (e < 2 * N2 ? lF[(Q + j) * N2 + e - N2] : (FT)0);
+            }
             wave_sync();
 
             const FT det = P11 * P22 - P12 * P21;
@@ -377,26 +408,24 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             const FT rd = (FT)1 / det;
             const FT i11 = P22 * rd, i12 = -P12 * rd, i21 = -P21 * rd, i22 = P11 * rd;
 
-            // record: Z0 rows p1, p2 over the slots after this level
+            // record: Z0 rows p1, p2 over the slots after this level, the
+            // inverse pivot and the forward values; one element per lane
             if (act) {
 #pragma unroll
-                for (int u = 0; u < TR; u++)
-#pragma unroll
-                    for (int w = 0; w < TC; w++) {
-                        if (a[u] == j)
-                            rec[b[w]] =
-                                (b[w] == j) ? E0 : ((b[w] == Q + j) ? (FT)0 : f[u][w]);
-                        if (a[u] == Q + j)
-                            rec[N2 + b[w]] =
-                                (b[w] == j) ? (FT)0 : ((b[w] == Q + j) ? E2 : f[u][w]);
+                for (int r = 0; r < RPL; r++) {
+                    const int e = ls + r * G::LPS;
+                    const int col = e < N2 ? e : e - N2;
+                    FT val;
+                    if (e < N2)
+                        val = col == j ? E0 : (col == Q + j ? (FT)0 : rraw[r]);
+                    else if (e < 2 * N2)
+                        val = col == j ? (FT)0 : (col == Q + j ? E2 : rraw[r]);
+                    else {
+                        const int t = e - 2 * N2;
+                        val = t == 0 ? i11 : t == 1 ? i12 : t == 2 ? i21 : t == 3 ? i22
+                                                                            : t == 4 ? y1 : y2;
                     }
-                if (ls == 0) {
-                    rec[4 * Q + 0] = i11;
-                    rec[4 * Q + 1] = i12;
-                    rec[4 * Q + 2] = i21;
-                    rec[4 * Q + 3] = i22;
-                    rec[4 * Q + 4] = y1;
-                    rec[4 * Q + 5] = y2;
+                    if (e < RLEN) rec[e] = val;
                 }
             }
 
@@ -538,9 +567,9 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
         }
         wave_sync();
         load_block(kb - SB);
-#pragma unroll
+#pragma unroll 1
         for (int jj = SB - 1; jj >= 0; jj--) {
-            const int j = jj % Q;
+            const int j = jj & (Q - 1);
             const int k = kb + jj + 1;
             if (k > kmax) continue;
             const bool act = live && (k <= v.npair);
@@ -554,18 +583,17 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
             const double r1 = y1 - s1, r2 = y2 - s2;
             const double x1 = i11 * r1 + i12 * r2;
             const double x2 = i21 * r1 + i22 * r2;
-            if (act) {
-                if (c == j && mine) xs = x1;
-                if (c == Q + j && mine) xs = x2;
-                const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
-                if (ls == 0) {
-                    if (ADD) {
-                        x[p1k] += x1;
-                        x[p2k] += x2;
-                    } else {
-                        x[p1k] = x1;
-                        x[p2k] = x2;
-                    }
+            xs = (act && c == j) ? x1 : ((act && c == Q + j) ? x2 : xs);
+            if (j == 0) {
+                // block of q levels done: lane c (< 2q) holds the unknown of
+                // slot c for the block's level kc; one store per block
+                const int kc = kb + jj + (c & (Q - 1)) + 1;
+                if (mine && live && kc <= v.npair) {
+                    const int g = c < Q ? v.P1_0 - (kc - 1) : v.P2_0 + (kc - 1);
+                    if (ADD)
+                        x[g] += xs;
+                    else
+                        x[g] = xs;
                 }
             }
         }
@@ -707,12 +735,17 @@ __global__ void __launch_bounds__(64)
     constexpr int stride = MIXED ? (G::ZREC + G::WREC) : G::ZREC;
     GLB_PTR(FT) rec = GLB(FT, reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride);
 
-    // clear the working active set
+    const bool exact = A.mode == LCP_EXACT;
+    // working active set: exact mode starts from A_0 = {bounded i : b_i <= 0}
+    // (the sign of b predicts the binding constraints of a diagonally
+    // dominant system); the other modes start empty
     if (live)
-        for (int i = ls; i < v.n; i += G::LPS) A.act[off + i] = 0;
+        for (int i = ls; i < v.n; i += G::LPS) {
+            const bool bnd = A.bounded ? A.bounded[off + i] != 0 : true;
+            A.act[off + i] = (exact && bnd && A.b[off + i] <= 0.0) ? 1 : 0;
+        }
     __syncthreads();
 
-    const bool exact = A.mode == LCP_EXACT;
     const int max_it = exact ? max(A.max_iter, 1) : 1;
     int st = SYS_OK;
     int it = 0;
