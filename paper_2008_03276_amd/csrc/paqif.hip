@@ -69,7 +69,7 @@ struct Geo {
     static constexpr int CT = N2 / TC;         // column tiles per tile row
     static constexpr int S = Q == 8 ? 1 : 16 / Q;  // blocks of q levels per prefetch superblock
     static constexpr int SB = S * Q;               // levels per superblock
-    static constexpr int WPE = SPW == 1 ? 4 : (SPW == 2 ? 2 : 1);
+    static constexpr int WPE = SPW == 1 ? 2 : (SPW == 2 ? 2 : 1);
     static constexpr int BW = 2 * Q + 1;       // band width
     static constexpr int ZREC = 4 * Q + 6;     // record without W0
     static constexpr int WREC = 4 * Q;         // W0 part of a record
@@ -150,6 +150,16 @@ PQ_DEV double beff(const SysView& v, GLB_PTR(const double) rhs, int i)
     return rhs[i];
 }
 
+// beff without branches (clamped address, then selects)
+PQ_DEV double beff_sel(const SysView& v, GLB_PTR(const double) rhs, int i)
+{
+    const bool in = (i >= 0) & (i < v.n);
+    const int ic = min(max(i, 0), v.n > 0 ? v.n - 1 : 0);
+    double val = rhs[ic];
+    if (v.pin) val = v.pin[ic] ? 0.0 : val;
+    return in ? val : 0.0;
+}
+
 // Global index held by frontier slot c after level k (pivot slot j).
 template <int Q>
 PQ_DEV int slot_index_post(int c, int j, int p1k, int p2k)
@@ -191,8 +201,8 @@ PQ_DEV double level_extra(const SysView& v, GLB_PTR(const double) rhs, bool fuse
     case 1: return aeff_sel<Q>(v, g1, p1k);
     case 2: return aeff_sel<Q>(v, p2k, g2);
     case 3: return aeff_sel<Q>(v, g2, p2k);
-    case 4: return fused ? beff(v, rhs, g1) : 0.0;
-    default: return fused ? beff(v, rhs, g2) : 0.0;
+    case 4: return fused ? beff_sel(v, rhs, g1) : 0.0;
+    default: return fused ? beff_sel(v, rhs, g2) : 0.0;
     }
 }
 
@@ -233,8 +243,7 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
     constexpr int N2 = G::N2;
     constexpr int TR = G::TR;
     constexpr int TC = G::TC;
-    constexpr int RLEN = 4 * Q + 6;                    // record without W0
-    constexpr int RPL = (RLEN + G::LPS - 1) / G::LPS;  // record elements per lane
+    constexpr int RPL = (2 * N2 + G::LPS - 1) / G::LPS;  // Z0 record elements per lane
     const int ta = ls / G::CT, tb = ls % G::CT;
     int a[TR], jr[TR], b[TC], jc[TC];
 #pragma unroll
@@ -322,19 +331,18 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
 #pragma unroll
                 for (int w = 0; w < TC; w++) {
                     const int kr = kn + sb * Q + jr[u] + 1, kc = kn + sb * Q + jc[w] + 1;
-                    nR[sb][u][w] =
-                        (FT)((live && kr <= v.npair) ? level_new<Q>(v, kr, a[u], b[w]) : 0.0);
-                    nC[sb][u][w] = (FT)((live && kc <= v.npair && jc[w] != jr[u])
-                                            ? level_new<Q>(v, kc, a[u], b[w])
-                                            : 0.0);
+                    // loads from clamped (valid) addresses, then selects
+                    const double vr = level_new<Q>(v, kr, a[u], b[w]);
+                    const double vc = level_new<Q>(v, kc, a[u], b[w]);
+                    nR[sb][u][w] = (FT)((live && kr <= v.npair) ? vr : 0.0);
+                    nC[sb][u][w] = (FT)((live && kc <= v.npair && jc[w] != jr[u]) ? vc : 0.0);
                 }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
             const int kx = kn + e / 6 + 1;
-            nX[x] = (FT)((live && e < 6 * SB && kx <= v.npair)
-                             ? level_extra<Q>(v, rhs, FUSED, kx, e % 6)
-                             : 0.0);
+            const double vx = level_extra<Q>(v, rhs, FUSED, kx, e % 6);
+            nX[x] = (FT)((live && e < 6 * SB && kx <= v.npair) ? vx : 0.0);
         }
     };
     load_super(0);
@@ -394,12 +402,14 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             }
             const FT E0 = lX[6 * jj + 0], E1 = lX[6 * jj + 1], E2 = lX[6 * jj + 2];
             const FT E3 = lX[6 * jj + 3], E4 = lX[6 * jj + 4], E5 = lX[6 * jj + 5];
-            // frontier rows j and q+j as published (the record's Z0 rows)
+            // frontier rows j and q+j as published (the record's Z0 rows);
+            // element e < 2 N2 of the record reads row (e < N2 ? j : q+j)
             FT rraw[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; r++) {
                 const int e = ls + r * G::LPS;
-                rraw[r] = e < N2 ? lF[j * N2 + e] : (e < 2 * N2 ? lF[(Q + j) * N2 + e - N2] : (FT)0);
+                const int row = (e & N2) ? Q + j : j;  // valid address for every lane
+                rraw[r] = lF[row * N2 + (e & (N2 - 1))];
             }
             wave_sync();
 
@@ -414,18 +424,21 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
 #pragma unroll
                 for (int r = 0; r < RPL; r++) {
                     const int e = ls + r * G::LPS;
-                    const int col = e < N2 ? e : e - N2;
-                    FT val;
-                    if (e < N2)
-                        val = col == j ? E0 : (col == Q + j ? (FT)0 : rraw[r]);
-                    else if (e < 2 * N2)
-                        val = col == j ? (FT)0 : (col == Q + j ? E2 : rraw[r]);
-                    else {
-                        const int t = e - 2 * N2;
-                        val = t == 0 ? i11 : t == 1 ? i12 : t == 2 ? i21 : t == 3 ? i22
-                                                                            : t == 4 ? y1 : y2;
-                    }
-                    if (e < RLEN) rec[e] = val;
+                    const bool row1 = e < N2;
+                    const int col = e & (N2 - 1);
+                    // Z0 rows: the pivot columns take E0 / E2 and 0
+                    const FT at_j = row1 ? E0 : (FT)0;
+                    const FT at_qj = row1 ? (FT)0 : E2;
+                    const FT zval = col == j ? at_j : (col == Q + j ? at_qj : rraw[r]);
+                    if (e < 2 * N2) rec[e] = zval;
+                }
+                if (ls == 0) {
+                    rec[4 * Q + 0] = i11;
+                    rec[4 * Q + 1] = i12;
+                    rec[4 * Q + 2] = i21;
+                    rec[4 * Q + 3] = i22;
+                    rec[4 * Q + 4] = y1;
+                    rec[4 * Q + 5] = y2;
                 }
             }
 
@@ -550,12 +563,15 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
     const int64_t lim = live ? (int64_t)v.npair * stride : 0;  // valid elements from recp
 
     FT nb[MAXPL];
+    const int64_t gmax = lim > 0 ? lim - 1 : 0;
     auto load_block = [&](int kb) {
 #pragma unroll
         for (int r = 0; r < MAXPL; r++) {
             const int e = ls + LPS * r;
             const int64_t ge = (int64_t)kb * stride + e;
-            nb[r] = (r < per_lane && e < blk && kb >= 0 && ge < lim) ? recp[ge] : (FT)0;
+            const bool ok = r < per_lane && e < blk && kb >= 0 && ge < lim;
+            const FT val = recp[ge < 0 ? 0 : (ge > gmax ? gmax : ge)];  // valid address
+            nb[r] = ok ? val : (FT)0;
         }
     };
     load_block(kb_last);
