@@ -56,7 +56,7 @@ namespace pq {
 //        L2 2x2 (16 lanes, 4 per wave)
 //   q=8: L0 2x2 (64 lanes, 1 per wave)          L1 2x4 (32 lanes, 2 per wave)
 //        L2 1x4 (64 lanes, 1 per wave)
-constexpr int layout_count(int q) { return q == 2 ? 2 : 3; }
+constexpr int layout_count(int q) { return 3; }  // q = 2: layout 2 is one system per lane
 
 template <int Q, int L>
 struct Geo {
@@ -109,10 +109,28 @@ struct SysView {
     GLB_PTR(const double) rhs;
 };
 
+// Zero block that an empty system's view points at: the prefetch loads from
+// clamped addresses unconditionally, and an empty system (or a lane without
+// a system) has no element of its own to clamp to (its offset may equal the
+// array length).  Indices stay below 2q+1 <= 17.
+__device__ const double kZeroBand[32] = {};
+__device__ const uint8_t kZeroFlags[32] = {};
+
 PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8_t* pin,
                          const double* rhs, int bw)
 {
     SysView v;
+    if (n <= 0) {
+        v.n = 0;
+        v.npair = 0;
+        v.odd = false;
+        v.P1_0 = -1;
+        v.P2_0 = 0;
+        v.band = GLB(const double, kZeroBand);
+        v.pin = pin ? GLB(const uint8_t, kZeroFlags) : nullptr;
+        v.rhs = rhs ? GLB(const double, kZeroBand) : nullptr;
+        return v;
+    }
     v.n = (int)n;
     v.odd = (n & 1) != 0;
     if (v.odd) {
@@ -935,6 +953,299 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
 }
 
 // --------------------------------------------------------------------------
+// One system per lane (small q): the whole 2q x 2q frontier and the
+// right-hand-side column live in the lane's registers, so a level needs no
+// LDS exchange and no cross-lane step; 64 systems per wave.  Same records,
+// active-set rule and outputs as paqif_lcp_kernel in FP64.
+// --------------------------------------------------------------------------
+template <int Q>
+struct LaneLevel {  // values entering the frontier at one level
+    double nw[2 * Q][2 * Q];  // new entries of refilled elements (others unused)
+    double e[6];              // the level's six extras
+};
+
+// element (a, b) is refilled (takes a new band entry) at pivot slot j
+template <int Q>
+PQ_DEV constexpr bool lane_refill(int a, int b, int j)
+{
+    return (a & (Q - 1)) == j || (b & (Q - 1)) == j;
+}
+
+template <int Q>
+PQ_DEV void lane_load_level(const SysView& v, bool live, int k, int j, LaneLevel<Q>& L)
+{
+    constexpr int N2 = 2 * Q;
+    const bool ok = live && k <= v.npair;
+#pragma unroll
+    for (int a = 0; a < N2; a++)
+#pragma unroll
+        for (int b = 0; b < N2; b++)
+            if (lane_refill<Q>(a, b, j)) {
+                const double val = level_new<Q>(v, k, a, b);
+                L.nw[a][b] = ok ? val : 0.0;
+            }
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        const double val = level_extra<Q>(v, v.rhs, true, k, e);
+        L.e[e] = ok ? val : 0.0;
+    }
+}
+
+template <int Q>
+PQ_DEV bool lane_factor(const SysView& v, bool live, GLB_PTR(double) rec)
+{
+    constexpr int N2 = 2 * Q, ZR = 4 * Q + 6;
+    double F[N2][N2], y[N2];
+    bool bad = false;
+    if (v.odd) {
+        const int m = v.npair;
+        const double amm = live ? aeff<Q>(v, m, m) : 1.0;
+        if (live && !(amm != 0.0 && isfinite(amm))) bad = true;
+        const double ramm = 1.0 / amm;
+        const double bm = live ? beff(v, v.rhs, m) : 0.0;
+        double amb[N2];
+#pragma unroll
+        for (int b = 0; b < N2; b++) amb[b] = aeff<Q>(v, m, slot_index_init<Q>(b, v));
+#pragma unroll
+        for (int a = 0; a < N2; a++) {
+            const int ia = slot_index_init<Q>(a, v);
+            const double aim = aeff<Q>(v, ia, m) * ramm;
+#pragma unroll
+            for (int b = 0; b < N2; b++)
+                F[a][b] = aeff<Q>(v, ia, slot_index_init<Q>(b, v)) - aim * amb[b];
+            y[a] = beff(v, v.rhs, ia) - aim * bm;
+        }
+        if (live) {
+#pragma unroll
+            for (int b = 0; b < N2; b++) {
+                rec[b] = amb[b];
+                rec[N2 + b] = 0.0;
+            }
+            rec[4 * Q + 0] = ramm;
+            rec[4 * Q + 1] = 0.0;
+            rec[4 * Q + 2] = 0.0;
+            rec[4 * Q + 3] = 0.0;
+            rec[4 * Q + 4] = bm;
+            rec[4 * Q + 5] = 0.0;
+        }
+        rec += ZR;
+    } else {
+#pragma unroll
+        for (int a = 0; a < N2; a++) {
+            const int ia = slot_index_init<Q>(a, v);
+#pragma unroll
+            for (int b = 0; b < N2; b++) F[a][b] = live ? aeff<Q>(v, ia, slot_index_init<Q>(b, v)) : 0.0;
+            y[a] = live ? beff(v, v.rhs, ia) : 0.0;
+        }
+    }
+    // the values of a block of q levels are loaded one block ahead
+    LaneLevel<Q> nxt[Q];
+#pragma unroll
+    for (int j = 0; j < Q; j++) lane_load_level<Q>(v, live, j + 1, j, nxt[j]);
+    const int np = live ? v.npair : 0;
+    for (int kb = 0; kb < np; kb += Q) {
+        LaneLevel<Q> cur[Q];
+#pragma unroll
+        for (int j = 0; j < Q; j++) cur[j] = nxt[j];
+#pragma unroll
+        for (int j = 0; j < Q; j++) lane_load_level<Q>(v, live, kb + Q + j + 1, j, nxt[j]);
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            const int k = kb + j + 1;
+            if (k > np) break;
+            const LaneLevel<Q>& L = cur[j];
+            const double P11 = F[j][j], P12 = F[j][Q + j], P21 = F[Q + j][j],
+                         P22 = F[Q + j][Q + j];
+            const double y1 = y[j], y2 = y[Q + j];
+            const double det = P11 * P22 - P12 * P21;
+            if (!(det != 0.0 && isfinite(det))) bad = true;
+            const double rd = 1.0 / det;
+            const double i11 = P22 * rd, i12 = -P12 * rd, i21 = -P21 * rd, i22 = P11 * rd;
+            // record: Z0 rows p1, p2 over the slots after this level
+            double cA[N2], cB[N2];
+#pragma unroll
+            for (int b = 0; b < N2; b++) {
+                cA[b] = b == j ? L.e[0] : (b == Q + j ? 0.0 : F[j][b]);
+                cB[b] = b == j ? 0.0 : (b == Q + j ? L.e[2] : F[Q + j][b]);
+                rec[b] = cA[b];
+                rec[N2 + b] = cB[b];
+            }
+            rec[4 * Q + 0] = i11;
+            rec[4 * Q + 1] = i12;
+            rec[4 * Q + 2] = i21;
+            rec[4 * Q + 3] = i22;
+            rec[4 * Q + 4] = y1;
+            rec[4 * Q + 5] = y2;
+            double w1[N2], w2[N2];
+#pragma unroll
+            for (int a = 0; a < N2; a++) {
+                if (a == j) {
+                    w1[a] = L.e[1] * i11;
+                    w2[a] = L.e[1] * i12;
+                } else if (a == Q + j) {
+                    w1[a] = L.e[3] * i21;
+                    w2[a] = L.e[3] * i22;
+                } else {
+                    w1[a] = F[a][j] * i11 + F[a][Q + j] * i21;
+                    w2[a] = F[a][j] * i12 + F[a][Q + j] * i22;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < N2; a++) {
+#pragma unroll
+                for (int b = 0; b < N2; b++) {
+                    const double base = lane_refill<Q>(a, b, j) ? L.nw[a][b] : F[a][b];
+                    F[a][b] = base - (w1[a] * cA[b] + w2[a] * cB[b]);
+                }
+                const double yb = a == j ? L.e[4] : (a == Q + j ? L.e[5] : y[a]);
+                y[a] = yb - (w1[a] * y1 + w2[a] * y2);
+            }
+            rec += ZR;
+        }
+    }
+    return bad;
+}
+
+template <int Q>
+PQ_DEV void lane_back(const SysView& v, bool live, GLB_PTR(const double) rec0,
+                      GLB_PTR(double) x)
+{
+    constexpr int N2 = 2 * Q, ZR = 4 * Q + 6;
+    if (!live) return;
+    double xs[N2];
+#pragma unroll
+    for (int c = 0; c < N2; c++) xs[c] = 0.0;
+    GLB_PTR(const double) recp = rec0 + (v.odd ? ZR : 0);
+    const int np = v.npair;
+    const int kb_last = np > 0 ? ((np - 1) / Q) * Q : -Q;
+    double nb[Q][ZR];
+    auto load = [&](int kb) {
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            const int k = kb + j + 1;
+            const int kc = k < 1 ? 1 : (k > np ? np : k);  // valid record
+#pragma unroll
+            for (int t = 0; t < ZR; t++) nb[j][t] = recp[(int64_t)(kc - 1) * ZR + t];
+        }
+    };
+    if (np > 0) load(kb_last);
+    for (int kb = kb_last; kb >= 0; kb -= Q) {
+        double cur[Q][ZR];
+#pragma unroll
+        for (int j = 0; j < Q; j++)
+#pragma unroll
+            for (int t = 0; t < ZR; t++) cur[j][t] = nb[j][t];
+        if (kb - Q >= 0) load(kb - Q);
+#pragma unroll
+        for (int j = Q - 1; j >= 0; j--) {
+            const int k = kb + j + 1;
+            if (k > np) continue;
+            const double* r = cur[j];
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < N2; c++) {
+                s1 += r[c] * xs[c];
+                s2 += r[N2 + c] * xs[c];
+            }
+            const double r1 = r[4 * Q + 4] - s1, r2 = r[4 * Q + 5] - s2;
+            const double x1 = r[4 * Q + 0] * r1 + r[4 * Q + 1] * r2;
+            const double x2 = r[4 * Q + 2] * r1 + r[4 * Q + 3] * r2;
+            xs[j] = x1;
+            xs[Q + j] = x2;
+            x[v.P1_0 - (k - 1)] = x1;
+            x[v.P2_0 + (k - 1)] = x2;
+        }
+    }
+    if (v.odd) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < N2; c++) s += rec0[c] * xs[c];
+        x[v.npair] = rec0[4 * Q] * (rec0[4 * Q + 4] - s);
+    }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
+{
+    constexpr int BW = 2 * Q + 1, ZR = 4 * Q + 6;
+    const int slot = blockIdx.x * 64 + threadIdx.x;
+    bool live = slot < A.count;
+    const int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    if (live && A.skip && A.skip[sys]) live = false;
+    const int64_t off = live ? A.offsets[sys] : 0;
+    const int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    SysView v = make_view(off, n, A.band, A.act, A.b, BW);
+    if (!live) {
+        v.n = 0;
+        v.npair = 0;
+    }
+    GLB_PTR(double) rec = GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * ZR);
+    GLB_PTR(double) u = GLB(double, A.u + off);
+    GLB_PTR(const double) bb = GLB(const double, A.b + off);
+    GLB_PTR(const double) band = GLB(const double, A.band + off * BW);
+    GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
+    GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
+    const bool exact = A.mode == LCP_EXACT;
+    // working active set: exact mode starts from {bounded i : b_i <= 0}
+    for (int i = 0; i < v.n; i++) act[i] = (exact && (bnds ? bnds[i] != 0 : true) && bb[i] <= 0.0);
+    const int max_it = exact ? max(A.max_iter, 1) : 1;
+    int st = SYS_OK, it = 0;
+    bool done = !live;
+    while (!done) {
+        const bool bad = lane_factor<Q>(v, true, rec);
+        lane_back<Q>(v, true, rec, u);
+        it++;
+        if (bad) {
+            st = SYS_ZERO_PIVOT;
+            break;
+        }
+        if (A.mode == LCP_CLIP)
+            for (int i = 0; i < v.n; i++)
+                if ((bnds ? bnds[i] != 0 : true) && u[i] < 0.0) {
+                    u[i] = 0.0;
+                    act[i] = 1;
+                }
+        // w = A u - b with the original band; active-set update
+        int changes = 0;
+        bool nonfinite = false;
+        for (int i = 0; i < v.n; i++) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < BW; d++) {
+                const int jc = i + d - Q;
+                if (jc >= 0 && jc < v.n) s += band[(int64_t)i * BW + d] * u[jc];
+            }
+            const double wi = s - bb[i];
+            const double ui = u[i];
+            if (!isfinite(ui)) nonfinite = true;
+            if (A.w) A.w[off + i] = wi;
+            if (exact) {
+                const int bnd = bnds ? (bnds[i] != 0) : 1;
+                const int cur = act[i];
+                const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
+                changes += nxt != cur;
+                act[i] = (uint8_t)nxt;
+            }
+        }
+        if (nonfinite) {
+            st = SYS_NONFINITE;
+            break;
+        }
+        if (!exact || changes == 0) break;
+        if (it >= max_it) {
+            st = SYS_LCP_NOT_CONVERGED;
+            break;
+        }
+    }
+    if (live) {
+        if (A.active_out)
+            for (int i = 0; i < v.n; i++) A.active_out[off + i] = act[i];
+        A.status[sys] = st;
+        if (A.iters) A.iters[sys] = it;
+    }
+}
+
+// --------------------------------------------------------------------------
 // Host launchers
 // --------------------------------------------------------------------------
 template <int Q, int L>
@@ -955,8 +1266,16 @@ static int launch_lcp(const LcpArgs& a, int prec, int layout, hipStream_t s)
     switch (layout) {
     case 1: return launch_lcp_l<Q, 1>(a, prec, s);
     case 2:
-        if constexpr (layout_count(Q) > 2) return launch_lcp_l<Q, 2>(a, prec, s);
-        return PAQIF_EINVAL;
+        if constexpr (Q == 2) {
+            // one system per lane (FP64; the FP32 + refinement path keeps layout 0)
+            if (prec == PREC_FP32_IR) return launch_lcp_l<Q, 0>(a, prec, s);
+            const int grid = (a.count + 63) / 64;
+            if (grid == 0) return PAQIF_OK;
+            hipLaunchKernelGGL((paqif_lcp_lane_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+            return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+        } else {
+            return launch_lcp_l<Q, 2>(a, prec, s);
+        }
     default: return launch_lcp_l<Q, 0>(a, prec, s);
     }
 }

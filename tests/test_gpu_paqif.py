@@ -188,3 +188,40 @@ def test_autotune_picks_a_layout(gpu):
     assert 0 <= chosen < P.paqif.layout_count(4)
     assert len(times) == P.paqif.layout_count(4) and min(times) > 0
     assert times[chosen] == min(times)
+
+
+@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_q2_layouts_modes_bounded_and_edges(gpu, layout, mode):
+    """Every q = 2 layout (layout 2: one system per lane) in every mode, with a
+    bounded mask, empty and one-row systems and a singular system."""
+    P = gpu
+    dev = torch.device("cuda")
+    sizes = [0, 1, 7, 0, 64, 301, 3, 1000, 2]
+    offs, band, f = synth.lcp_batch(len(sizes), 2, seed=33, sizes=sizes)
+    rng = np.random.default_rng(5)
+    bounded = (rng.random(len(f)) < 0.8).astype(np.uint8)
+    sing = int(offs[6])  # the 3-row system: zero its centre row
+    band[sing + 1, :] = 0.0
+    o = oracle.lcp_batch(2, offs, band, f, mode=mode, bounded=bounded)
+    bt = P.paqif.Batch(offs, 2, order="lpt")
+    keep = P.paqif.get_layout(2, 0)
+    try:
+        P.paqif.set_layout(2, 0, layout)
+        r = P.paqif.solve_lcp(bt, torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev),
+                              mode=mode, bounded=torch.as_tensor(bounded, device=dev))
+        torch.cuda.synchronize()
+    finally:
+        P.paqif.set_layout(2, 0, keep)
+    st = r["status"].cpu().numpy()
+    assert (st == o["status"]).all(), (st, o["status"])
+    u, act, w = r["u"].cpu().numpy(), r["active"].cpu().numpy(), r["w"].cpu().numpy()
+    it = r["iters"].cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        if st[s] != 0 or b == a:
+            continue
+        assert (act[a:b] == o["active"][a:b]).all(), s
+        assert it[s] == o["iters"][s], s
+        assert _relerr(u[a:b], o["u"][a:b]) < 1e-12, s
+        assert np.abs(w[a:b] - o["w"][a:b]).max() <= 1e-12 * max(1.0, np.abs(o["w"][a:b]).max())
