@@ -56,7 +56,8 @@ namespace pq {
 //        L2 2x2 (16 lanes, 4 per wave)
 //   q=8: L0 2x2 (64 lanes, 1 per wave)          L1 2x4 (32 lanes, 2 per wave)
 //        L2 1x4 (64 lanes, 1 per wave)
-constexpr int layout_count(int q) { return 3; }  // q = 2: layout 2 is one system per lane
+// q = 2: layout 2 is one system per lane (its own kernel below)
+constexpr int layout_count(int q) { return 3; }
 
 template <int Q, int L>
 struct Geo {
@@ -243,6 +244,70 @@ PQ_DEV double aeff_sel(const SysView& v, int i, int j)
     return in ? val : 0.0;
 }
 
+// One effective entry split into its raw loads: the band value at a clamped
+// (valid) address and the pin flags of its row and column, with the
+// load-independent part of the selection (inside the matrix and the band, on
+// the diagonal) in `code`.  The consumer applies the selection (ent_value)
+// one superblock later: a select on a freshly loaded value would make the
+// compiler wait for that load on the spot and so serialise the prefetch.
+struct RawEnt {
+    double val;
+    uint32_t pi, pj;
+    uint32_t code;  // bit 0: entry exists, bit 1: diagonal
+};
+
+PQ_DEV double ent_value(const RawEnt& r)
+{
+    const bool pinned = (r.pi | r.pj) != 0u;
+    const double s = pinned ? ((r.code & 2u) ? 1.0 : 0.0) : r.val;
+    return (r.code & 1u) ? s : 0.0;
+}
+
+template <int Q>
+PQ_DEV RawEnt raw_ent(const SysView& v, int i, int j, bool use)
+{
+    RawEnt r;
+    const int d = j - i;
+    const bool in =
+        use & (i >= 0) & (j >= 0) & (i < v.n) & (j < v.n) & (d >= -Q) & (d <= Q);
+    const int nm = v.n > 0 ? v.n - 1 : 0;
+    const int ic = min(max(i, 0), nm), jc = min(max(j, 0), nm);
+    const int dc = min(max(d + Q, 0), 2 * Q);
+    r.val = v.band[(int64_t)ic * (2 * Q + 1) + dc];
+    r.pi = v.pin ? (uint32_t)v.pin[ic] : 0u;
+    r.pj = v.pin ? (uint32_t)v.pin[jc] : 0u;
+    r.code = (in ? 1u : 0u) | (i == j ? 2u : 0u);
+    return r;
+}
+
+// Raw form of level_extra: one load per element, from the band (e < 4) or
+// the right-hand side (e >= 4, pinned rows give 0), chosen by address.
+template <int Q>
+PQ_DEV RawEnt raw_extra(const SysView& v, GLB_PTR(const double) rhs, bool fused, int k, int e,
+                        bool use)
+{
+    const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
+    const bool right = (e == 2) | (e == 3) | (e == 5);
+    const bool swap = (e == 1) | (e == 3);
+    const bool isr = e >= 4;
+    const int p = right ? p2k : p1k, g = right ? p2k + Q : p1k - Q;
+    const int i = (isr | swap) ? g : p, j = (isr | !swap) ? g : p;
+    const int d = j - i;
+    const bool in = use & (!isr | fused) & (i >= 0) & (j >= 0) & (i < v.n) & (j < v.n);
+    const int nm = v.n > 0 ? v.n - 1 : 0;
+    const int ic = min(max(i, 0), nm), jc = min(max(j, 0), nm);
+    const int dc = min(max(d + Q, 0), 2 * Q);
+    const bool from_rhs = isr & fused;
+    GLB_PTR(const double) src = from_rhs ? rhs : v.band;
+    const int64_t idx = from_rhs ? (int64_t)ic : (isr ? 0 : (int64_t)ic * (2 * Q + 1) + dc);
+    RawEnt r;
+    r.val = src[idx];
+    r.pi = v.pin ? (uint32_t)v.pin[ic] : 0u;
+    r.pj = v.pin ? (uint32_t)v.pin[jc] : 0u;
+    r.code = in ? 1u : 0u;  // never diagonal: |d| = q, or a pinned rhs row (0)
+    return r;
+}
+
 // New entry of element (a, b) at level k (pivot slot j = (k-1) mod q).
 template <int Q>
 PQ_DEV double level_new(const SysView& v, int k, int a, int b)
@@ -338,9 +403,9 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
     // superblock of S blocks are loaded one superblock ahead -----------------
     constexpr int S = G::S;
     constexpr int SB = G::SB;
-    FT nR[S][TR][TC], nC[S][TR][TC];
+    RawEnt nR[S][TR][TC], nC[S][TR][TC];
     constexpr int XPL = (6 * SB + G::LPS - 1) / G::LPS;  // extras per lane
-    FT nX[XPL];
+    RawEnt nX[XPL];
     auto load_super = [&](int kn) {
 #pragma unroll
         for (int sb = 0; sb < S; sb++)
@@ -349,18 +414,21 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
 #pragma unroll
                 for (int w = 0; w < TC; w++) {
                     const int kr = kn + sb * Q + jr[u] + 1, kc = kn + sb * Q + jc[w] + 1;
-                    // loads from clamped (valid) addresses, then selects
-                    const double vr = level_new<Q>(v, kr, a[u], b[w]);
-                    const double vc = level_new<Q>(v, kc, a[u], b[w]);
-                    nR[sb][u][w] = (FT)((live && kr <= v.npair) ? vr : 0.0);
-                    nC[sb][u][w] = (FT)((live && kc <= v.npair && jc[w] != jr[u]) ? vc : 0.0);
+                    const int jr0 = (kr - 1) & (Q - 1), jc0 = (kc - 1) & (Q - 1);
+                    const int p1r = v.P1_0 - (kr - 1), p2r = v.P2_0 + (kr - 1);
+                    const int p1c = v.P1_0 - (kc - 1), p2c = v.P2_0 + (kc - 1);
+                    nR[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jr0, p1r, p2r),
+                                              slot_index_post<Q>(b[w], jr0, p1r, p2r),
+                                              live && kr <= v.npair);
+                    nC[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jc0, p1c, p2c),
+                                              slot_index_post<Q>(b[w], jc0, p1c, p2c),
+                                              live && kc <= v.npair && jc[w] != jr[u]);
                 }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
             const int kx = kn + e / 6 + 1;
-            const double vx = level_extra<Q>(v, rhs, FUSED, kx, e % 6);
-            nX[x] = (FT)((live && e < 6 * SB && kx <= v.npair) ? vx : 0.0);
+            nX[x] = raw_extra<Q>(v, rhs, FUSED, kx, e % 6, live && e < 6 * SB && kx <= v.npair);
         }
     };
     load_super(0);
@@ -374,13 +442,13 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             for (int u = 0; u < TR; u++)
 #pragma unroll
                 for (int w = 0; w < TC; w++) {
-                    vR[sb][u][w] = nR[sb][u][w];
-                    vC[sb][u][w] = nC[sb][u][w];
+                    vR[sb][u][w] = (FT)ent_value(nR[sb][u][w]);
+                    vC[sb][u][w] = (FT)ent_value(nC[sb][u][w]);
                 }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
-            if (e < 6 * SB) lX[e] = nX[x];
+            if (e < 6 * SB) lX[e] = (FT)ent_value(nX[x]);
         }
         load_super(kb + SB);
         // blocks of the superblock unrolled (their prefetched registers are
@@ -527,28 +595,55 @@ PQ_DEV void wsolve_system(SysView v, bool live, GLB_PTR(const double) rhs,
     } else if (mine && live) {
         bc = beff(v, rhs, slot_index_init<Q>(c, v));
     }
+    // one block of q levels is loaded a block ahead: the lane's multipliers
+    // of every level and the right-hand side entering its slot (refilled at
+    // j = c mod q), raw from clamped addresses and selected when used
+    GLB_PTR(const double) rb = v.n > 0 ? rhs : GLB(const double, kZeroBand);
+    const int nm = v.n > 0 ? v.n - 1 : 0;
+    const int lastk = v.npair > 0 ? v.npair - 1 : 0;
+    FT nw[Q][2];
+    double nbv;
+    uint32_t npin;
+    auto load_blk = [&](int kb) {
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            const int kk = min(max(kb + j, 0), lastk);  // record index of level kb+j+1
+            const int64_t e = (int64_t)kk * stride + 4 * Q + 6 + 2 * c;
+            nw[j][0] = rec[e];
+            nw[j][1] = rec[e + 1];
+        }
+        const int k = kb + (c & (Q - 1)) + 1;
+        const int g = c < Q ? v.P1_0 - (k - 1) - Q : v.P2_0 + (k - 1) + Q;
+        const int gc = min(max(g, 0), nm);
+        nbv = rb[gc];
+        npin = v.pin ? (uint32_t)v.pin[gc] : 0u;
+    };
+    load_blk(0);
     for (int kb = 0; kb < kmax; kb += Q) {
+        FT cw[Q][2];
+#pragma unroll
+        for (int j = 0; j < Q; j++) {
+            cw[j][0] = nw[j][0];
+            cw[j][1] = nw[j][1];
+        }
+        const int kin = kb + (c & (Q - 1)) + 1;
+        const int gin = c < Q ? v.P1_0 - (kin - 1) - Q : v.P2_0 + (kin - 1) + Q;
+        const double bin = (gin >= 0 && gin < v.n && npin == 0u) ? nbv : 0.0;
+        load_blk(kb + Q);
 #pragma unroll
         for (int j = 0; j < Q; j++) {
             const int k = kb + j + 1;
             if (k > kmax) break;
             const bool act = live && (k <= v.npair);
-            const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
             const double y1 = __shfl(bc, gbase + j);
             const double y2 = __shfl(bc, gbase + Q + j);
-            if (act && mine) {
-                double base = bc;
-                if (c == j) base = beff(v, rhs, p1k - Q);
-                if (c == Q + j) base = beff(v, rhs, p2k + Q);
-                const double w1 = (double)rec[4 * Q + 6 + 2 * c];
-                const double w2 = (double)rec[4 * Q + 6 + 2 * c + 1];
-                bc = base - (w1 * y1 + w2 * y2);
-                if (c == 0) {
-                    rec[4 * Q + 4] = (FT)y1;
-                    rec[4 * Q + 5] = (FT)y2;
-                }
+            const double base = (c == j || c == Q + j) ? bin : bc;
+            const double nb = base - ((double)cw[j][0] * y1 + (double)cw[j][1] * y2);
+            bc = (act && mine) ? nb : bc;
+            if (act && c == 0 && mine) {
+                rec[(int64_t)(k - 1) * stride + 4 * Q + 4] = (FT)y1;
+                rec[(int64_t)(k - 1) * stride + 4 * Q + 5] = (FT)y2;
             }
-            rec += stride;
         }
     }
 }
@@ -580,6 +675,9 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
     const int kb_last = kmax > 0 ? ((kmax - 1) / SB) * SB : -SB;
     const int64_t lim = live ? (int64_t)v.npair * stride : 0;  // valid elements from recp
 
+    // raw loads from clamped (valid) addresses; elements past the records
+    // are zeroed when the block is consumed, so that no select waits on a
+    // load in flight
     FT nb[MAXPL];
     const int64_t gmax = lim > 0 ? lim - 1 : 0;
     auto load_block = [&](int kb) {
@@ -587,9 +685,7 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
         for (int r = 0; r < MAXPL; r++) {
             const int e = ls + LPS * r;
             const int64_t ge = (int64_t)kb * stride + e;
-            const bool ok = r < per_lane && e < blk && kb >= 0 && ge < lim;
-            const FT val = recp[ge < 0 ? 0 : (ge > gmax ? gmax : ge)];  // valid address
-            nb[r] = ok ? val : (FT)0;
+            nb[r] = recp[ge < 0 ? 0 : (ge > gmax ? gmax : ge)];
         }
     };
     load_block(kb_last);
@@ -597,7 +693,8 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
 #pragma unroll
         for (int r = 0; r < MAXPL; r++) {
             const int e = ls + LPS * r;
-            if (r < per_lane && e < blk) lB[e] = nb[r];
+            const bool ok = (int64_t)kb * stride + e < lim;  // kb >= 0 here
+            if (r < per_lane && e < blk) lB[e] = ok ? nb[r] : (FT)0;
         }
         wave_sync();
         load_block(kb - SB);
