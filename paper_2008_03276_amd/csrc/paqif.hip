@@ -778,24 +778,48 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
     GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
     int ch = 0, nf = 0;
+    // R rows per lane per pass; all their loads (clamped, valid addresses)
+    // are issued before any is used, so a pass waits for memory once
+    constexpr int R = BW <= 5 ? 4 : (BW <= 9 ? 2 : 1);
     if (live) {
-        for (int i = ls; i < v.n; i += G::LPS) {
-            double s = 0.0;
+        const int nm = v.n - 1;
+        for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
+            double av[R][BW], uv[R][BW], bv[R];
+            uint32_t cv[R], kv[R];
 #pragma unroll
-            for (int d = 0; d < BW; d++) {
-                const int jcol = i + d - Q;
-                if (jcol >= 0 && jcol < v.n) s += band[(int64_t)i * BW + d] * u[jcol];
+            for (int r = 0; r < R; r++) {
+                const int i = min(i0 + r * G::LPS, nm);
+#pragma unroll
+                for (int d = 0; d < BW; d++) {
+                    av[r][d] = band[(int64_t)i * BW + d];
+                    uv[r][d] = u[min(max(i + d - Q, 0), nm)];
+                }
+                bv[r] = bb[i];
+                cv[r] = act[i];
+                kv[r] = bnds ? (uint32_t)bnds[i] : 1u;
             }
-            const double wi = s - bb[i];
-            const double ui = u[i];
-            if (!isfinite(ui)) nf = 1;
-            if (write_w && wout) wout[i] = wi;
-            if (update) {
-                const int bnd = bnds ? (bnds[i] != 0) : 1;
-                const int cur = act[i];
-                const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
-                ch += (nxt != cur);
-                act[i] = (uint8_t)nxt;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int i = i0 + r * G::LPS;
+                if (i < v.n) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int d = 0; d < BW; d++) {
+                        const int jcol = i + d - Q;
+                        s = __builtin_fma(av[r][d], (jcol >= 0 && jcol < v.n) ? uv[r][d] : 0.0, s);
+                    }
+                    const double wi = s - bv[r];
+                    const double ui = uv[r][Q];
+                    if (!isfinite(ui)) nf = 1;
+                    if (write_w && wout) wout[i] = wi;
+                    if (update) {
+                        const int bnd = kv[r] != 0u;
+                        const int cur = cv[r] != 0u;
+                        const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
+                        ch += (nxt != cur);
+                        act[i] = (uint8_t)nxt;
+                    }
+                }
             }
         }
     }
@@ -813,16 +837,47 @@ PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
     ls = launder(ls);
     using G = Geo<Q, L>;
     double rm = 0.0, bm = 0.0;
+    constexpr int BW = G::BW;
+    constexpr int R = BW <= 5 ? 2 : 1;  // rows per lane per pass, loads issued first
     if (live) {
-        for (int i = ls; i < v.n; i += G::LPS) {
-            double s = 0.0;
+        const int nm = v.n - 1;
+        for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
+            double av[R][BW], uv[R][BW], bv[R];
+            uint32_t pv[R][BW];
 #pragma unroll
-            for (int d = 0; d < G::BW; d++) s += aeff<Q>(v, i, i + d - Q) * ((i + d - Q >= 0 && i + d - Q < v.n) ? u[i + d - Q] : 0.0);
-            const double be = beff(v, bsys, i);
-            const double ri = be - s;
-            r[i] = ri;
-            rm = fmax(rm, fabs(ri));
-            bm = fmax(bm, fabs(be));
+            for (int rr = 0; rr < R; rr++) {
+                const int i = min(i0 + rr * G::LPS, nm);
+#pragma unroll
+                for (int d = 0; d < BW; d++) {
+                    const int jc = min(max(i + d - Q, 0), nm);
+                    av[rr][d] = v.band[(int64_t)i * BW + d];
+                    uv[rr][d] = u[jc];
+                    pv[rr][d] = v.pin ? (uint32_t)v.pin[jc] : 0u;
+                }
+                bv[rr] = bsys[i];
+            }
+#pragma unroll
+            for (int rr = 0; rr < R; rr++) {
+                const int i = i0 + rr * G::LPS;
+                if (i < v.n) {
+                    // pinned rows and columns of A_eff are those of the identity
+                    const bool pin_i = pv[rr][Q] != 0u;
+                    double s = 0.0;
+#pragma unroll
+                    for (int d = 0; d < BW; d++) {
+                        const int jcol = i + d - Q;
+                        const bool in = jcol >= 0 && jcol < v.n;
+                        const double a =
+                            (pin_i || pv[rr][d] != 0u) ? (d == Q ? 1.0 : 0.0) : av[rr][d];
+                        s = __builtin_fma(a, in ? uv[rr][d] : 0.0, s);
+                    }
+                    const double be = pin_i ? 0.0 : bv[rr];
+                    const double ri = be - s;
+                    r[i] = ri;
+                    rm = fmax(rm, fabs(ri));
+                    bm = fmax(bm, fabs(be));
+                }
+            }
         }
     }
 #pragma unroll
