@@ -245,26 +245,27 @@ PQ_DEV double aeff_sel(const SysView& v, int i, int j)
 }
 
 // One effective entry split into its raw loads: the band value at a clamped
-// (valid) address and the pin flags of its row and column, with the
-// load-independent part of the selection (inside the matrix and the band, on
-// the diagonal) in `code`.  The consumer applies the selection (ent_value)
-// one superblock later: a select on a freshly loaded value would make the
-// compiler wait for that load on the spot and so serialise the prefetch.
+// (valid) address and the pin flags of its row and column.  The
+// load-independent part of the selection is a 2-bit code (bit 0: the entry
+// exists, inside the matrix and the band; bit 1: diagonal), packed by the
+// caller into one word per superblock.  The consumer applies the selection
+// (ent_value) one superblock later: a select on a freshly loaded value would
+// make the compiler wait for that load on the spot and so serialise the
+// prefetch.
 struct RawEnt {
     double val;
     uint32_t pi, pj;
-    uint32_t code;  // bit 0: entry exists, bit 1: diagonal
 };
 
-PQ_DEV double ent_value(const RawEnt& r)
+PQ_DEV double ent_value(const RawEnt& r, uint32_t code)
 {
     const bool pinned = (r.pi | r.pj) != 0u;
-    const double s = pinned ? ((r.code & 2u) ? 1.0 : 0.0) : r.val;
-    return (r.code & 1u) ? s : 0.0;
+    const double s = pinned ? ((code & 2u) ? 1.0 : 0.0) : r.val;
+    return (code & 1u) ? s : 0.0;
 }
 
 template <int Q>
-PQ_DEV RawEnt raw_ent(const SysView& v, int i, int j, bool use)
+PQ_DEV RawEnt raw_ent(const SysView& v, int i, int j, bool use, uint32_t& code)
 {
     RawEnt r;
     const int d = j - i;
@@ -276,7 +277,7 @@ PQ_DEV RawEnt raw_ent(const SysView& v, int i, int j, bool use)
     r.val = v.band[(int64_t)ic * (2 * Q + 1) + dc];
     r.pi = v.pin ? (uint32_t)v.pin[ic] : 0u;
     r.pj = v.pin ? (uint32_t)v.pin[jc] : 0u;
-    r.code = (in ? 1u : 0u) | (i == j ? 2u : 0u);
+    code = (in ? 1u : 0u) | (i == j ? 2u : 0u);
     return r;
 }
 
@@ -284,7 +285,7 @@ PQ_DEV RawEnt raw_ent(const SysView& v, int i, int j, bool use)
 // the right-hand side (e >= 4, pinned rows give 0), chosen by address.
 template <int Q>
 PQ_DEV RawEnt raw_extra(const SysView& v, GLB_PTR(const double) rhs, bool fused, int k, int e,
-                        bool use)
+                        bool use, uint32_t& code)
 {
     const int p1k = v.P1_0 - (k - 1), p2k = v.P2_0 + (k - 1);
     const bool right = (e == 2) | (e == 3) | (e == 5);
@@ -304,7 +305,7 @@ PQ_DEV RawEnt raw_extra(const SysView& v, GLB_PTR(const double) rhs, bool fused,
     r.val = src[idx];
     r.pi = v.pin ? (uint32_t)v.pin[ic] : 0u;
     r.pj = v.pin ? (uint32_t)v.pin[jc] : 0u;
-    r.code = in ? 1u : 0u;  // never diagonal: |d| = q, or a pinned rhs row (0)
+    code = in ? 1u : 0u;  // never diagonal: |d| = q, or a pinned rhs row (0)
     return r;
 }
 
@@ -406,7 +407,10 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
     RawEnt nR[S][TR][TC], nC[S][TR][TC];
     constexpr int XPL = (6 * SB + G::LPS - 1) / G::LPS;  // extras per lane
     RawEnt nX[XPL];
+    static_assert(S * TR * TC <= 16 && XPL <= 32, "selection codes fit one word");
+    uint32_t cR, cC, cX;  // selection codes, 2 bits per entry (1 per extra)
     auto load_super = [&](int kn) {
+        cR = cC = cX = 0u;
 #pragma unroll
         for (int sb = 0; sb < S; sb++)
 #pragma unroll
@@ -417,18 +421,25 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
                     const int jr0 = (kr - 1) & (Q - 1), jc0 = (kc - 1) & (Q - 1);
                     const int p1r = v.P1_0 - (kr - 1), p2r = v.P2_0 + (kr - 1);
                     const int p1c = v.P1_0 - (kc - 1), p2c = v.P2_0 + (kc - 1);
+                    const int sh = 2 * ((sb * TR + u) * TC + w);
+                    uint32_t code;
                     nR[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jr0, p1r, p2r),
                                               slot_index_post<Q>(b[w], jr0, p1r, p2r),
-                                              live && kr <= v.npair);
+                                              live && kr <= v.npair, code);
+                    cR |= code << sh;
                     nC[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jc0, p1c, p2c),
                                               slot_index_post<Q>(b[w], jc0, p1c, p2c),
-                                              live && kc <= v.npair && jc[w] != jr[u]);
+                                              live && kc <= v.npair && jc[w] != jr[u], code);
+                    cC |= code << sh;
                 }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
             const int kx = kn + e / 6 + 1;
-            nX[x] = raw_extra<Q>(v, rhs, FUSED, kx, e % 6, live && e < 6 * SB && kx <= v.npair);
+            uint32_t code;
+            nX[x] = raw_extra<Q>(v, rhs, FUSED, kx, e % 6, live && e < 6 * SB && kx <= v.npair,
+                                 code);
+            cX |= code << x;
         }
     };
     load_super(0);
@@ -442,24 +453,25 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
             for (int u = 0; u < TR; u++)
 #pragma unroll
                 for (int w = 0; w < TC; w++) {
-                    vR[sb][u][w] = (FT)ent_value(nR[sb][u][w]);
-                    vC[sb][u][w] = (FT)ent_value(nC[sb][u][w]);
+                    const int sh = 2 * ((sb * TR + u) * TC + w);
+                    vR[sb][u][w] = (FT)ent_value(nR[sb][u][w], (cR >> sh) & 3u);
+                    vC[sb][u][w] = (FT)ent_value(nC[sb][u][w], (cC >> sh) & 3u);
                 }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
-            if (e < 6 * SB) lX[e] = (FT)ent_value(nX[x]);
+            if (e < 6 * SB) lX[e] = (FT)ent_value(nX[x], (cX >> x) & 1u);
         }
         load_super(kb + SB);
-        // blocks of the superblock unrolled (their prefetched registers are
-        // indexed at compile time); the q levels of a block are a real loop
+        // the whole superblock is unrolled (prefetched registers and LDS
+        // offsets are compile-time); a wave runs whole superblocks, levels
+        // past a system's last one compute on zeros and store nothing
 #pragma unroll
         for (int sb = 0; sb < S; sb++)
-#pragma unroll 1
+#pragma unroll
         for (int j = 0; j < Q; j++) {    // pivot slot
             const int jj = sb * Q + j;   // level within the superblock
             const int k = kb + jj + 1;  // level number (1-based)
-            if (k > kmax) break;
             const bool act = live && (k <= v.npair);
 
             // publish the tile and the rhs column
@@ -633,7 +645,6 @@ PQ_DEV void wsolve_system(SysView v, bool live, GLB_PTR(const double) rhs,
 #pragma unroll
         for (int j = 0; j < Q; j++) {
             const int k = kb + j + 1;
-            if (k > kmax) break;
             const bool act = live && (k <= v.npair);
             const double y1 = __shfl(bc, gbase + j);
             const double y2 = __shfl(bc, gbase + Q + j);
@@ -698,11 +709,10 @@ PQ_DEV void back_system(SysView v, bool live, GLB_PTR(const FT) rec0,
         }
         wave_sync();
         load_block(kb - SB);
-#pragma unroll 1
-        for (int jj = SB - 1; jj >= 0; jj--) {
+#pragma unroll
+        for (int jj = SB - 1; jj >= 0; jj--) {  // levels past the last one are inert
             const int j = jj & (Q - 1);
             const int k = kb + jj + 1;
-            if (k > kmax) continue;
             const bool act = live && (k <= v.npair);
             LDS_PTR(FT) r = lB + jj * stride;
             const double z1 = (double)r[c], z2 = (double)r[N2 + c];
