@@ -99,16 +99,26 @@ def ehl_legs(P, torch, synth, dev, args):
         torch.cuda.synchronize()
         dt = _t.perf_counter() - t0
         st = r["status"].cpu().numpy()
+        ok = st == 0
+        it = r["iters"].cpu().numpy()
         res[name] = dict(seconds=round(dt, 3), solves_per_s=round(nb / dt, 3),
-                         converged=int((st == 0).sum()), instances=nb,
-                         mean_newton_steps=float(r["iters"].float().mean()))
+                         converged=int(ok.sum()), converged_per_s=round(int(ok.sum()) / dt, 3),
+                         instances=nb, mean_newton_steps=float(it.mean()),
+                         mean_newton_steps_converged=float(it[ok].mean()) if ok.any() else None)
         res[name]["_P"] = r["P"]
+        res[name]["_ok"] = torch.as_tensor(ok, device=r["P"].device)
         log(f"ehl sweep {name}: {dt:.2f} s, converged {res[name]['converged']}/{nb}")
-    d = (res["fp32_deform"]["_P"] - res["fp64"]["_P"]).abs().max() / \
-        res["fp64"]["_P"].abs().max()
+    both = res["fp32_deform"]["_ok"] & res["fp64"]["_ok"]
+    d = None
+    if bool(both.any()):
+        p64, p32 = res["fp64"]["_P"][both], res["fp32_deform"]["_P"][both]
+        d = float(((p32 - p64).abs().amax(dim=1) / p64.abs().amax(dim=1)).max())
     for v in res.values():
         v.pop("_P")
-    res["max_rel_diff_fp32_vs_fp64"] = float(d)
+        v.pop("_ok")
+    # compared on the instances that converged in both runs
+    res["max_rel_diff_fp32_vs_fp64"] = d
+    res["compared_instances"] = int(both.sum())
     out["sweep_N1025"] = res
     if not args.no_adjoint:
         out["adjoint_N2049"] = adjoint_leg(P, torch, synth, args)
