@@ -283,7 +283,9 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid *grid, const eh
  * ehl_newton_tvd -- line contact: the hybrid Newton line iteration (Lhs1)
  * for B instances on one grid until each converges or hits max_newton:
  * deformation (MFMA), assembly, PAQIF solve of the linearised LCP (exact
- * active set), P <- max(0, P + omega D (v - P)), H0 <- H0 - c (pi/2 -
+ * active set; each step's active-set iteration starts from the previous
+ * step's final set, the first from the empty set: the LCP solution does not
+ * depend on the start), P <- max(0, P + omega D (v - P)), H0 <- H0 - c (pi/2 -
  * h sum P) (eq. 75).  Steps are captured in HIP graphs of steps_per_graph
  * steps; the host reads the per-instance done flags after every replay
  * (this call synchronises the stream).

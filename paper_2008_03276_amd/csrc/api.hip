@@ -162,6 +162,7 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double*
     a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
     a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
     a.skip = nullptr;
+    a.warm = 0;
     return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
                             (hipStream_t)stream);
 }

@@ -335,6 +335,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                    : nullptr;
     }
     la.skip = nullptr;
+    la.warm = 0;  // the lines change with the sweep direction and colour
 
     pq::PointUpdateArgs ua;
     ua.Nx = Nx;
@@ -614,6 +615,10 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
                    : nullptr;
     }
     la.skip = done;
+    // each Newton step's LCP starts from the previous step's final active
+    // set (the same rows every step); the first starts from the empty set
+    la.warm = 1;
+    if (hipMemsetAsync(la.act, 0, (size_t)B * n, s) != hipSuccess) return PAQIF_EHIP;
 
     pq::LineUpdateArgs ua;
     ua.N = N;

@@ -934,11 +934,14 @@ __global__ void __launch_bounds__(64)
     const bool exact = A.mode == LCP_EXACT;
     // working active set: exact mode starts from A_0 = {bounded i : b_i <= 0}
     // (the sign of b predicts the binding constraints of a diagonally
-    // dominant system); the other modes start empty
+    // dominant system), or, warm, from the flags the caller left in act
+    // restricted to bounded rows; the other modes start empty
+    const bool warm = exact && A.warm;
     if (live)
         for (int i = ls; i < v.n; i += G::LPS) {
             const bool bnd = A.bounded ? A.bounded[off + i] != 0 : true;
-            A.act[off + i] = (exact && bnd && A.b[off + i] <= 0.0) ? 1 : 0;
+            const bool start = warm ? A.act[off + i] != 0 : A.b[off + i] <= 0.0;
+            A.act[off + i] = (exact && bnd && start) ? 1 : 0;
         }
     __syncthreads();
 
@@ -1348,8 +1351,10 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
     GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
     const bool exact = A.mode == LCP_EXACT;
-    // working active set: exact mode starts from {bounded i : b_i <= 0}
-    for (int i = 0; i < v.n; i++) act[i] = (exact && (bnds ? bnds[i] != 0 : true) && bb[i] <= 0.0);
+    // working active set: exact mode starts from {bounded i : b_i <= 0}, or
+    // warm from the flags in act (bounded rows only)
+    for (int i = 0; i < v.n; i++)
+        act[i] = (exact && (bnds ? bnds[i] != 0 : true) && (A.warm ? act[i] != 0 : bb[i] <= 0.0));
     const int max_it = exact ? max(A.max_iter, 1) : 1;
     int st = SYS_OK, it = 0;
     bool done = !live;

@@ -37,6 +37,7 @@ struct LcpArgs {
     uint8_t* act;  // working active flags (total_rows)
     double* r;     // refinement residual (total_rows), FP32_IR only
     const uint8_t* skip;  // per system: nonzero = leave untouched (may be null)
+    int warm;  // exact mode: start from the flags already in act (bounded rows only)
 };
 
 struct FactorArgs {
