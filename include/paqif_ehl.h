@@ -292,12 +292,16 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid *grid, const eh
  *  P: DEVICE nx x B, in: start (ignored with start_rule 1), out: solution.
  *  H0: DEVICE [B], in/out.  H: DEVICE nx x B out (film).  Hmin: DEVICE [B].
  *  status: DEVICE int32[B] (SYS_OK, SYS_NEWTON_NOT_CONVERGED,
- *  SYS_NEGATIVE_FILM, SYS_NONFINITE).  iters: DEVICE int32[B].
+ *  SYS_NEGATIVE_FILM, SYS_NONFINITE; line contact also
+ *  SYS_LCP_NOT_CONVERGED when the step's LCP hit lcp_max_iter in 16
+ *  consecutive steps: the active-set iteration cycles and the instance is
+ *  stopped).  iters: DEVICE int32[B].
  *  workspace: DEVICE, ehl_newton_workspace_bytes(handle, grid, B, opts).
  * Point contact (grid with ny > 1; nx, ny >= 5): alternating x/y line sweeps,
  * each sweep direction in two colours of lines (odd line index, then even,
  * the film re-evaluated in between), every colour one batched PAQIF solve of
- * its lines; weighted change with quarter weights to the four neighbours
+ * its lines (its active-set iteration starts from the set the same lines
+ * ended with one step earlier); weighted change with quarter weights to the four neighbours
  * (eq. 69); y-lines change the direct nodes only; H0 <- H0 - c (2 pi/3 -
  * hx hy sum P) after each direction (eq. 75); convergence tested after each
  * x+y step.  P, H: DEVICE B x nx x ny; rough must be NULL.

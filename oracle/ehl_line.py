@@ -61,6 +61,8 @@ RHO_B = 1.34
 XA, XB = -4.5, 1.5
 SWITCH = 0.6
 LIMJAC = 2   # limiter terms of the Newton matrix (see limiter_jacobian)
+LCP_NOT_CONVERGED = 3   # status: the step's LCP hit its active-set cap ...
+LCP_FAIL_STEPS = 16     # ... in this many consecutive Newton steps
 
 
 def moes_line(M, L):
@@ -348,8 +350,9 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
-    <= t, t = max(tol, 4 N eps) (status 0), else status 6 after max_newton
-    steps.  Returns a dict
+    <= t, t = max(tol, 4 N eps) (status 0), when the linearised LCP hits its
+    active-set cap in LCP_FAIL_STEPS consecutive steps (status 3), else
+    status 6 after max_newton steps.  Returns a dict
     with P (N nodes), H0, H, Hmin (min over all nodes, first index), the
     number of steps and the status."""
     x, h = grid(N)
@@ -360,28 +363,34 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     if H0 is None:
         H0 = start_h0(x, h, kvec, M)
     status = 6
-    lcp_bad = 0
+    last = [0]
 
     def lcp(A, b, bnd):
-        nonlocal lcp_bad
         u, st = lcp_exact(A, b, bnd)
-        lcp_bad |= st != 0
+        last[0] = st
         return u
 
     # the FP64 rounding floor of the change grows with N: stop at
     # max(tol, 4 N eps), eps = 2^-52
     tl = max(tol, 4.0 * N * np.finfo(np.float64).eps)
     it = 0
+    fails = 0  # consecutive steps whose LCP hit the active-set cap
     for it in range(1, max_newton + 1):
         Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms,
                                    LIMJAC if limjac is None else limjac)
         dP = np.abs(Pn - P).max()
         P = Pn
+        fails = fails + 1 if last[0] == LCP_NOT_CONVERGED else 0
         if not np.isfinite(dP):
             status = 2
             break
         if dP <= tl * max(1.0, np.abs(P).max()) and abs(np.pi / 2 - h * P.sum()) <= tl:
             status = 0
+            break
+        if fails >= LCP_FAIL_STEPS:
+            # the active-set iteration cycles: this linearisation has no
+            # solution the iteration reaches, the Newton iteration is lost
+            status = LCP_NOT_CONVERGED
             break
     H = film(P, H0, x, kvec, rough)
     if status == 0 and H.min() <= 0.0:

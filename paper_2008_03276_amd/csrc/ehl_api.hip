@@ -77,8 +77,8 @@ bool valid_opts(const ehl_opts* o)
 
 // Newton workspace layout (line contact)
 struct NewtonLayout {
-    size_t kvec, hel, band, rhs, v, pn, bounded, direct, done, dP, lerr, offs, lst, lit, lcp,
-        total;
+    size_t kvec, hel, band, rhs, v, pn, bounded, direct, done, dP, lerr, offs, lst, lit, lfail,
+        lcp, total;
 };
 
 size_t lcp_ws_bytes(int B, int n, int prec)
@@ -116,6 +116,7 @@ NewtonLayout newton_layout(const ehl_grid* g, int B, const ehl_opts* o)
     L.offs = take((b + 1) * sizeof(int64_t));
     L.lst = take(b * sizeof(int32_t));
     L.lit = take(b * sizeof(int32_t));
+    L.lfail = take(b * sizeof(int32_t));
     L.lcp = take(lcp_ws_bytes(B, (int)n, o ? o->lcp_prec : PREC_FP64));
     L.total = p;
     return L;
@@ -161,8 +162,8 @@ __global__ void final_status_kernel(int B, const uint8_t* done, const double* Hm
 // Point contact (2D grid): workspace and driver.
 // ---------------------------------------------------------------------------
 struct PointLayout {
-    size_t dws, hel, nodes, direct, q, pstart, band, rhs, v, bounded, done, offs[4], lst, lit, lcp,
-        total;
+    size_t dws, hel, nodes, direct, q, pstart, band, rhs, v, bounded, done, offs[4], act[4], lst,
+        lit, lcp, total;
     int nlc[4], nrow[4];  // (axis, colour) -> lines per instance, rows per line
 };
 
@@ -199,6 +200,8 @@ PointLayout point_layout(const ehl_grid* g, int B, const ehl_opts* o)
     L.bounded = take(rows_max);
     L.done = take(B);
     for (int k = 0; k < 4; k++) L.offs[k] = take((size_t)(L.nlc[k] * B + 1) * sizeof(int64_t));
+    // active flags of each colour pass, kept from one step to the next
+    for (int k = 0; k < 4; k++) L.act[k] = take((size_t)L.nlc[k] * L.nrow[k] * B);
     L.lst = take((size_t)cnt_max * sizeof(int32_t));
     L.lit = take((size_t)cnt_max * sizeof(int32_t));
     L.lcp = take(lcp_ws_bytes(cnt_max, n_max, o ? o->lcp_prec : PREC_FP64));
@@ -335,7 +338,12 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                    : nullptr;
     }
     la.skip = nullptr;
-    la.warm = 0;  // the lines change with the sweep direction and colour
+    // each colour pass keeps its own active flags: a pass's LCP starts from
+    // the set its lines ended with one step earlier (first step: empty set)
+    la.warm = 1;
+    for (int k = 0; k < 4; k++)
+        if (hipMemsetAsync(ws + L.act[k], 0, (size_t)L.nlc[k] * L.nrow[k] * B, s) != hipSuccess)
+            return PAQIF_EHIP;
 
     pq::PointUpdateArgs ua;
     ua.Nx = Nx;
@@ -377,6 +385,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                 if ((e = pq::launch_point_assemble(pa, s))) return e;
                 la.count = L.nlc[k] * B;
                 la.offsets = reinterpret_cast<const int64_t*>(ws + L.offs[k]);
+                la.act = reinterpret_cast<uint8_t*>(ws + L.act[k]);
                 if (la.count > 0 && (e = pq::dispatch_lcp(4, la, opts->lcp_prec, layout, s)))
                     return e;
                 ua.axis = ax;
@@ -636,6 +645,8 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     ua.iters = iters;
     ua.dP = dP;
     ua.load_err = lerr;
+    ua.lcp_status = lst;
+    ua.lcp_fails = reinterpret_cast<int32_t*>(ws + L.lfail);
 
     auto one_step = [&](int dprec) -> int {
         int e;
@@ -663,6 +674,8 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
         if (ph > 0)
             hipLaunchKernelGGL(reopen_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done,
                                status);
+        if (hipMemsetAsync(ua.lcp_fails, 0, (size_t)B * sizeof(int32_t), s) != hipSuccess)
+            return PAQIF_EHIP;
         hipGraphExec_t exec = nullptr;
         bool use_graph = stream != nullptr;
         if (use_graph) {

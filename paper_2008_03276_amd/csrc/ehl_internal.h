@@ -48,7 +48,13 @@ struct LineUpdateArgs {
     int32_t* iters;      // B
     double* dP;          // B (last max change)
     double* load_err;    // B
+    const int32_t* lcp_status;  // B, status of this step's LCP solve
+    int32_t* lcp_fails;  // B, consecutive steps whose LCP hit its active-set cap
 };
+// An instance whose linearised LCP hits the active-set cap in this many
+// consecutive Newton steps stops with SYS_LCP_NOT_CONVERGED (the active-set
+// iteration is cycling: the step's linearisation has no reachable solution)
+constexpr int kLcpFailSteps = 16;
 int launch_line_update_ws(const LineUpdateArgs& a, double* Pnew, hipStream_t s);
 
 struct LineInitArgs {

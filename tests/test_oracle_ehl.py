@@ -194,3 +194,22 @@ def test_line_solution_reference_values(converged_cfg1):
     assert 0.05 < r["Hmin"] < 0.1
     herz = E.hertz_start(x)
     assert np.abs(P - herz)[np.abs(x) < 0.5].max() < 0.1
+
+
+def test_newton_stops_when_the_lcp_keeps_hitting_its_cap(monkeypatch):
+    """The line iteration gives up with status 3 once the linearised LCP has
+    hit its active-set cap in LCP_FAIL_STEPS consecutive steps (the GPU
+    driver applies the same rule); an LCP that converges resets the count."""
+    real = E.lcp_exact
+    calls = {"n": 0}
+
+    def capped(A, b, bnd):
+        calls["n"] += 1
+        u, _ = real(A, b, bnd)
+        # one converged step in the middle resets the consecutive count
+        return u, (0 if calls["n"] == 5 else E.LCP_NOT_CONVERGED)
+
+    monkeypatch.setattr(E, "lcp_exact", capped)
+    r = E.solve_line(20.0, 10.0, 65, max_newton=200)
+    assert r["status"] == E.LCP_NOT_CONVERGED
+    assert r["iters"] == 5 + E.LCP_FAIL_STEPS
