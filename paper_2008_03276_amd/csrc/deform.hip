@@ -11,10 +11,11 @@
 // Point contact (case 2): H_el[i][j] = sum_{i',j'} k2[|i-i'|][|j-j'|] P[i'][j'],
 // k2 = (2/pi^2) * (cell integral of 1/r, closed form with asinh terms).  For
 // a fixed row offset d = i - i' the j-sum is a Toeplitz product, so an
-// output tile (16 j x 16 i) accumulates MFMAs with A = T_|d| (16 j x 4 j') and
-// B = P[i - d][j'] (4 j' x 16 i) over all d and j'.  The d range is split over
-// workgroups (fixed partition, partial sums reduced in a fixed order), so the
-// result is deterministic.
+// output tile accumulates MFMAs with A = T_|d| (16 j x 4 j') and
+// B = P[i - d][j'] (4 j' x 16 i) over all d and j'; FP64 and FP32 use 32 x 32
+// tiles per wave (two A and two B operands feed four MFMAs), split BF16
+// 16 x 16.  The d range is split over workgroups (fixed partition, partial
+// sums reduced in a fixed order), so the result is deterministic.
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32),
 // and split BF16: every operand x is split as x = hi + lo with hi = bf16(x),
@@ -125,16 +126,32 @@ __global__ void __launch_bounds__(256) line_deform_kernel(int N, int B,
     if constexpr (PREC == PREC_FP64) {
         f64x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
         const int bA = b0 + li, bB = b0 + 16 + li;
-        const double* PA = P + (int64_t)bA * N;
-        const double* PB = P + (int64_t)bB * N;
-        for (int j0 = 0; j0 < N; j0 += 4) {
-            const int j = j0 + lk;
-            const bool jin = j < N;
-            const double a = (i < N && jin) ? sk[abs(i - j)] : 0.0;
-            const double x0 = (jin && bA < B) ? PA[j] : 0.0;
-            const double x1 = (jin && bB < B) ? PB[j] : 0.0;
-            c0 = mfma_f64(a, x0, c0);
-            c1 = mfma_f64(a, x1, c1);
+        // U K-steps per pass: all their loads (clamped, valid addresses) are
+        // issued before the MFMAs, which zero out-of-range operands (the MFMA
+        // is convergent, so the compiler does not unroll a loop of unknown
+        // trip count by itself)
+        constexpr int U = 4;
+        const double* PA = P + (int64_t)min(bA, B - 1) * N;
+        const double* PB = P + (int64_t)min(bB, B - 1) * N;
+        const int ic = min(i, N - 1);
+        for (int jb = 0; jb < N; jb += 4 * U) {
+            double ar[U], x0r[U], x1r[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int jc = min(jb + 4 * u + lk, N - 1);
+                ar[u] = sk[abs(ic - jc)];
+                x0r[u] = PA[jc];
+                x1r[u] = PB[jc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool jin = jb + 4 * u + lk < N;
+                const double a = (i < N && jin) ? ar[u] : 0.0;
+                const double x0 = (jin && bA < B) ? x0r[u] : 0.0;
+                const double x1 = (jin && bB < B) ? x1r[u] : 0.0;
+                c0 = mfma_f64(a, x0, c0);
+                c1 = mfma_f64(a, x1, c1);
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -147,16 +164,28 @@ __global__ void __launch_bounds__(256) line_deform_kernel(int N, int B,
     } else if constexpr (PREC == PREC_FP32) {
         f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
         const int bA = b0 + li, bB = b0 + 16 + li;
-        const double* PA = P + (int64_t)bA * N;
-        const double* PB = P + (int64_t)bB * N;
-        for (int j0 = 0; j0 < N; j0 += 4) {
-            const int j = j0 + lk;
-            const bool jin = j < N;
-            const float a = (i < N && jin) ? (float)sk[abs(i - j)] : 0.0f;
-            const float x0 = (jin && bA < B) ? (float)PA[j] : 0.0f;
-            const float x1 = (jin && bB < B) ? (float)PB[j] : 0.0f;
-            c0 = mfma_f32(a, x0, c0);
-            c1 = mfma_f32(a, x1, c1);
+        constexpr int U = 4;  // as in the FP64 path
+        const double* PA = P + (int64_t)min(bA, B - 1) * N;
+        const double* PB = P + (int64_t)min(bB, B - 1) * N;
+        const int ic = min(i, N - 1);
+        for (int jb = 0; jb < N; jb += 4 * U) {
+            double ar[U], x0r[U], x1r[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int jc = min(jb + 4 * u + lk, N - 1);
+                ar[u] = sk[abs(ic - jc)];
+                x0r[u] = PA[jc];
+                x1r[u] = PB[jc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool jin = jb + 4 * u + lk < N;
+                const float a = (i < N && jin) ? (float)ar[u] : 0.0f;
+                const float x0 = (jin && bA < B) ? (float)x0r[u] : 0.0f;
+                const float x1 = (jin && bB < B) ? (float)x1r[u] : 0.0f;
+                c0 = mfma_f32(a, x0, c0);
+                c1 = mfma_f32(a, x1, c1);
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -216,7 +245,7 @@ __global__ void __launch_bounds__(256) line_deform_kernel(int N, int B,
 // partial sums go to part[s][inst][Nx*Ny] and are reduced by
 // point_reduce_kernel.
 // ---------------------------------------------------------------------------
-template <int PREC>
+template <int PREC>  // PREC_SPLIT_BF16
 __global__ void __launch_bounds__(256) point_deform_kernel(int Nx, int Ny, int nseg, int B,
                                                            const double* __restrict__ k2,
                                                            const double* __restrict__ P,
@@ -238,7 +267,6 @@ __global__ void __launch_bounds__(256) point_deform_kernel(int Nx, int Ny, int n
     const int ds0 = dlo + s * per, ds1 = min(dhi, ds0 + per - 1);
     const int jrow = j0 + li;  // A row (output j) of this lane
     const int icol = i0 + li;  // B column (output i) of this lane
-    f64x4 c64 = {0, 0, 0, 0};
     f32x4 c32 = {0, 0, 0, 0};
     for (int d = ds0; d <= ds1; d++) {
         const int ad = abs(d);
@@ -247,37 +275,103 @@ __global__ void __launch_bounds__(256) point_deform_kernel(int Nx, int Ny, int n
         const int ip = icol - d;  // P row for this lane's B column
         const bool iok = icol < Nx && ip >= 0 && ip < Nx;
         const double* prow = Pi + (int64_t)(iok ? ip : 0) * Ny;
-        if constexpr (PREC == PREC_FP64 || PREC == PREC_FP32) {
-            for (int jp0 = 0; jp0 < Ny; jp0 += 4) {
-                const int jp = jp0 + lk;
-                const bool jok = jp < Ny;
-                const double a = (jrow < Ny && jok) ? krow[abs(jrow - jp)] : 0.0;
-                const double x = (iok && jok) ? prow[jp] : 0.0;
-                if constexpr (PREC == PREC_FP64)
-                    c64 = mfma_f64(a, x, c64);
-                else
-                    c32 = mfma_f32((float)a, (float)x, c32);
-            }
-        } else {
-            for (int jp0 = 0; jp0 < Ny; jp0 += 16) {
-                bf16x4 ah, al, xh, xl;
+        for (int jp0 = 0; jp0 < Ny; jp0 += 16) {
+            bf16x4 ah, al, xh, xl;
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int jp = jp0 + 4 * lk + e;
-                    const bool jok = jp < Ny;
-                    const float a = (jrow < Ny && jok) ? (float)krow[abs(jrow - jp)] : 0.0f;
-                    const float x = (iok && jok) ? (float)prow[jp] : 0.0f;
-                    short h, lo;
-                    split_bf16(a, h, lo);
-                    ah[e] = h;
-                    al[e] = lo;
-                    split_bf16(x, h, lo);
-                    xh[e] = h;
-                    xl[e] = lo;
+            for (int e = 0; e < 4; e++) {
+                const int jp = jp0 + 4 * lk + e;
+                const bool jok = jp < Ny;
+                const float a = (jrow < Ny && jok) ? (float)krow[abs(jrow - jp)] : 0.0f;
+                const float x = (iok && jok) ? (float)prow[jp] : 0.0f;
+                short h, lo;
+                split_bf16(a, h, lo);
+                ah[e] = h;
+                al[e] = lo;
+                split_bf16(x, h, lo);
+                xh[e] = h;
+                xl[e] = lo;
+            }
+            c32 = mfma_bf16(ah, xh, c32);
+            c32 = mfma_bf16(ah, xl, c32);
+            c32 = mfma_bf16(al, xh, c32);
+        }
+    }
+    double* dst = part + ((int64_t)s * B + inst) * Nx * Ny;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int jo = j0 + 4 * lk + r;  // D row (output j): f32 result row 4*(l/16) + r
+        const int io = i0 + li;          // D column = output i
+        if (jo < Ny && io < Nx) dst[(int64_t)io * Ny + jo] = (double)c32[r];
+    }
+}
+
+// FP64 / FP32 point contact with a 32 j x 32 i output tile per wave (four
+// 16 x 16 accumulators): each K-step loads two A columns (T_|d| rows) and two
+// B rows (P rows) for four MFMAs, half the operand loads per MFMA of the
+// 16 x 16 tile, whose loads (L1 traffic) had bound it.  4 waves per
+// workgroup along i; blockIdx.y = segment of the d range as above.
+template <int PREC>
+__global__ void __launch_bounds__(256) point_deform_kernel32(int Nx, int Ny, int nseg, int B,
+                                                             const double* __restrict__ k2,
+                                                             const double* __restrict__ P,
+                                                             double* __restrict__ part)
+{
+    constexpr int U = 4;  // K-steps per pass, loads issued before the MFMAs
+    const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int li = l % 16, lk = l / 16;
+    const int ntj = (Ny + 31) / 32;
+    const int tj = blockIdx.x % ntj;
+    const int ti = (blockIdx.x / ntj) * 4 + wave;
+    const int j0 = tj * 32, i0 = ti * 32;
+    const int s = blockIdx.y, inst = blockIdx.z;
+    if (i0 >= Nx) return;
+    const double* Pi = P + (int64_t)inst * Nx * Ny;
+    const int dlo = i0 - (Nx - 1), dhi = i0 + 31;
+    const int span = dhi - dlo + 1;
+    const int per = (span + nseg - 1) / nseg;
+    const int ds0 = dlo + s * per, ds1 = min(dhi, ds0 + per - 1);
+    const int jr0 = j0 + li, jr1 = j0 + 16 + li;    // A rows (output j)
+    const int ic0 = i0 + li, ic1 = i0 + 16 + li;    // B columns (output i)
+    const int jc0 = min(jr0, Ny - 1), jc1 = min(jr1, Ny - 1);
+    f64x4 d00 = {0, 0, 0, 0}, d01 = d00, d10 = d00, d11 = d00;
+    f32x4 f00 = {0, 0, 0, 0}, f01 = f00, f10 = f00, f11 = f00;
+    for (int d = ds0; d <= ds1; d++) {
+        const int ad = abs(d);
+        if (ad >= Nx) continue;  // uniform over the wave
+        const double* krow = k2 + (int64_t)ad * Ny;
+        const int ip0 = ic0 - d, ip1 = ic1 - d;  // P rows of the two B column tiles
+        const bool ok0 = ic0 < Nx && ip0 >= 0 && ip0 < Nx;
+        const bool ok1 = ic1 < Nx && ip1 >= 0 && ip1 < Nx;
+        const double* pr0 = Pi + (int64_t)min(max(ip0, 0), Nx - 1) * Ny;
+        const double* pr1 = Pi + (int64_t)min(max(ip1, 0), Nx - 1) * Ny;
+        for (int jb = 0; jb < Ny; jb += 4 * U) {
+            double a0[U], a1[U], x0[U], x1[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int jp = min(jb + 4 * u + lk, Ny - 1);
+                a0[u] = krow[abs(jc0 - jp)];
+                a1[u] = krow[abs(jc1 - jp)];
+                x0[u] = pr0[jp];
+                x1[u] = pr1[jp];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool jok = jb + 4 * u + lk < Ny;
+                const double A0 = (jr0 < Ny && jok) ? a0[u] : 0.0;
+                const double A1 = (jr1 < Ny && jok) ? a1[u] : 0.0;
+                const double X0 = (ok0 && jok) ? x0[u] : 0.0;
+                const double X1 = (ok1 && jok) ? x1[u] : 0.0;
+                if constexpr (PREC == PREC_FP64) {
+                    d00 = mfma_f64(A0, X0, d00);
+                    d01 = mfma_f64(A0, X1, d01);
+                    d10 = mfma_f64(A1, X0, d10);
+                    d11 = mfma_f64(A1, X1, d11);
+                } else {
+                    f00 = mfma_f32((float)A0, (float)X0, f00);
+                    f01 = mfma_f32((float)A0, (float)X1, f01);
+                    f10 = mfma_f32((float)A1, (float)X0, f10);
+                    f11 = mfma_f32((float)A1, (float)X1, f11);
                 }
-                c32 = mfma_bf16(ah, xh, c32);
-                c32 = mfma_bf16(ah, xl, c32);
-                c32 = mfma_bf16(al, xh, c32);
             }
         }
     }
@@ -285,10 +379,15 @@ __global__ void __launch_bounds__(256) point_deform_kernel(int Nx, int Ny, int n
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         // D row (output j): f64 result row 4*r + l/16, f32 result row 4*(l/16) + r
-        const int jo = j0 + (PREC == PREC_FP64 ? 4 * r + lk : 4 * lk + r);
-        const int io = i0 + li;  // D column = output i
-        if (jo < Ny && io < Nx)
-            dst[(int64_t)io * Ny + jo] = PREC == PREC_FP64 ? c64[r] : (double)c32[r];
+        const int jo = (PREC == PREC_FP64 ? 4 * r + lk : 4 * lk + r);
+        const double v00 = PREC == PREC_FP64 ? d00[r] : (double)f00[r];
+        const double v01 = PREC == PREC_FP64 ? d01[r] : (double)f01[r];
+        const double v10 = PREC == PREC_FP64 ? d10[r] : (double)f10[r];
+        const double v11 = PREC == PREC_FP64 ? d11[r] : (double)f11[r];
+        if (j0 + jo < Ny && ic0 < Nx) dst[(int64_t)ic0 * Ny + j0 + jo] = v00;
+        if (j0 + jo < Ny && ic1 < Nx) dst[(int64_t)ic1 * Ny + j0 + jo] = v01;
+        if (j0 + 16 + jo < Ny && ic0 < Nx) dst[(int64_t)ic0 * Ny + j0 + 16 + jo] = v10;
+        if (j0 + 16 + jo < Ny && ic1 < Nx) dst[(int64_t)ic1 * Ny + j0 + 16 + jo] = v11;
     }
 }
 
@@ -334,26 +433,34 @@ int launch_line_deform(int N, int B, int prec, const double* k, const double* P,
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
-int point_segments(int Nx) { return Nx >= 128 ? 8 : 1; }
+// segments of the d range: enough waves to fill the chip at one instance
+// (about 1500 waves of 32 x 32 tiles), at most 32
+int point_segments(int Nx, int Ny)
+{
+    const int tiles = ((Nx + 31) / 32) * ((Ny + 31) / 32);
+    return std::max(1, std::min(32, 1536 / std::max(1, tiles)));
+}
 
 size_t point_workspace_doubles(int Nx, int Ny, int B)
 {
-    return (size_t)Nx * Ny + (size_t)point_segments(Nx) * B * Nx * Ny;
+    return (size_t)Nx * Ny + (size_t)point_segments(Nx, Ny) * B * Nx * Ny;
 }
 
 int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const double* P,
                         double* out, double* part, hipStream_t s)
 {
     if (Nx <= 0 || Ny <= 0 || B <= 0) return PAQIF_OK;
-    const int nseg = point_segments(Nx);
+    const int nseg = point_segments(Nx, Ny);
+    const int ntj32 = (Ny + 31) / 32, nti32 = (Nx + 31) / 32;
+    const dim3 grid32(ntj32 * ((nti32 + 3) / 4), nseg, B), block(256);
     const int ntj = (Ny + 15) / 16, nti = (Nx + 15) / 16;
-    dim3 grid(ntj * ((nti + 3) / 4), nseg, B), block(256);
+    const dim3 grid(ntj * ((nti + 3) / 4), nseg, B);
     if (prec == PREC_FP64)
-        hipLaunchKernelGGL((point_deform_kernel<PREC_FP64>), grid, block, 0, s, Nx, Ny, nseg, B,
-                           k2, P, part);
+        hipLaunchKernelGGL((point_deform_kernel32<PREC_FP64>), grid32, block, 0, s, Nx, Ny, nseg,
+                           B, k2, P, part);
     else if (prec == PREC_FP32)
-        hipLaunchKernelGGL((point_deform_kernel<PREC_FP32>), grid, block, 0, s, Nx, Ny, nseg, B,
-                           k2, P, part);
+        hipLaunchKernelGGL((point_deform_kernel32<PREC_FP32>), grid32, block, 0, s, Nx, Ny, nseg,
+                           B, k2, P, part);
     else
         hipLaunchKernelGGL((point_deform_kernel<PREC_SPLIT_BF16>), grid, block, 0, s, Nx, Ny, nseg,
                            B, k2, P, part);
