@@ -409,29 +409,52 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
     RawEnt nX[XPL];
     static_assert(S * TR * TC <= 16 && XPL <= 32, "selection codes fit one word");
     uint32_t cR, cC, cX;  // selection codes, 2 bits per entry (1 per extra)
+    // The index a slot takes at its refill is linear in t = kb + sb q (the
+    // first level of the block, minus one): left slots move down by one per
+    // level, right slots up.  Bases, signs and the last valid t of every
+    // prefetched entry are set once here.
+    int sgA[TR], sgB[TC];  // -1 left slot, +1 right slot
+#pragma unroll
+    for (int u = 0; u < TR; u++) sgA[u] = a[u] < Q ? -1 : 1;
+#pragma unroll
+    for (int w = 0; w < TC; w++) sgB[w] = b[w] < Q ? -1 : 1;
+    int iR0[TR], tR[TR], jR0[TR][TC], iC0[TR][TC], jC0[TC], tC[TC];
+#pragma unroll
+    for (int u = 0; u < TR; u++) {
+        // row refill at level t + jr + 1: slots a[u] and b[w] after that level
+        const int p1 = v.P1_0 - jr[u], p2 = v.P2_0 + jr[u];
+        iR0[u] = slot_index_post<Q>(a[u], jr[u], p1, p2);
+        tR[u] = v.npair - jr[u] - 1;  // the level exists while t <= tR
+#pragma unroll
+        for (int w = 0; w < TC; w++) jR0[u][w] = slot_index_post<Q>(b[w], jr[u], p1, p2);
+    }
+#pragma unroll
+    for (int w = 0; w < TC; w++) {
+        const int p1 = v.P1_0 - jc[w], p2 = v.P2_0 + jc[w];
+        jC0[w] = slot_index_post<Q>(b[w], jc[w], p1, p2);
+        tC[w] = v.npair - jc[w] - 1;
+#pragma unroll
+        for (int u = 0; u < TR; u++) iC0[u][w] = slot_index_post<Q>(a[u], jc[w], p1, p2);
+    }
     auto load_super = [&](int kn) {
         cR = cC = cX = 0u;
 #pragma unroll
-        for (int sb = 0; sb < S; sb++)
+        for (int sb = 0; sb < S; sb++) {
+            const int t = kn + sb * Q;
 #pragma unroll
             for (int u = 0; u < TR; u++)
 #pragma unroll
                 for (int w = 0; w < TC; w++) {
-                    const int kr = kn + sb * Q + jr[u] + 1, kc = kn + sb * Q + jc[w] + 1;
-                    const int jr0 = (kr - 1) & (Q - 1), jc0 = (kc - 1) & (Q - 1);
-                    const int p1r = v.P1_0 - (kr - 1), p2r = v.P2_0 + (kr - 1);
-                    const int p1c = v.P1_0 - (kc - 1), p2c = v.P2_0 + (kc - 1);
                     const int sh = 2 * ((sb * TR + u) * TC + w);
                     uint32_t code;
-                    nR[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jr0, p1r, p2r),
-                                              slot_index_post<Q>(b[w], jr0, p1r, p2r),
-                                              live && kr <= v.npair, code);
+                    nR[sb][u][w] = raw_ent<Q>(v, iR0[u] + sgA[u] * t, jR0[u][w] + sgB[w] * t,
+                                              live && t <= tR[u], code);
                     cR |= code << sh;
-                    nC[sb][u][w] = raw_ent<Q>(v, slot_index_post<Q>(a[u], jc0, p1c, p2c),
-                                              slot_index_post<Q>(b[w], jc0, p1c, p2c),
-                                              live && kc <= v.npair && jc[w] != jr[u], code);
+                    nC[sb][u][w] = raw_ent<Q>(v, iC0[u][w] + sgA[u] * t, jC0[w] + sgB[w] * t,
+                                              live && t <= tC[w] && jc[w] != jr[u], code);
                     cC |= code << sh;
                 }
+        }
 #pragma unroll
         for (int x = 0; x < XPL; x++) {
             const int e = ls + x * G::LPS;
@@ -513,7 +536,18 @@ PQ_DEV bool factor_system(SysView v, bool live, GLB_PTR(FT) rec, int stride, LDS
 
             const FT det = P11 * P22 - P12 * P21;
             if (act && !(det != (FT)0 && isfinite(det))) bad = true;
-            const FT rd = (FT)1 / det;
+            // 1/det: hardware reciprocal and two Newton steps (each squares
+            // the relative error: ~2^-23 -> below 2^-53), a shorter dependent
+            // chain than the IEEE division sequence on the level's critical
+            // path; a zero or non-finite det is flagged above
+            FT rd;
+            if constexpr (sizeof(FT) == 8) {
+                const double r0 = __builtin_amdgcn_rcp(det);
+                const double r1 = __builtin_fma(r0, __builtin_fma(-det, r0, 1.0), r0);
+                rd = __builtin_fma(r1, __builtin_fma(-det, r1, 1.0), r1);
+            } else {
+                rd = (FT)1 / det;
+            }
             const FT i11 = P22 * rd, i12 = -P12 * rd, i21 = -P21 * rd, i22 = P11 * rd;
 
             // record: Z0 rows p1, p2 over the slots after this level, the
