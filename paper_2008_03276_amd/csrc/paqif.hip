@@ -971,12 +971,28 @@ __global__ void __launch_bounds__(64)
     // dominant system), or, warm, from the flags the caller left in act
     // restricted to bounded rows; the other modes start empty
     const bool warm = exact && A.warm;
-    if (live)
-        for (int i = ls; i < v.n; i += G::LPS) {
-            const bool bnd = A.bounded ? A.bounded[off + i] != 0 : true;
-            const bool start = warm ? A.act[off + i] != 0 : A.b[off + i] <= 0.0;
-            A.act[off + i] = (exact && bnd && start) ? 1 : 0;
+    if (live) {
+        // 8 rows per lane per pass, loads (clamped rows) issued before use
+        constexpr int R = 8;
+        const int nm = v.n - 1;
+        for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
+            uint32_t bn[R], pa[R];
+            double bv[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int64_t g = off + min(i0 + r * G::LPS, nm);
+                bn[r] = A.bounded ? (uint32_t)A.bounded[g] : 1u;
+                pa[r] = warm ? (uint32_t)A.act[g] : 0u;
+                bv[r] = A.b[g];
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int i = i0 + r * G::LPS;
+                const bool start = warm ? pa[r] != 0u : bv[r] <= 0.0;
+                if (i < v.n) A.act[off + i] = (exact && bn[r] != 0u && start) ? 1 : 0;
+            }
         }
+    }
     __syncthreads();
 
     const int max_it = exact ? max(A.max_iter, 1) : 1;
@@ -1067,8 +1083,18 @@ __global__ void __launch_bounds__(64)
         // the others in the wave
     }
     if (live) {
-        if (A.active_out)
-            for (int i = ls; i < v.n; i += G::LPS) A.active_out[off + i] = A.act[off + i];
+        if (A.active_out) {  // copy, 8 rows per lane per pass
+            constexpr int R = 8;
+            const int nm = v.n - 1;
+            for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
+                uint8_t f[R];
+#pragma unroll
+                for (int r = 0; r < R; r++) f[r] = A.act[off + min(i0 + r * G::LPS, nm)];
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (i0 + r * G::LPS < v.n) A.active_out[off + i0 + r * G::LPS] = f[r];
+            }
+        }
         if (ls == 0) {
             A.status[sys] = st;
             if (A.iters) A.iters[sys] = it;
