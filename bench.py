@@ -71,9 +71,10 @@ def log(msg):
 
 def ehl_legs(P, torch, synth, dev, args):
     """EHL solves/s: config 1 (N=257, M=20, L=10, one instance, time to
-    solution) and a batched line-contact sweep (N=1025, M log-uniform in
-    [10,1000], L uniform in [5,20]); FP64 and FP32-deformation (+FP64
-    refresh) variants; iterations and statuses reported."""
+    solution) and a batched line-contact sweep (M log-uniform in [10,1000],
+    L uniform in [5,20], N in {1025, 2049, 4097}, one batch per N) in FP64,
+    plus the FP32-deformation (+FP64 refresh) variant on the N=1025 batch;
+    iterations and statuses reported."""
     import time as _t
     out = {}
     # config 1
@@ -87,39 +88,55 @@ def ehl_legs(P, torch, synth, dev, args):
     out["config1"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 3),
                           status=int(r["status"][0]), newton_steps=int(r["iters"][0]),
                           H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]))
-    # sweep
+    # sweep: nb instances, N drawn from {1025, 2049, 4097} (grouped by N,
+    # one batched solve per group), FP64; the FP32-deformation variant
+    # (+ FP64 refresh) on the N = 1025 group
     nb = args.ehl_sweep
     M, L = synth.ehl_sweep_params(nb, seed=args.seed)
-    res = {}
-    for name, prec in (("fp64", P.PREC_FP64), ("fp32_deform", P.PREC_FP32)):
-        opts = P.ehl.default_opts(deform_prec=prec, max_newton=3000, lcp_max_iter=16)
+    groups = np.array_split(np.arange(nb), 3)
+    res = {"instances": nb, "groups": {}}
+    t_all, conv_all = 0.0, 0
+    P1025 = None
+    for N, idx in zip((1025, 2049, 4097), groups):
+        # active-set cap 8: a warm-started step's LCP needs about one solve,
+        # and a batched launch lasts as long as its slowest (cycling) system
+        opts = P.ehl.default_opts(max_newton=3000, lcp_max_iter=8)
         torch.cuda.synchronize()
         t0 = _t.perf_counter()
-        r = P.ehl.solve_line(M, L, 1025, opts=opts)
+        r = P.ehl.solve_line(M[idx], L[idx], N, opts=opts)
         torch.cuda.synchronize()
         dt = _t.perf_counter() - t0
         st = r["status"].cpu().numpy()
-        ok = st == 0
         it = r["iters"].cpu().numpy()
-        res[name] = dict(seconds=round(dt, 3), solves_per_s=round(nb / dt, 3),
-                         converged=int(ok.sum()), converged_per_s=round(int(ok.sum()) / dt, 3),
-                         instances=nb, mean_newton_steps=float(it.mean()),
-                         mean_newton_steps_converged=float(it[ok].mean()) if ok.any() else None)
-        res[name]["_P"] = r["P"]
-        res[name]["_ok"] = torch.as_tensor(ok, device=r["P"].device)
-        log(f"ehl sweep {name}: {dt:.2f} s, converged {res[name]['converged']}/{nb}")
-    both = res["fp32_deform"]["_ok"] & res["fp64"]["_ok"]
+        ok = st == 0
+        res["groups"][str(N)] = dict(
+            instances=int(len(idx)), seconds=round(dt, 3), converged=int(ok.sum()),
+            statuses={str(int(k)): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+            mean_newton_steps_converged=float(it[ok].mean()) if ok.any() else None)
+        t_all += dt
+        conv_all += int(ok.sum())
+        if N == 1025:
+            P1025, ok1025, idx1025 = r["P"], ok, idx
+        log(f"ehl sweep N={N}: {dt:.2f} s, converged {int(ok.sum())}/{len(idx)}")
+    res.update(seconds=round(t_all, 3), converged=conv_all,
+               solves_per_s=round(nb / t_all, 3), converged_per_s=round(conv_all / t_all, 3))
+    opts = P.ehl.default_opts(deform_prec=P.PREC_FP32, max_newton=3000, lcp_max_iter=8)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    r = P.ehl.solve_line(M[idx1025], L[idx1025], 1025, opts=opts)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t0
+    ok32 = r["status"].cpu().numpy() == 0
+    both = torch.as_tensor(ok32 & ok1025, device=r["P"].device)
     d = None
     if bool(both.any()):
-        p64, p32 = res["fp64"]["_P"][both], res["fp32_deform"]["_P"][both]
+        p64, p32 = P1025[both], r["P"][both]
         d = float(((p32 - p64).abs().amax(dim=1) / p64.abs().amax(dim=1)).max())
-    for v in res.values():
-        v.pop("_P")
-        v.pop("_ok")
-    # compared on the instances that converged in both runs
-    res["max_rel_diff_fp32_vs_fp64"] = d
-    res["compared_instances"] = int(both.sum())
-    out["sweep_N1025"] = res
+    res["fp32_deform_N1025"] = dict(seconds=round(dt, 3), converged=int(ok32.sum()),
+                                    fp64_seconds=res["groups"]["1025"]["seconds"],
+                                    max_rel_diff_vs_fp64=d, compared_instances=int(both.sum()))
+    log(f"ehl sweep N=1025 FP32 deformation: {dt:.2f} s, converged {int(ok32.sum())}")
+    out["sweep"] = res
     if not args.no_adjoint:
         out["adjoint_N2049"] = adjoint_leg(P, torch, synth, args)
     if not args.no_point:
@@ -198,7 +215,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-ehl", action="store_true")
     ap.add_argument("--ehl-sweep", type=int, default=512,
-                    help="instances of the line-contact sweep leg (N=1025)")
+                    help="instances of the line-contact sweep leg (N in {1025, 2049, 4097})")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-point", action="store_true")
     ap.add_argument("--rough-amp", type=float, default=0.005,
