@@ -99,8 +99,9 @@ def ehl_legs(P, torch, synth, dev, args):
     P1025 = None
     for N, idx in zip((1025, 2049, 4097), groups):
         # active-set cap 8: a warm-started step's LCP needs about one solve,
-        # and a batched launch lasts as long as its slowest (cycling) system
-        opts = P.ehl.default_opts(max_newton=3000, lcp_max_iter=8)
+        # and a batched launch lasts as long as its slowest (cycling) system;
+        # an instance whose change sets no new minimum in 600 steps stops
+        opts = P.ehl.default_opts(max_newton=3000, lcp_max_iter=8, stall_steps=600)
         torch.cuda.synchronize()
         t0 = _t.perf_counter()
         r = P.ehl.solve_line(M[idx], L[idx], N, opts=opts)
@@ -120,7 +121,8 @@ def ehl_legs(P, torch, synth, dev, args):
         log(f"ehl sweep N={N}: {dt:.2f} s, converged {int(ok.sum())}/{len(idx)}")
     res.update(seconds=round(t_all, 3), converged=conv_all,
                solves_per_s=round(nb / t_all, 3), converged_per_s=round(conv_all / t_all, 3))
-    opts = P.ehl.default_opts(deform_prec=P.PREC_FP32, max_newton=3000, lcp_max_iter=8)
+    opts = P.ehl.default_opts(deform_prec=P.PREC_FP32, max_newton=3000, lcp_max_iter=8,
+                              stall_steps=600)
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
     r = P.ehl.solve_line(M[idx1025], L[idx1025], 1025, opts=opts)

@@ -219,6 +219,9 @@ typedef struct {
                             residual always has the full limiter): 0 exact
                             derivatives, 1 ratio phi(r) frozen at the current
                             iterate (eqs. 64-65), 2 first-order flux           */
+    int32_t stall_steps; /* line contact: stop an instance (status
+                            SYS_NEWTON_NOT_CONVERGED) once max|dP| has set no
+                            new minimum for this many steps; 0 = never       */
 } ehl_opts;
 
 /*

@@ -346,13 +346,14 @@ def lcp_exact(A, b, bounded):
 
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
-               rough=None, P=None, H0=None, limjac=None):
+               rough=None, P=None, H0=None, limjac=None, stall_steps=0):
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
     <= t, t = max(tol, 4 N eps) (status 0), when the linearised LCP hits its
-    active-set cap in LCP_FAIL_STEPS consecutive steps (status 3), else
-    status 6 after max_newton steps.  Returns a dict
+    active-set cap in LCP_FAIL_STEPS consecutive steps (status 3), when
+    max |P change| has set no new minimum for stall_steps steps (status 6;
+    0 = never), else status 6 after max_newton steps.  Returns a dict
     with P (N nodes), H0, H, Hmin (min over all nodes, first index), the
     number of steps and the status."""
     x, h = grid(N)
@@ -375,6 +376,7 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     tl = max(tol, 4.0 * N * np.finfo(np.float64).eps)
     it = 0
     fails = 0  # consecutive steps whose LCP hit the active-set cap
+    best, best_it = np.inf, 0
     for it in range(1, max_newton + 1):
         Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms,
                                    LIMJAC if limjac is None else limjac)
@@ -392,6 +394,10 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
             # solution the iteration reaches, the Newton iteration is lost
             status = LCP_NOT_CONVERGED
             break
+        if dP < best:
+            best, best_it = dP, it
+        elif stall_steps > 0 and it - best_it >= stall_steps:
+            break  # stalled (limit cycle or drift above the rounding floor): status 6
     H = film(P, H0, x, kvec, rough)
     if status == 0 and H.min() <= 0.0:
         status = 5

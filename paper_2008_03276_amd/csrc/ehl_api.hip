@@ -72,13 +72,13 @@ bool valid_opts(const ehl_opts* o)
             o->deform_prec == PREC_SPLIT_BF16) &&
            (o->lcp_prec == PREC_FP64 || o->lcp_prec == PREC_FP32_IR) &&
            o->steps_per_graph >= 1 && o->steps_per_graph <= 64 && o->limiter_jacobian >= 0 &&
-           o->limiter_jacobian <= 2;
+           o->limiter_jacobian <= 2 && o->stall_steps >= 0;
 }
 
 // Newton workspace layout (line contact)
 struct NewtonLayout {
     size_t kvec, hel, band, rhs, v, pn, bounded, direct, done, dP, lerr, offs, lst, lit, lfail,
-        lcp, total;
+        best, bstep, lcp, total;
 };
 
 size_t lcp_ws_bytes(int B, int n, int prec)
@@ -117,6 +117,8 @@ NewtonLayout newton_layout(const ehl_grid* g, int B, const ehl_opts* o)
     L.lst = take(b * sizeof(int32_t));
     L.lit = take(b * sizeof(int32_t));
     L.lfail = take(b * sizeof(int32_t));
+    L.best = take(b * sizeof(double));
+    L.bstep = take(b * sizeof(int32_t));
     L.lcp = take(lcp_ws_bytes(B, (int)n, o ? o->lcp_prec : PREC_FP64));
     L.total = p;
     return L;
@@ -142,6 +144,15 @@ __global__ void reopen_kernel(int B, uint8_t* done, int32_t* status)
     if (i < B && status[i] != SYS_NONFINITE) {
         done[i] = 0;
         status[i] = SYS_NEWTON_NOT_CONVERGED;
+    }
+}
+
+__global__ void stall_init_kernel(int B, double* best, int32_t* step, const int32_t* iters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) {
+        best[i] = INFINITY;
+        step[i] = iters[i];
     }
 }
 
@@ -647,6 +658,9 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     ua.load_err = lerr;
     ua.lcp_status = lst;
     ua.lcp_fails = reinterpret_cast<int32_t*>(ws + L.lfail);
+    ua.best_dP = reinterpret_cast<double*>(ws + L.best);
+    ua.best_step = reinterpret_cast<int32_t*>(ws + L.bstep);
+    ua.stall_steps = opts->stall_steps;
 
     auto one_step = [&](int dprec) -> int {
         int e;
@@ -676,6 +690,9 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
                                status);
         if (hipMemsetAsync(ua.lcp_fails, 0, (size_t)B * sizeof(int32_t), s) != hipSuccess)
             return PAQIF_EHIP;
+        // stall tracking restarts with every phase
+        hipLaunchKernelGGL(stall_init_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B,
+                           ua.best_dP, ua.best_step, iters);
         hipGraphExec_t exec = nullptr;
         bool use_graph = stream != nullptr;
         if (use_graph) {

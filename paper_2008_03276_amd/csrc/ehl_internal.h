@@ -50,6 +50,9 @@ struct LineUpdateArgs {
     double* load_err;    // B
     const int32_t* lcp_status;  // B, status of this step's LCP solve
     int32_t* lcp_fails;  // B, consecutive steps whose LCP hit its active-set cap
+    double* best_dP;     // B, smallest max |P change| of the phase so far
+    int32_t* best_step;  // B, step (iters count) at which it was reached
+    int stall_steps;     // stop after this many steps without a new minimum (0: never)
 };
 // An instance whose linearised LCP hits the active-set cap in this many
 // consecutive Newton steps stops with SYS_LCP_NOT_CONVERGED (the active-set

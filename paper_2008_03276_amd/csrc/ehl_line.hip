@@ -270,6 +270,13 @@ __global__ void __launch_bounds__(256) line_update_kernel(LineUpdateArgs a, doub
         } else if (fails >= kLcpFailSteps) {
             a.status[b] = SYS_LCP_NOT_CONVERGED;
             a.done[b] = 1;
+        } else if (dmax < a.best_dP[b]) {
+            a.best_dP[b] = dmax;
+            a.best_step[b] = a.iters[b];
+        } else if (a.stall_steps > 0 && a.iters[b] - a.best_step[b] >= a.stall_steps) {
+            // stalled: a limit cycle or a drift above the rounding floor
+            a.status[b] = SYS_NEWTON_NOT_CONVERGED;
+            a.done[b] = 1;
         }
     }
 }

@@ -213,3 +213,27 @@ def test_newton_stops_when_the_lcp_keeps_hitting_its_cap(monkeypatch):
     r = E.solve_line(20.0, 10.0, 65, max_newton=200)
     assert r["status"] == E.LCP_NOT_CONVERGED
     assert r["iters"] == 5 + E.LCP_FAIL_STEPS
+
+
+def test_newton_stops_when_the_change_stalls(monkeypatch):
+    """Status 6 before max_newton once max |P change| has set no new minimum
+    for stall_steps steps (the GPU driver applies the same rule): a change
+    that halves for 10 steps and then hovers above that minimum stops at step
+    10 + stall_steps; with the rule off it runs to max_newton."""
+    calls = {"n": 0}
+
+    def fake_step(P, H0, *args):
+        calls["n"] += 1
+        k = calls["n"]
+        size = 0.5 ** k if k <= 10 else 0.5 ** 10 * (1.5 if k % 2 else 1.2)
+        Pn = P.copy()
+        Pn[len(P) // 2] += size if k % 2 else -size
+        return Pn, H0, {}
+
+    monkeypatch.setattr(E, "newton_step", fake_step)
+    r = E.solve_line(20.0, 10.0, 65, max_newton=2000, stall_steps=300)
+    assert r["status"] == 6
+    assert r["iters"] == 10 + 300
+    calls["n"] = 0
+    r = E.solve_line(20.0, 10.0, 65, max_newton=500)
+    assert r["status"] == 6 and r["iters"] == 500
