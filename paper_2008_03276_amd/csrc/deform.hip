@@ -433,12 +433,12 @@ int launch_line_deform(int N, int B, int prec, const double* k, const double* P,
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
-// segments of the d range: enough waves to fill the chip at one instance
-// (about 1500 waves of 32 x 32 tiles), at most 32
+// segments of the d range: about 4096 waves of 32 x 32 tiles at one instance
+// (four per SIMD, to hide the operand-load latency), at most 64
 int point_segments(int Nx, int Ny)
 {
     const int tiles = ((Nx + 31) / 32) * ((Ny + 31) / 32);
-    return std::max(1, std::min(32, 1536 / std::max(1, tiles)));
+    return std::max(1, std::min(64, 4096 / std::max(1, tiles)));
 }
 
 size_t point_workspace_doubles(int Nx, int Ny, int B)
