@@ -108,14 +108,18 @@ int point_color_lines(int Nx, int Ny, int axis, int color)
     return first <= nl - 2 ? (nl - 2 - first) / 2 + 1 : 0;
 }
 
-// One thread per row of a line of the colour: band of -dR/dsigma, rhs and
-// the bounded mask (layout of paqif_solve_lcp, system = b * nlc + slot).
-__global__ void __launch_bounds__(128) point_assemble_kernel(PointAssembleArgs a)
+// Sixteen lanes per row of a line of the colour: lane 4 + s (s = -4..4)
+// computes band entry s of -dR/dsigma, the row's rhs R + sum_s A_s P_(p+s)
+// is a 16-lane shuffle sum, lane 4 writes it and the bounded mask (layout of
+// paqif_solve_lcp, system = b * nlc + slot).  One thread per row had left a
+// few hundred dependent loads per thread on a few waves per CU.
+__global__ void __launch_bounds__(256) point_assemble_kernel(PointAssembleArgs a)
 {
     const LineGeo g = line_geo(a.Nx, a.Ny, a.axis, a.color);
     const int n = g.nn - 2;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (int64_t)a.B * g.nlc * n) return;
+    const int64_t tid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;  // row
+    const int lane_s = (int)(threadIdx.x & 15) - 4;  // band offset of this lane (-4..11)
+    if (tid >= (int64_t)a.B * g.nlc * n) return;     // whole 16-lane groups
     const int r = (int)(tid % n);
     const int64_t sys = tid / n;
     const int b = (int)(sys / g.nlc), slot = (int)(sys % g.nlc);
@@ -202,10 +206,13 @@ __global__ void __launch_bounds__(128) point_assemble_kernel(PointAssembleArgs a
 
     double* brow = a.band + (sys * n + r) * 9;
     const int64_t ro = sys * n + r;
+    const bool active = lane_s <= 4;
     if (a.axis == 1 && dist(l, p)) {  // y-lines leave weighted-change nodes alone
-        for (int s = 0; s < 9; s++) brow[s] = s == 4 ? 1.0 : 0.0;
-        a.rhs[ro] = Pn(l, p);
-        a.bounded[ro] = 0;
+        if (active) brow[lane_s + 4] = lane_s == 0 ? 1.0 : 0.0;
+        if (lane_s == 0) {
+            a.rhs[ro] = Pn(l, p);
+            a.bounded[ro] = 0;
+        }
         return;
     }
     const double eph = 0.5 * (eps(l, p) + eps(l, p + 1));
@@ -223,12 +230,12 @@ __global__ void __launch_bounds__(128) point_assemble_kernel(PointAssembleArgs a
         if (l - 1 >= 1)
             limiter_jacobian(lj, rH(l - 1, p) - rH(l - 2, p), rH(l, p) - rH(l - 1, p), pa1, pb1);
     }
-    double rhs = R;
-#pragma unroll
-    for (int s = -4; s <= 4; s++) {
+    double contrib = 0.0;
+    {
+        const int s = lane_s;
         const int k = p + s;
         double Av = 0.0;
-        if (k >= 1 && k <= nn - 2) {
+        if (active && k >= 1 && k <= nn - 2) {
             const double de_p = 0.5 * (dEps(p, k) + dEps(p + 1, k));
             const double de_m = 0.5 * (dEps(p - 1, k) + dEps(p, k));
             const double dPi = dPd(0, p, k);
@@ -264,22 +271,26 @@ __global__ void __launch_bounds__(128) point_assemble_kernel(PointAssembleArgs a
                 conv = (fi - fm) / h_p;
             }
             Av = -(along + across - conv);
-            rhs += Av * Pn(l, k);
+            contrib = Av * Pn(l, k);
         }
-        brow[s + 4] = Av;
+        if (active) brow[s + 4] = Av;
     }
-    a.rhs[ro] = rhs;
-    a.bounded[ro] = (!dist(l, p) && !dist(l, p - 1) && !dist(l, p + 1)) ? 1 : 0;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) contrib += __shfl_xor(contrib, m, 16);
+    if (lane_s == 0) {
+        a.rhs[ro] = R + contrib;
+        a.bounded[ro] = (!dist(l, p) && !dist(l, p - 1) && !dist(l, p + 1)) ? 1 : 0;
+    }
 }
 
 int launch_point_assemble(const PointAssembleArgs& a, hipStream_t s)
 {
     const int nlc = point_color_lines(a.Nx, a.Ny, a.axis, a.color);
     const int n = (a.axis == 0 ? a.Nx : a.Ny) - 2;
-    const int64_t cnt = (int64_t)a.B * nlc * n;
+    const int64_t cnt = (int64_t)a.B * nlc * n;  // rows, 16 lanes each
     if (cnt <= 0) return PAQIF_OK;
-    hipLaunchKernelGGL(point_assemble_kernel, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0,
-                       s, a);
+    hipLaunchKernelGGL(point_assemble_kernel, dim3((unsigned)((cnt * 16 + 255) / 256)), dim3(256),
+                       0, s, a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
