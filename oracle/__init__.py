@@ -11,6 +11,8 @@ Parts:
   * ``deform.py``: elastic deformation kernels and sums (Sec. 3.3.1).
   * ``ehl_line.py`` / ``ehl_point.py``: EHL residual, band Jacobian,
     hybrid Newton line iteration and load balance (Sec. 3.3).
+  * ``convdiff.py``: the linear convection-diffusion workload of the
+    numerical results (kappa-schemes, line relaxation with banded solves).
 """
 import ctypes
 import os
