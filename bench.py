@@ -143,6 +143,49 @@ def ehl_legs(P, torch, synth, dev, args):
         out["adjoint_N2049"] = adjoint_leg(P, torch, synth, args)
     if not args.no_point:
         out[f"point_{args.point_n}"] = point_leg(P, torch, args)
+    out["convdiff"] = convdiff_leg(P, torch, args)
+    return out
+
+
+def convdiff_leg(P, torch, args):
+    """Convection-diffusion workload (linear case study of the numerical
+    results): 257 x 257 nodes, eps = 1e-6, kappa in {0, 1/3, -1}, line
+    relaxation to max defect <= 1e-10 max|f|; iterations, time, line solves
+    per second and the max error against x^4 + y^4.  With the CPU leg on, the
+    oracle's time at 65 x 65 nodes beside the GPU's at the same size."""
+    import time as _t
+    out = {}
+    x = None
+    for n in (257, 65):
+        x = np.linspace(-1.0, 1.0, n)
+        ex = x[:, None] ** 4 + x[None, :] ** 4
+        ws = torch.empty(P.lib().cd_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        res_n = {}
+        for kappa in (0.0, 1.0 / 3.0, -1.0):
+            f, u = P.convdiff.example(n)
+            P.convdiff.line_relax(f, u.clone(), kappa, tol=1e-10, max_iter=2, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = _t.perf_counter()
+            it, res = P.convdiff.line_relax(f, u, kappa, tol=1e-10, max_iter=2000, workspace=ws)
+            torch.cuda.synchronize()
+            dt = _t.perf_counter() - t0
+            err = float(np.abs(u.cpu().numpy() - ex)[1:-1, 1:-1].max() / ex[1:-1, 1:-1].max())
+            res_n[f"kappa_{kappa:.3f}"] = dict(
+                iterations=it, ms=round(dt * 1e3, 3), ms_per_iteration=round(dt * 1e3 / it, 4),
+                line_solves_per_s=round(2 * (n - 2) * it / dt, 1), max_defect=res,
+                linf_rel_error=err)
+        out[f"n{n}"] = res_n
+        log(f"convdiff n={n}: " + ", ".join(f"{k} {v['iterations']} it {v['ms']} ms"
+                                             for k, v in res_n.items()))
+    if not args.no_cpu:
+        from oracle import convdiff as OC
+        cpu = {}
+        for kappa in (0.0, 1.0 / 3.0, -1.0):
+            t0 = _t.perf_counter()
+            r = OC.solve(65, kappa, tol=1e-10, max_iter=2000)
+            cpu[f"kappa_{kappa:.3f}"] = dict(iterations=r["iters"],
+                                             ms=round((_t.perf_counter() - t0) * 1e3, 1))
+        out["oracle_n65"] = cpu
     return out
 
 

@@ -352,6 +352,43 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid *grid, const ehl_param
                       double rtol, int max_iter, double *dM, double *dL, double *drough,
                       int32_t *status, int32_t *iters, void *workspace, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Linear convection-diffusion workload (Sec. 4, linear case study of
+ * Example 1, kappa-schemes of Sec. 2): the banded solver on non-symmetric,
+ * non-complementarity line systems.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * (a u)_x + (b u)_y - eps (u_xx + u_yy) = f on [-1, 1]^2, Dirichlet data, a,
+ * b > 0 constant (the paper does not give a(x, y), b(x, y)).  Grid n x n
+ * nodes, h = 2/(n-1), arrays row major: u[i*n + j] = u(x_i, y_j).
+ * Convection: kappa-scheme flux difference c (u_{i+1/2} - u_{i-1/2}) / h,
+ * u_{i+1/2} = u_i + (1+kappa)/4 (u_{i+1} - u_i) + (1-kappa)/4 (u_i - u_{i-1}),
+ * ghost u_{-1} = 2 u_0 - u_1 next to the inflow boundary; diffusion 5-point.
+ *
+ * cd_example: f for the exact solution u = x^4 + y^4 and the start iterate
+ * (exact boundary values, zero inside).  f, u: DEVICE n x n, out.
+ *
+ * cd_line_relax: line relaxation as a defect correction (the paper's line
+ * splittings): a half-step solves, on all n-2 lines of one direction in one
+ * batched PAQIF launch (plain linear mode, half-bandwidth 2), M sigma =
+ * f - L_h u with M the line's whole operator along the line plus the
+ * diagonal of the across-line part, then u += omega sigma; x- and y-lines
+ * alternate.  Stops after the first full iteration with
+ * max|f - L_h u| <= tol max|f| (interior nodes), or after max_iter.
+ *  n >= 5; -1 <= kappa < 1; eps >= 0; a, b > 0; 0 < omega < 2.
+ *  f: DEVICE n x n in;  u: DEVICE n x n in/out (boundary values are kept).
+ *  iters, defect: HOST out (iterations done, final max |f - L_h u|; a
+ *  non-finite defect stops the iteration and is returned as infinity).
+ *  workspace: DEVICE, cd_workspace_bytes(n) bytes.  Synchronises the stream
+ *  once per iteration (the stopping test is read on the host).
+ */
+size_t cd_workspace_bytes(int n);
+int cd_example(int n, double eps, double a, double b, double *f, double *u, void *stream);
+int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a, double b,
+                  double omega, double tol, int max_iter, const double *f, double *u,
+                  int32_t *iters, double *defect, void *workspace, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,5 +10,6 @@ from ._binding import (LCP_CLIP, LCP_EXACT, LCP_LINEAR, PREC_FP32, PREC_FP32_IR,
                        SYS_ZERO_PIVOT, LibraryMissing, lib)
 from . import paqif
 from . import ehl
+from . import convdiff
 
-__all__ = ["lib", "paqif", "ehl", "LibraryMissing"]
+__all__ = ["lib", "paqif", "ehl", "convdiff", "LibraryMissing"]

@@ -102,6 +102,10 @@ def lib():
         "ehl_adjoint_solve": ([vp, ctypes.POINTER(EhlGrid), vp, ctypes.c_int,
                                ctypes.POINTER(EhlOpts), vp, vp, vp, vp, vp, vp, d, ctypes.c_int,
                                vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "cd_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
+        "cd_example": ([ctypes.c_int, d, d, d, vp, vp, vp], ctypes.c_int),
+        "cd_line_relax": ([vp, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp, vp,
+                           ctypes.POINTER(i32), ctypes.POINTER(d), vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
