@@ -825,7 +825,20 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
     // R rows per lane per pass; all their loads (clamped, valid addresses)
     // are issued before any is used, so a pass waits for memory once
     constexpr int R = BW <= 5 ? 4 : (BW <= 9 ? 2 : 1);
-    if (live) {
+    if (live && !update && !(write_w && wout)) {
+        // nothing to store (plain linear solve without w): only the
+        // finiteness check of u
+        constexpr int RU = 8;
+        const int nm = v.n - 1;
+        for (int i0 = ls; i0 < v.n; i0 += RU * G::LPS) {
+            double uv[RU];
+#pragma unroll
+            for (int r = 0; r < RU; r++) uv[r] = u[min(i0 + r * G::LPS, nm)];
+#pragma unroll
+            for (int r = 0; r < RU; r++)
+                if (i0 + r * G::LPS < v.n && !isfinite(uv[r])) nf = 1;
+        }
+    } else if (live) {
         const int nm = v.n - 1;
         for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
             double av[R][BW], uv[R][BW], bv[R];
