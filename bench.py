@@ -269,6 +269,8 @@ def main():
                     help="nodes per side of the point-contact leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (scale of the HBM byte counters)")
+    ap.add_argument("--convdiff-only", action="store_true",
+                    help="run only the convection-diffusion leg (one JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "
@@ -290,6 +292,9 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 8}))
         return
     P.lib()
+    if args.convdiff_only:
+        print(json.dumps({"convdiff": convdiff_leg(P, torch, args)}))
+        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     batches = {}
