@@ -113,12 +113,29 @@ def vanleer(dm, dp):
     return psi, dpsi_dp, dpsi_dm
 
 
-def limiter_jacobian(dm, dp, mode):
+def slope(dm, dp, kappa=None):
+    """Slope psi of the convective face value (rH)_{i+1/2} = (rH)_i + psi/2
+    and its partials wrt D+ and D-: the van Leer limited slope (TVD, the
+    method's default), or with kappa given the kappa-scheme of Sec. 2 (eqs.
+    57-59), psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear and unlimited."""
+    if kappa is None:
+        return vanleer(dm, dp)
+    return (0.5 * (1.0 + kappa) * dp + 0.5 * (1.0 - kappa) * dm,
+            np.full(np.shape(dp), 0.5 * (1.0 + kappa)), np.full(np.shape(dm), 0.5 * (1.0 - kappa)))
+
+
+def limiter_jacobian(dm, dp, mode, kappa=None):
     """Limiter coefficients (pa = d/dD+, pb = d/dD-) used in the Newton
     matrix; the residual always uses psi.  mode 0: exact derivatives of psi;
     1: the ratio frozen at the current iterate, psi = phi(r) D- with r = D+/D-,
     phi(r) = 2r/(1+r) held fixed (eqs. 64-65 evaluate r from the old film), so
-    pa = 0, pb = phi; 2: first-order upwind flux, pa = pb = 0."""
+    pa = 0, pb = phi; 2: first-order upwind flux, pa = pb = 0.  For the
+    kappa-scheme (linear) modes 0 and 1 are both its exact constants."""
+    if kappa is not None:
+        _, pa, pb = slope(dm, dp, kappa)
+        if mode == 2:
+            return np.zeros_like(pa), np.zeros_like(pb)
+        return pa, pb
     _, pa, pb = vanleer(dm, dp)
     if mode == 0:
         return pa, pb
@@ -136,12 +153,13 @@ def state(P, H, ph, lam):
     return dict(rho=rho, drho=drho, dlneta=dlneta, eta=eta, eps=eps, rH=rho * H, H=H)
 
 
-def residual(P, H, ph, lam, h):
-    """R_i for interior i (array of length N-2), plus the state."""
+def residual(P, H, ph, lam, h, kappa=None):
+    """R_i for interior i (array of length N-2), plus the state (convective
+    slope: van Leer, or the kappa-scheme when kappa is given)."""
     s = state(P, H, ph, lam)
     eps, rH = s["eps"], s["rH"]
     epsh = 0.5 * (eps[:-1] + eps[1:])             # faces i+1/2, i = 0..N-2
-    psi, _, _ = vanleer(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1])
+    psi, _, _ = slope(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1], kappa)
     f = np.empty(len(P) - 1)
     f[0] = rH[0]
     f[1:] = rH[1:-1] + 0.5 * psi
@@ -150,7 +168,7 @@ def residual(P, H, ph, lam, h):
     return R, s
 
 
-def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0):
+def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa=None):
     """Band of dR_i/dsigma_j (interior rows and columns) for the change
     delta = D sigma (column j of D: e_j for a direct node, e_j - (e_{j-1} +
     e_{j+1})/2 for a distributive one; boundary nodes stay fixed).
@@ -212,7 +230,7 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0):
     epsh = 0.5 * (eps[:-1] + eps[1:])
     dm = rH[1:-1] - rH[:-2]
     dp = rH[2:] - rH[1:-1]
-    pa, pb = limiter_jacobian(dm, dp, limjac)  # index t -> node t+1
+    pa, pb = limiter_jacobian(dm, dp, limjac, kappa)  # index t -> node t+1
     i = np.arange(1, N - 1)
     J = np.zeros((n, 9))
     for s in range(-4, 5):
@@ -296,15 +314,17 @@ def hybrid_direct(P, eps, h):
     return direct | near
 
 
-def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2, limjac=LIMJAC):
-    """One Lhs1 step; returns (P_new, H0_new, info)."""
+def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2, limjac=LIMJAC,
+                kappa=None):
+    """One Lhs1 step (kappa given: the kappa-scheme convection of Sec. 2
+    instead of the limited slope); returns (P_new, H0_new, info)."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
-    R, st = residual(P, H, ph, lam, h)
+    R, st = residual(P, H, ph, lam, h, kappa)
     direct_all = hybrid_direct(P, st["eps"], h)
     direct = direct_all[1:-1]
     D = distributive_matrix_band(direct)
-    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac)
+    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac, kappa)
     Pi = P[1:-1]
     b = band_matvec(A, Pi) + R
     nb = np.concatenate([[True], direct, [True]])
@@ -320,11 +340,11 @@ def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2
     return Pn, H0n, info
 
 
-def complementarity(P, H0, x, h, kvec, M, L, rough=None):
+def complementarity(P, H0, x, h, kvec, M, L, rough=None, kappa=None):
     """max_i |min(P_i, L_i)| over interior nodes and the load error."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
-    R, _ = residual(P, H, ph, lam, h)
+    R, _ = residual(P, H, ph, lam, h, kappa)
     Lop = -R
     return np.abs(np.minimum(P[1:-1], Lop)).max(), np.pi / 2 - h * P.sum(), Lop, H
 
@@ -346,7 +366,7 @@ def lcp_exact(A, b, bounded):
 
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
-               rough=None, P=None, H0=None, limjac=None, stall_steps=0):
+               rough=None, P=None, H0=None, limjac=None, stall_steps=0, kappa=None):
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
@@ -379,7 +399,7 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     best, best_it = np.inf, 0
     for it in range(1, max_newton + 1):
         Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms,
-                                   LIMJAC if limjac is None else limjac)
+                                   LIMJAC if limjac is None else limjac, kappa)
         dP = np.abs(Pn - P).max()
         P = Pn
         fails = fails + 1 if last[0] == LCP_NOT_CONVERGED else 0

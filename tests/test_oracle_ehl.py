@@ -86,7 +86,7 @@ def test_point_hertz_identity():
     assert errs[1] < errs[0] < 0.05
 
 
-def _fd_sigma_jacobian(P, H, ph, lam, h, D, T):
+def _fd_sigma_jacobian(P, H, ph, lam, h, D, T, kappa=None):
     """Central differences of sigma -> R(P + D sigma, H + T sigma)."""
     n = len(P) - 2
     J = np.zeros((n, n))
@@ -96,14 +96,15 @@ def _fd_sigma_jacobian(P, H, ph, lam, h, D, T):
         s[k] = e
         Pp = P.copy(); Pp[1:-1] += D @ s
         Pm = P.copy(); Pm[1:-1] -= D @ s
-        Rp, _ = E.residual(Pp, H + T @ np.concatenate([[0], s, [0]]), ph, lam, h)
-        Rm, _ = E.residual(Pm, H - T @ np.concatenate([[0], s, [0]]), ph, lam, h)
+        Rp, _ = E.residual(Pp, H + T @ np.concatenate([[0], s, [0]]), ph, lam, h, kappa)
+        Rm, _ = E.residual(Pm, H - T @ np.concatenate([[0], s, [0]]), ph, lam, h, kappa)
         J[:, k] = (Rp - Rm) / (2 * e)
     return J
 
 
-@pytest.mark.parametrize("kterms", [1, 2])
-def test_band_jacobian_matches_finite_differences(kterms):
+@pytest.mark.parametrize("kterms,kappa", [(1, None), (2, None), (2, 0.0), (2, 1.0 / 3.0),
+                                          (1, -1.0)])
+def test_band_jacobian_matches_finite_differences(kterms, kappa):
     N = 65
     M, L = 20.0, 10.0
     x, h = E.grid(N)
@@ -133,8 +134,8 @@ def test_band_jacobian_matches_finite_differences(kterms):
         for k in range(1, N - 1):
             if abs(m - k) <= kterms:
                 T[m, k] = KD[m, k]
-    Jfd = _fd_sigma_jacobian(P, H, ph, lam, h, D, T)
-    J = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac=0)
+    Jfd = _fd_sigma_jacobian(P, H, ph, lam, h, D, T, kappa)
+    J = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac=0, kappa=kappa)
     Jd = np.zeros((n, n))
     for r in range(n):
         for s in range(-4, 5):
@@ -237,3 +238,44 @@ def test_newton_stops_when_the_change_stalls(monkeypatch):
     calls["n"] = 0
     r = E.solve_line(20.0, 10.0, 65, max_newton=500)
     assert r["status"] == 6 and r["iters"] == 500
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1.0 / 3.0, -1.0, 0.5])
+def test_kappa_slope_closed_form_on_a_cubic(kappa):
+    """The kappa-scheme face values (rH)_{i+1/2} = (rH)_i + psi/2 of Sec. 2
+    on rH = x^3: the flux difference is 3 x^2 + h^2 (3 kappa - 1)/2 exactly
+    (third order only for kappa = 1/3); swapping the (1+kappa), (1-kappa)
+    weights or halving psi fails it."""
+    h = 0.01
+    x = h * np.arange(-20, 21)
+    rH = x ** 3
+    psi, _, _ = E.slope(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1], kappa)
+    f = rH[1:-1] + 0.5 * psi                   # faces i+1/2 for nodes 1..n-2
+    diff = (f[1:] - f[:-1]) / h                # at nodes 2..n-2
+    ref = 3 * x[2:-1] ** 2 + h * h * (3 * kappa - 1) / 2
+    assert np.abs(diff - ref).max() <= 1e-10
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1.0 / 3.0, -1.0])
+def test_converged_config1_with_kappa_scheme(kappa):
+    """Config 1 with the kappa-scheme convection: complementarity, load
+    balance, and the face-flux invariant on the pressurised run."""
+    r = E.solve_line(20.0, 10.0, 257, tol=1e-13, max_newton=2000, kappa=kappa)
+    assert r["status"] == 0
+    P, H, h = r["P"], r["H"], r["h"]
+    comp, load_err, Lop, _ = E.complementarity(P, r["H0"], r["x"], h, r["kvec"], 20.0, 10.0,
+                                                kappa=kappa)
+    scale = np.abs(Lop).max()
+    assert abs(load_err) < 1e-12 and comp < 1e-10 * scale
+    assert Lop[P[1:-1] == 0].min() >= -1e-10 * scale
+    _, lam, ph = E.moes_line(20.0, 10.0)
+    st = E.state(P, H, ph, lam)
+    eps, rH = st["eps"], st["rH"]
+    psi, _, _ = E.slope(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1], kappa)
+    f = np.empty(len(P) - 1)
+    f[0] = rH[0]
+    f[1:] = rH[1:-1] + 0.5 * psi
+    q = f - 0.5 * (eps[:-1] + eps[1:]) * (P[1:] - P[:-1]) / h
+    pos = np.where(P > 0)[0]
+    qq = q[pos[0] - 1:pos[-1] + 1]
+    assert (qq.max() - qq.min()) < 1e-9 * np.abs(qq).max()
