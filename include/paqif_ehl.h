@@ -222,6 +222,13 @@ typedef struct {
     int32_t stall_steps; /* line contact: stop an instance (status
                             SYS_NEWTON_NOT_CONVERGED) once max|dP| has set no
                             new minimum for this many steps; 0 = never       */
+    int32_t convection;  /* convective face value (rho H)_{i+1/2} = (rho H)_i
+                            + psi/2: 0 van Leer limited slope (TVD, default);
+                            1 kappa-scheme psi = (1+kappa)/2 D+ + (1-kappa)/2
+                            D- (Sec. 2, eqs. 57-59; line contact only: the
+                            point contact and the adjoint return
+                            PAQIF_EINVAL)                                    */
+    double kappa;        /* -1 <= kappa <= 1 for convection 1                */
 } ehl_opts;
 
 /*

@@ -43,7 +43,8 @@ class EhlOpts(ctypes.Structure):
                 ("lcp_max_iter", ctypes.c_int32), ("deform_prec", ctypes.c_int32),
                 ("lcp_prec", ctypes.c_int32), ("steps_per_graph", ctypes.c_int32),
                 ("start_rule", ctypes.c_int32), ("limiter_jacobian", ctypes.c_int32),
-                ("stall_steps", ctypes.c_int32)]
+                ("stall_steps", ctypes.c_int32), ("convection", ctypes.c_int32),
+                ("kappa", ctypes.c_double)]
 
 
 class LibraryMissing(RuntimeError):

@@ -605,6 +605,7 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid* grid, const ehl_param
     if (!handle || !adj_valid_grid(grid) || B < 0 || !opts) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
     if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
+    if (opts->convection != 0) return PAQIF_EINVAL;  // the adjoint differentiates van Leer
     if (!(rtol > 0.0 && rtol < 1.0) || max_iter < 1) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H0 || !dM || !dL || !drough || !status || !iters || !workspace)
@@ -634,6 +635,8 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid* grid, const ehl_param
     aa.B = B;
     aa.kterms = opts->kernel_terms;
     aa.limjac = opts->limiter_jacobian;
+    aa.conv = 0;
+    aa.kappa = 0.0;
     aa.h = h;
     aa.x0 = grid->x0;
     aa.switch_ratio = opts->switch_ratio;

@@ -63,6 +63,11 @@ void host_kernel_head(double h, double kap[4])
 // 1.5e-13 at n = 1025 and 6e-13 at n = 2049, which a fixed 1e-13 never meets).
 double fp64_floor(int n) { return 4.0 * n * 2.220446049250313e-16; }
 
+bool valid_convection(const ehl_opts* o)
+{
+    return o->convection == 0 || (o->convection == 1 && o->kappa >= -1.0 && o->kappa <= 1.0);
+}
+
 bool valid_opts(const ehl_opts* o)
 {
     return o && o->omega > 0 && o->omega <= 1.0 && o->c_h0 > 0 && o->tol > 0 &&
@@ -72,7 +77,7 @@ bool valid_opts(const ehl_opts* o)
             o->deform_prec == PREC_SPLIT_BF16) &&
            (o->lcp_prec == PREC_FP64 || o->lcp_prec == PREC_FP32_IR) &&
            o->steps_per_graph >= 1 && o->steps_per_graph <= 64 && o->limiter_jacobian >= 0 &&
-           o->limiter_jacobian <= 2 && o->stall_steps >= 0;
+           o->limiter_jacobian <= 2 && o->stall_steps >= 0 && valid_convection(o);
 }
 
 // Newton workspace layout (line contact)
@@ -504,6 +509,7 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_p
     if (!handle || !valid_line(grid) || B < 0 || !opts) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
     if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
+    if (!valid_convection(opts)) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded) return PAQIF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -513,6 +519,8 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_p
     a.B = B;
     a.kterms = opts->kernel_terms;
     a.limjac = opts->limiter_jacobian;
+    a.conv = opts->convection;
+    a.kappa = opts->kappa;
     a.h = hx_of(grid);
     a.x0 = grid->x0;
     a.switch_ratio = opts->switch_ratio;
@@ -552,6 +560,7 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H0 || !Hmin || !status || !iters || !workspace) return PAQIF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (valid_point(grid) && opts->convection != 0) return PAQIF_EINVAL;  // van Leer only
     if (valid_point(grid)) {
         if (rough) return PAQIF_EINVAL;  // roughness is a line-contact input
         return point_newton(handle, grid, params, B, opts, P, H0, H, Hmin, status, iters,
@@ -593,6 +602,8 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     aa.B = B;
     aa.kterms = opts->kernel_terms;
     aa.limjac = opts->limiter_jacobian;
+    aa.conv = opts->convection;
+    aa.kappa = opts->kappa;
     aa.h = h;
     aa.x0 = grid->x0;
     aa.switch_ratio = opts->switch_ratio;
@@ -760,6 +771,7 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
         return PAQIF_EINVAL;
     if ((axis != 0 && axis != 1) || (color != 0 && color != 1)) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
+    if (opts->convection != 0) return PAQIF_EINVAL;  // point contact: van Leer only
     if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded || !workspace)

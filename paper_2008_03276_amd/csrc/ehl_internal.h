@@ -19,6 +19,8 @@ int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const
 // ehl_line.hip
 struct LineAssembleArgs {
     int N, B, kterms, limjac;
+    int conv;       // 0 van Leer slope, 1 kappa-scheme
+    double kappa;
     double h, x0, switch_ratio;
     const ehl_params* params;  // device, B
     const double* kvec;        // N (device) or null: use kap

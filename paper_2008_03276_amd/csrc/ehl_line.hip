@@ -139,8 +139,7 @@ __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
     // limiter at node tt (1 <= tt <= N-2)
     auto limiter = [&](int tt, double& psi, double& pa, double& pb) {
         const double dm = rHn(tt) - rHn(tt - 1), dp = rHn(tt + 1) - rHn(tt);
-        van_leer(dm, dp, psi, pa, pb);
-        limiter_jacobian(a.limjac, dm, dp, pa, pb);
+        convective_slope(a.conv, a.kappa, a.limjac, dm, dp, psi, pa, pb);
     };
     // residual
     const double eph = 0.5 * (epsn(i) + epsn(i + 1));

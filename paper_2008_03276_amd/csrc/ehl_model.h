@@ -90,4 +90,22 @@ PQ_DEV void limiter_jacobian(int mode, double dm, double dp, double& pa, double&
     pb = (mode == 1 && dm * dp > 0.0) ? 2.0 * dp / (dm + dp) : 0.0;
 }
 
+// Convective slope psi of the face value (rho H)_{i+1/2} = (rho H)_i + psi/2
+// and the coefficients (pa, pb) of the Newton matrix: conv 0 the van Leer
+// slope with limiter_jacobian(limjac); conv 1 the kappa-scheme (Sec. 2,
+// eqs. 57-59) psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear, whose exact
+// coefficients are used for limjac 0 and 1 (limjac 2: first-order flux).
+PQ_DEV void convective_slope(int conv, double kappa, int limjac, double dm, double dp,
+                             double& psi, double& pa, double& pb)
+{
+    if (conv == 1) {
+        psi = 0.5 * (1.0 + kappa) * dp + 0.5 * (1.0 - kappa) * dm;
+        pa = limjac == 2 ? 0.0 : 0.5 * (1.0 + kappa);
+        pb = limjac == 2 ? 0.0 : 0.5 * (1.0 - kappa);
+        return;
+    }
+    van_leer(dm, dp, psi, pa, pb);
+    limiter_jacobian(limjac, dm, dp, pa, pb);
+}
+
 }  // namespace pq

@@ -168,3 +168,58 @@ def test_newton_not_converged_status(gpu):
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 6
     assert int(r["iters"][0]) == 3
+
+
+KAPPA_CASES = [0.0, 1.0 / 3.0, -1.0]
+
+
+@pytest.mark.parametrize("N", [65, 700])
+@pytest.mark.parametrize("limjac", [0, 2])
+@pytest.mark.parametrize("kappa", KAPPA_CASES)
+def test_line_assembly_kappa_scheme(gpu, N, limjac, kappa):
+    """kappa-scheme convection (Sec. 2): band, residual, rhs and masks of the
+    GPU assembly against the oracle's, same bounds as the van Leer case."""
+    P = gpu.ehl
+    Ms, Ls, H0s = [20.0, 100.0], [10.0, 5.0], [-0.3, -0.55]
+    x, h, kvec, _ = _state(N, 0)
+    Ps = np.stack([_state(N, s)[3] for s in range(2)])
+    Hel = np.stack([odef.line_deformation(Ps[b], h) for b in range(2)])
+    opts = P.default_opts(kernel_terms=2, limiter_jacobian=limjac, convection=1, kappa=kappa)
+    r = P.assemble(P.line_grid(N), P.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
+                   torch.as_tensor(Hel, device=DEV),
+                   torch.as_tensor(H0s, dtype=torch.float64, device=DEV), opts)
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    for b in range(2):
+        _, lam, ph = OE.moes_line(Ms[b], Ls[b])
+        H = H0s[b] + 0.5 * x * x + Hel[b]
+        R, st = OE.residual(Ps[b], H, ph, lam, h, kappa)
+        direct = OE.hybrid_direct(Ps[b], st["eps"], h)[1:-1]
+        A = -OE.jacobian_band(Ps[b], H, ph, lam, h, kvec, direct, 2, limjac, kappa)
+        rhs = OE.band_matvec(A, Ps[b][1:-1]) + R
+        scale = np.abs(A).max(axis=1, keepdims=True)
+        assert (np.abs(g["band"][b] - A) <= 1e-11 * scale + 1e-14 * np.abs(A).max()).all()
+        assert _rel(g["R"][b], R) < 1e-11
+        assert np.abs(g["rhs"][b] - rhs).max() <= 1e-11 * max(1, np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("kappa", KAPPA_CASES)
+def test_newton_config1_kappa_scheme_matches_oracle(gpu, kappa):
+    P = gpu.ehl
+    o = OE.solve_line(20.0, 10.0, 257, kappa=kappa)
+    assert o["status"] == 0
+    r = P.solve_line([20.0], [10.0], 257, opts=P.default_opts(convection=1, kappa=kappa))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    assert _rel(r["P"][0].cpu().numpy(), o["P"]) < 1e-10
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
+
+
+def test_kappa_scheme_rejected_where_not_supported(gpu):
+    P = gpu.ehl
+    # the library refuses the options (the workspace query returns 0 for
+    # invalid options, the solve returns PAQIF_EINVAL)
+    with pytest.raises((RuntimeError, ValueError)):  # point contact: van Leer only
+        P.solve_point([200.0], [10.0], 17, 17, opts=P.default_opts(convection=1, kappa=0.0))
+    with pytest.raises((RuntimeError, ValueError)):  # out of range
+        P.solve_line([20.0], [10.0], 65, opts=P.default_opts(convection=1, kappa=1.5))
