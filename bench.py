@@ -88,6 +88,20 @@ def ehl_legs(P, torch, synth, dev, args):
     out["config1"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 3),
                           status=int(r["status"][0]), newton_steps=int(r["iters"][0]),
                           H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]))
+    # the same contact with the kappa-scheme convection instead of van Leer
+    kap = {}
+    for kappa in (0.0, 1.0 / 3.0, -1.0):
+        o = P.ehl.default_opts(convection=1, kappa=kappa)
+        P.ehl.solve_line([20.0], [10.0], 257, opts=o)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        r = P.ehl.solve_line([20.0], [10.0], 257, opts=o)
+        torch.cuda.synchronize()
+        kap[f"kappa_{kappa:.3f}"] = dict(seconds=round(_t.perf_counter() - t0, 4),
+                                         status=int(r["status"][0]),
+                                         newton_steps=int(r["iters"][0]),
+                                         H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]))
+    out["config1_kappa_scheme"] = kap
     # sweep: nb instances, N drawn from {1025, 2049, 4097} (grouped by N,
     # one batched solve per group), FP64; the FP32-deformation variant
     # (+ FP64 refresh) on the N = 1025 group
