@@ -11,6 +11,8 @@ Parts:
   * ``deform.py``: elastic deformation kernels and sums (Sec. 3.3.1).
   * ``ehl_line.py`` / ``ehl_point.py``: EHL residual, band Jacobian,
     hybrid Newton line iteration and load balance (Sec. 3.3).
+  * ``partitioned.py``: the partitioned PAQIF solve of one long band
+    system (Sec. 2.1-2.2, Steps 1-7).
   * ``convdiff.py``: the linear convection-diffusion workload of the
     numerical results (kappa-schemes, line relaxation with banded solves).
 """

@@ -10,6 +10,9 @@ Workloads (the paper publishes no data set; these stand in for it):
   * banded LCP batches: symmetric band matrices with off-diagonals U(-1, 1)
     and diagonal = sum of |off-diagonals| + U(0.5, 1.5); right-hand side
     N(mean, 1); sizes uniform in [nmin, nmax];
+  * one long band system for the partitioned solve: off-diagonals
+    U(-1, 1) drawn independently above and below (not symmetric), diagonal
+    as above, right-hand side N(mean, 1);
   * EHL line-contact sweeps: Moes M log-uniform, L uniform;
   * roughness: a sinusoid of given amplitude and wavelength.
 """
@@ -18,6 +21,7 @@ import numpy as np
 WL_LCP = 2
 WL_EHL_SWEEP = 3
 WL_EHL_ADJOINT = 4
+WL_LONG = 5
 
 
 def lcp_sizes(count, nmin=513, nmax=4097, seed=0):
@@ -43,6 +47,20 @@ def lcp_system(n, q, seed=0, item=0, rhs_mean=0.0):
             band[d:, q - d] = up[: n - d, d - 1]      # a(i, i-d) = a(i-d, i)
     off = np.abs(band).sum(axis=1)
     band[:, q] = off + rng.uniform(0.5, 1.5, size=n)
+    f = rng.normal(rhs_mean, 1.0, size=n)
+    return band, f
+
+
+def long_system(n, q, seed=0, rhs_mean=0.0):
+    """One non-symmetric, strictly diagonally dominant band system of order n
+    (same layout as lcp_system)."""
+    rng = np.random.default_rng([WL_LONG, seed, q])
+    n = int(n)
+    band = rng.uniform(-1.0, 1.0, size=(n, 2 * q + 1))
+    cols = np.arange(n)[:, None] + np.arange(-q, q + 1)[None, :]
+    band[(cols < 0) | (cols >= n)] = 0.0
+    band[:, q] = 0.0
+    band[:, q] = np.abs(band).sum(axis=1) + rng.uniform(0.5, 1.5, size=n)
     f = rng.normal(rhs_mean, 1.0, size=n)
     return band, f
 
