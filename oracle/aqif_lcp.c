@@ -245,11 +245,13 @@ static int aqif_back(xmat *S, const double *y, double *x)
         /* Z row p1 spans [p1-q, p1] u [p2, p2+q-1]; Z row p2 spans
          * [p1-q+1, p1] u [p2, p2+q].  Columns other than the pivots are
          * the already-solved outer unknowns. */
-        for (int64_t cc = p1 - q; cc <= p2 + q; cc++) {
-            if (cc < 0 || cc >= n || cc == p1 || cc == p2) continue;
-            if (cc > p1 && cc < p2) continue;
-            r1 -= xget(S, p1, cc) * x[cc];
-            r2 -= xget(S, p2, cc) * x[cc];
+        for (int side = 0; side < 2; side++) {
+            const int64_t c0 = side == 0 ? p1 - q : p2 + 1;
+            for (int64_t cc = c0; cc < c0 + q; cc++) {
+                if (cc < 0 || cc >= n) continue;
+                r1 -= xget(S, p1, cc) * x[cc];
+                r2 -= xget(S, p2, cc) * x[cc];
+            }
         }
         double a = xget(S, p1, p1), b = xget(S, p1, p2);
         double c = xget(S, p2, p1), d = xget(S, p2, p2);
