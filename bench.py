@@ -203,6 +203,76 @@ def convdiff_leg(P, torch, args):
     return out
 
 
+def partitioned_leg(P, torch, synth, args):
+    """Partitioned PAQIF of one long band system (n = 2^20 and 2^22 rows,
+    q = 2 and 4, linear mode): time per solve over r blocks (HIP events on
+    the library's stream, median of 5 after one warm-up), against the same
+    kernel on the unpartitioned system (one wavefront walks n/2 levels) and,
+    with the CPU leg on, the oracle's serial AQIF solve of the same system."""
+    import time as _t
+    out = {}
+    for n, q, rs in ((1 << 20, 2, (128, 256, 512, 1024, 2048)),
+                     (1 << 20, 4, (128, 256, 512, 1024)),
+                     (1 << 22, 2, (512, 1024, 2048, 4096))):
+        band_h, f_h = synth.long_system(n, q, seed=args.seed)
+        band = torch.as_tensor(band_h, device="cuda")
+        f = torch.as_tensor(f_h, device="cuda")
+        res = {}
+        for r in rs:
+            ws = torch.empty(P.paqif.partitioned_workspace_bytes(n, q, r), dtype=torch.uint8,
+                             device="cuda")
+            u, st = P.paqif.solve_partitioned(band, f, r, workspace=ws)
+            times = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                u, st = P.paqif.solve_partitioned(band, f, r, workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            res[str(r)] = dict(ms=round(float(np.median(times)), 4), status=int(st.cpu()[0]))
+            del ws
+        best = min(res, key=lambda k: res[k]["ms"])
+        entry = dict(n=n, q=q, r=res, best_r=int(best), best_ms=res[best]["ms"],
+                     rows_per_s=round(n / (res[best]["ms"] / 1e3), 1))
+        if n == 1 << 20:
+            # the unpartitioned system alone: lane layout 0 (a wavefront per system)
+            keep = P.paqif.get_layout(q)
+            P.paqif.set_layout(q, P.PREC_FP64, 0)
+            bt = P.paqif.Batch(np.array([0, n], dtype=np.int64), q)
+            ws1 = bt.workspace(P.PREC_FP64, P.LCP_LINEAR)
+            P.paqif.solve_lcp(bt, band, f, mode=P.LCP_LINEAR, workspace=ws1, want_w=False,
+                              want_active=False)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r1 = P.paqif.solve_lcp(bt, band, f, mode=P.LCP_LINEAR, workspace=ws1, want_w=False,
+                                   want_active=False)
+            e1.record()
+            torch.cuda.synchronize()
+            mono = e0.elapsed_time(e1)
+            P.paqif.set_layout(q, P.PREC_FP64, keep)
+            u, _ = P.paqif.solve_partitioned(band, f, int(best))
+            d = float((u - r1["u"]).abs().max() / r1["u"].abs().max())
+            entry["unpartitioned_ms"] = round(mono, 3)
+            entry["speedup_vs_unpartitioned"] = round(mono / res[best]["ms"], 1)
+            entry["max_rel_diff_vs_unpartitioned"] = d
+            del ws1
+            if not args.no_cpu:
+                import oracle
+                t0 = _t.perf_counter()
+                oracle.aqif_solve(band_h, f_h)
+                entry["oracle_serial_ms"] = round((_t.perf_counter() - t0) * 1e3, 2)
+        out[f"n{n}_q{q}"] = entry
+        log(f"partitioned n={n} q={q}: best r={best} {res[best]['ms']:.3f} ms"
+            + (f", unpartitioned {entry['unpartitioned_ms']:.1f} ms"
+               if "unpartitioned_ms" in entry else ""))
+        del band, f
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_leg(P, torch, synth, args):
     """Adjoint of the line contact: N=2049, 64 instances, M log-uniform in
     [20, 500], L = 10, roughness A sin(2 pi X / 0.25).  Forward solve, then
@@ -283,6 +353,9 @@ def main():
                     help="nodes per side of the point-contact leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (scale of the HBM byte counters)")
+    ap.add_argument("--partitioned-only", action="store_true",
+                    help="run only the partitioned long-system leg (one JSON object)")
+    ap.add_argument("--no-partitioned", action="store_true")
     ap.add_argument("--convdiff-only", action="store_true",
                     help="run only the convection-diffusion leg (one JSON object)")
     args = ap.parse_args()
@@ -308,6 +381,9 @@ def main():
     P.lib()
     if args.convdiff_only:
         print(json.dumps({"convdiff": convdiff_leg(P, torch, args)}))
+        return
+    if args.partitioned_only:
+        print(json.dumps({"partitioned": partitioned_leg(P, torch, synth, args)}))
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -401,6 +477,7 @@ def main():
         mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
 
     ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
+    part = partitioned_leg(P, torch, synth, args) if not args.no_partitioned else None
 
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
     tr = measured_traffic(dom)
@@ -448,6 +525,7 @@ def main():
                           "active_set_match": mixed_active_match},
         "autotune": tune,
         "ehl": ehl,
+        "partitioned": part,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

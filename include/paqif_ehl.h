@@ -180,6 +180,40 @@ int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *
                    double *u, int32_t *sys_status, void *workspace, void *stream,
                    float *times_ms);
 
+/*
+ * Partitioned PAQIF solve of ONE long band system (Sec. 2.1 eqs. 15-18 and
+ * Sec. 2.2 "PAQIF method", Steps 1-7), spread over many wavefronts.
+ * The order-n system (half-bandwidth q, band layout above, one system) is
+ * cut into r blocks, block m owning rows floor(m n / r) .. floor((m+1) n / r)
+ * - 1; its first q and last q unknowns are coupled to the neighbouring
+ * blocks.  Every block's inner unknowns are eliminated in parallel (one
+ * batched PAQIF launch over the r blocks and their 2q+1 right-hand sides),
+ * the reduced system on the 2 q r outer unknowns (a band of half-bandwidth
+ * 2q - 1, solved directly by the PAQIF kernel in place of the paper's normal
+ * equations) is solved and, in LCP_CLIP mode, projected (Step 5), then the
+ * inner unknowns follow from their blocks and are projected (Steps 6-7).
+ *  n, q, r  : q in {2, 4}; every block needs at least 2q+1 rows
+ *             (n / r >= 2q + 1); n <= 2^31.
+ *  band     : DEVICE, n x (2q+1) doubles; b: DEVICE, n doubles.
+ *  bounded  : DEVICE uint8[n] or NULL (all rows bounded); clip mode only.
+ *  mode     : LCP_LINEAR (u = A^{-1} b) or LCP_CLIP (the paper's projected
+ *             partitioned solve; not the same as clipping A^{-1} b, since the
+ *             inner unknowns use the projected outer ones).  LCP_EXACT is
+ *             refused.
+ *  u        : DEVICE out, n doubles.
+ *  status   : DEVICE out, int32[1]: the largest SYS_* code of the block and
+ *             reduced solves (SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE).
+ *  workspace: DEVICE, paqif_partitioned_workspace_bytes(n, q, r) bytes
+ *             (about (2q+1)^2 n doubles; 0 = invalid arguments).
+ * Returns PAQIF_EINVAL for invalid arguments before any launch.
+ * The block solves use the handle's lane layout for q; the reduced system
+ * (one system) runs with layout 0.
+ */
+size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r);
+int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double *band,
+                            const double *b, const uint8_t *bounded, int mode, double *u,
+                            int32_t *status, void *workspace, void *stream);
+
 /* ------------------------------------------------------------------------
  * Elastohydrodynamic lubrication (Sec. 3.3 of the paper)
  * ------------------------------------------------------------------------ */

@@ -1,0 +1,366 @@
+// Partitioned PAQIF solve of ONE long band system (Sec. 2.1 eqs. 15-18,
+// Sec. 2.2 "PAQIF method", Steps 1-7), spread over many wavefronts.
+//
+// The system of order N, half-bandwidth q, is cut into r consecutive blocks,
+// block m owning rows p_m .. p_{m+1}-1 with p_m = floor(m N / r).  Its first
+// q and last q unknowns are the outer unknowns U_F, U_L; the rest, U_M, are
+// inner.  Inner rows only touch unknowns of their own block, so
+//   A_ii u_M = f_i - A_io u_o                                  (Step 6)
+// and the outer rows, after the inner unknowns are eliminated, form the
+// reduced system on the outer unknowns of all blocks                (Step 4)
+//   S_m u_o^(m) + L-^(m) U_L^(m-1) + L+^(m) U_F^(m+1) = g_m,
+//   S_m = A_oo - A_oi A_ii^{-1} A_io,  g_m = f_o - A_oi A_ii^{-1} f_i.
+// The paper writes these rows after the centre-out factorisation of the
+// block, i.e. multiplied on the left by the inverse of the outer 2q x 2q
+// block of W0 (Steps 1-3); the solution is the same.  In the natural order
+// (U_F^(1), U_L^(1), U_F^(2), ...) the reduced matrix is a band of
+// half-bandwidth 2q - 1 and order 2 q r.
+//
+// GPU realisation, five launches on one stream:
+//   1. part_expand: (2q+1) copies of every block's inner band, one per
+//      right-hand side: f_i and the 2q columns of A_io (nonzero on q rows
+//      each);
+//   2. one batched PAQIF launch (plain linear mode) over the (2q+1) r inner
+//      systems -- all blocks and right-hand sides in parallel (Steps 1-2);
+//   3. part_reduce: S_m, g_m from the solutions next to the outer rows, and
+//      the reduced band rows with the couplings L-, L+ (Steps 3-4);
+//   4. one PAQIF launch on the reduced system (half-bandwidth 2q), in clip
+//      mode for the projection of U_F, U_L (Steps 4-5) -- a direct solve in
+//      place of the paper's normal equations;
+//   5. part_combine: u_M = x_f - X_io u_o, projected on bounded rows in clip
+//      mode (Steps 6-7), and u_o scattered back.
+#include <algorithm>
+#include <climits>
+
+#include "common.h"
+#include "paqif_args.h"
+
+namespace pq {
+namespace {
+
+struct PartGeo {
+    int64_t N;
+    int q, r;
+    int64_t Ni;  // inner rows of all blocks, N - 2 q r
+};
+
+PQ_DEV int64_t pstart(const PartGeo& g, int64_t m) { return (m * g.N) / g.r; }
+// first compacted inner row of block m
+PQ_DEV int64_t ioff(const PartGeo& g, int64_t m) { return pstart(g, m) - 2 * (int64_t)g.q * m; }
+
+// block owning global row `row`: largest m with p_m <= row
+PQ_DEV int block_of_row(const PartGeo& g, int64_t row)
+{
+    int lo = 0, hi = g.r - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pstart(g, mid) <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// block owning compacted inner row `ir`
+PQ_DEV int block_of_inner(const PartGeo& g, int64_t ir)
+{
+    int lo = 0, hi = g.r - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ioff(g, mid) <= ir) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// a(row, col) of the band (0 outside the band or the matrix)
+PQ_DEV double band_at(const PartGeo& g, const double* band, int64_t row, int64_t col)
+{
+    const int64_t d = col - row;
+    if (col < 0 || col >= g.N || d < -g.q || d > g.q) return 0.0;
+    return band[row * (2 * g.q + 1) + (d + g.q)];
+}
+
+// global column of outer unknown j (0..2q-1) of block m
+PQ_DEV int64_t outer_col(const PartGeo& g, int m, int j)
+{
+    return j < g.q ? pstart(g, m) + j : pstart(g, m + 1) - 2 * g.q + j;
+}
+
+__global__ void part_offsets_kernel(PartGeo g, int64_t* eoffs)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = (int64_t)(2 * g.q + 1) * g.r;
+    if (k > cnt) return;
+    if (k == cnt) {
+        eoffs[k] = (2 * g.q + 1) * g.Ni;
+        return;
+    }
+    const int64_t t = k / g.r, m = k % g.r;
+    eoffs[k] = t * g.Ni + ioff(g, m);
+}
+
+// Expanded row e = t * Ni + ir: inner row ir of its block with right-hand
+// side t (0: f, 1 + j: column of outer unknown j).
+__global__ void part_expand_kernel(PartGeo g, const double* __restrict__ band,
+                                   const double* __restrict__ f, double* __restrict__ eband,
+                                   double* __restrict__ erhs)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int W = 2 * g.q + 1;
+    if (e >= (int64_t)W * g.Ni) return;
+    const int t = (int)(e / g.Ni);
+    const int64_t ir = e - (int64_t)t * g.Ni;
+    const int m = block_of_inner(g, ir);
+    const int64_t row = ir + 2 * (int64_t)g.q * m + g.q;  // global row
+    const double* src = band + row * W;
+    double* dst = eband + e * W;
+    for (int d = 0; d < W; d++) dst[d] = src[d];
+    erhs[e] = t == 0 ? f[row] : band_at(g, band, row, outer_col(g, m, t - 1));
+}
+
+// Reduced row R = 2 q m + c: S_m and g_m from the inner solutions next to
+// the outer row, plus the couplings to the neighbouring blocks.
+__global__ void part_reduce_kernel(PartGeo g, const double* __restrict__ band,
+                                   const double* __restrict__ f, const uint8_t* __restrict__ bounded,
+                                   const double* __restrict__ ex, double* __restrict__ rband,
+                                   double* __restrict__ rrhs, uint8_t* __restrict__ rbnd)
+{
+    const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = g.q, N2 = 2 * q, RW = 4 * q + 1;
+    if (R >= (int64_t)N2 * g.r) return;
+    const int m = (int)(R / N2), c = (int)(R % N2);
+    const int64_t row = outer_col(g, m, c);
+    const int64_t in0 = pstart(g, m) + q, in1 = pstart(g, m + 1) - q;  // inner range
+    const int64_t io = ioff(g, m);
+    double* out = rband + R * RW;
+    for (int s = 0; s < RW; s++) out[s] = 0.0;
+    // S_m row c and g_m[c]
+    double gv = f[row];
+    for (int j = 0; j < N2; j++) {
+        double s = band_at(g, band, row, outer_col(g, m, j));
+        for (int d = -q; d <= q; d++) {
+            const int64_t col = row + d;
+            if (col < in0 || col >= in1) continue;
+            s -= band_at(g, band, row, col) * ex[(int64_t)(1 + j) * g.Ni + io + (col - in0)];
+        }
+        out[(int64_t)N2 * m + j - R + N2] = s;
+    }
+    for (int d = -q; d <= q; d++) {
+        const int64_t col = row + d;
+        if (col < in0 || col >= in1) continue;
+        gv -= band_at(g, band, row, col) * ex[io + (col - in0)];
+    }
+    // couplings: first q rows to U_L^(m-1), last q rows to U_F^(m+1)
+    if (c < q && m > 0) {
+        for (int j = 0; j < q; j++) {
+            const int64_t col = pstart(g, m) - q + j;
+            out[(int64_t)N2 * (m - 1) + q + j - R + N2] += band_at(g, band, row, col);
+        }
+    } else if (c >= q && m + 1 < g.r) {
+        for (int j = 0; j < q; j++) {
+            const int64_t col = pstart(g, m + 1) + j;
+            out[(int64_t)N2 * (m + 1) + j - R + N2] += band_at(g, band, row, col);
+        }
+    }
+    rrhs[R] = gv;
+    rbnd[R] = bounded ? (bounded[row] ? 1 : 0) : 1;
+}
+
+__global__ void part_combine_kernel(PartGeo g, const uint8_t* __restrict__ bounded, int clip,
+                                    const double* __restrict__ ex, const double* __restrict__ rx,
+                                    double* __restrict__ u)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= g.N) return;
+    const int q = g.q, N2 = 2 * q;
+    const int m = block_of_row(g, row);
+    const int64_t p0 = pstart(g, m), p1 = pstart(g, m + 1);
+    const int64_t base = (int64_t)N2 * m;
+    if (row < p0 + q) {
+        u[row] = rx[base + (row - p0)];
+        return;
+    }
+    if (row >= p1 - q) {
+        u[row] = rx[base + q + (row - (p1 - q))];
+        return;
+    }
+    const int64_t ir = ioff(g, m) + (row - p0 - q);
+    double v = ex[ir];
+    for (int j = 0; j < N2; j++) v -= ex[(int64_t)(1 + j) * g.Ni + ir] * rx[base + j];
+    if (clip && (!bounded || bounded[row])) v = v > 0.0 ? v : 0.0;
+    u[row] = v;
+}
+
+// status = the largest code over the inner systems and the reduced system
+__global__ void part_status_kernel(const int32_t* __restrict__ est, int cnt,
+                                   const int32_t* __restrict__ rst, int32_t* __restrict__ status)
+{
+    __shared__ int32_t red[256];
+    int32_t v = threadIdx.x == 0 ? rst[0] : 0;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) v = max(v, est[k]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) status[0] = red[0];
+}
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct PartLayout {
+    size_t eoffs, eband, erhs, ex, est, eit, erec, eact;
+    size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, total;
+};
+
+bool part_valid(int64_t N, int q, int32_t r)
+{
+    if (!(q == 2 || q == 4) || r < 1 || N < 1) return false;
+    if (N / r < 2 * q + 1) return false;                    // every block >= 2q+1 rows
+    if ((int64_t)(2 * q + 1) * r > INT_MAX - 1) return false;
+    if (N > ((int64_t)1 << 31)) return false;                // keeps m * N in int64
+    if (N / r + 1 > ((int64_t)1 << 30) || (int64_t)2 * q * r > ((int64_t)1 << 30)) return false;
+    return true;
+}
+
+PartLayout part_layout(int64_t N, int q, int32_t r)
+{
+    const size_t W = 2 * q + 1, cnt = W * (size_t)r;
+    const size_t Ni = (size_t)(N - 2 * (int64_t)q * r), E = W * Ni, K = 2 * (size_t)q * r;
+    PartLayout L;
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p += a256(bytes);
+        return at;
+    };
+    L.eoffs = take((cnt + 1) * sizeof(int64_t));
+    L.eband = take(E * W * sizeof(double));
+    L.erhs = take(E * sizeof(double));
+    L.ex = take(E * sizeof(double));
+    L.est = take(cnt * sizeof(int32_t));
+    L.eit = take(cnt * sizeof(int32_t));
+    L.erec = take(((E + cnt) / 2 + 1) * (size_t)record_stride(q, true) * sizeof(double));
+    L.eact = take(E);
+    L.roffs = take(2 * sizeof(int64_t));
+    L.rband = take(K * (4 * q + 1) * sizeof(double));
+    L.rrhs = take(K * sizeof(double));
+    L.rx = take(K * sizeof(double));
+    L.rbnd = take(K);
+    L.rst = take(sizeof(int32_t));
+    L.rit = take(sizeof(int32_t));
+    L.rrec = take(((K + 1) / 2 + 1) * (size_t)record_stride(2 * q, true) * sizeof(double));
+    L.ract = take(K);
+    L.total = p;
+    return L;
+}
+
+__global__ void part_roffs_kernel(int64_t K, int64_t* roffs)
+{
+    if (threadIdx.x == 0) {
+        roffs[0] = 0;
+        roffs[1] = K;
+    }
+}
+
+unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+LcpArgs lcp_args(int32_t count, const int64_t* offs, const double* band, const double* b,
+                 const uint8_t* bounded, int mode, double* u, int32_t* st, int32_t* it, void* rec,
+                 uint8_t* act)
+{
+    LcpArgs la;
+    la.count = count;
+    la.offsets = offs;
+    la.order = nullptr;
+    la.band = band;
+    la.b = b;
+    la.bounded = bounded;
+    la.mode = mode;
+    la.max_iter = 1;
+    la.refine_tol = 0.0;
+    la.u = u;
+    la.w = nullptr;
+    la.active_out = nullptr;
+    la.status = st;
+    la.iters = it;
+    la.rec = rec;
+    la.act = act;
+    la.r = nullptr;
+    la.skip = nullptr;
+    la.warm = 0;
+    return la;
+}
+
+}  // namespace
+}  // namespace pq
+
+extern "C" {
+
+size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r)
+{
+    if (!pq::part_valid(n, q, r)) return 0;
+    return pq::part_layout(n, q, r).total;
+}
+
+int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
+                            const double* b, const uint8_t* bounded, int mode, double* u,
+                            int32_t* status, void* workspace, void* stream)
+{
+    if (!handle || !pq::part_valid(n, q, r) || !(mode == LCP_LINEAR || mode == LCP_CLIP) ||
+        !band || !b || !u || !status || !workspace)
+        return PAQIF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pq::PartLayout L = pq::part_layout(n, q, r);
+    char* ws = static_cast<char*>(workspace);
+    pq::PartGeo g;
+    g.N = n;
+    g.q = q;
+    g.r = r;
+    g.Ni = n - 2 * (int64_t)q * r;
+    const int W = 2 * q + 1;
+    const int32_t cnt = W * r;
+    const int64_t E = (int64_t)W * g.Ni, K = 2 * (int64_t)q * r;
+    int64_t* eoffs = reinterpret_cast<int64_t*>(ws + L.eoffs);
+    double* eband = reinterpret_cast<double*>(ws + L.eband);
+    double* erhs = reinterpret_cast<double*>(ws + L.erhs);
+    double* ex = reinterpret_cast<double*>(ws + L.ex);
+    int32_t* est = reinterpret_cast<int32_t*>(ws + L.est);
+    int64_t* roffs = reinterpret_cast<int64_t*>(ws + L.roffs);
+    double* rband = reinterpret_cast<double*>(ws + L.rband);
+    double* rrhs = reinterpret_cast<double*>(ws + L.rrhs);
+    double* rx = reinterpret_cast<double*>(ws + L.rx);
+    uint8_t* rbnd = reinterpret_cast<uint8_t*>(ws + L.rbnd);
+    int32_t* rst = reinterpret_cast<int32_t*>(ws + L.rst);
+
+    hipLaunchKernelGGL(pq::part_offsets_kernel, dim3(pq::nblk(cnt + 1)), dim3(256), 0, s, g, eoffs);
+    hipLaunchKernelGGL(pq::part_roffs_kernel, dim3(1), dim3(64), 0, s, K, roffs);
+    hipLaunchKernelGGL(pq::part_expand_kernel, dim3(pq::nblk(E)), dim3(256), 0, s, g, band, b,
+                       eband, erhs);
+    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    // Steps 1-2: every block's inner system with its 2q+1 right-hand sides
+    pq::LcpArgs li = pq::lcp_args(cnt, eoffs, eband, erhs, nullptr, LCP_LINEAR, ex, est,
+                                  reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec,
+                                  reinterpret_cast<uint8_t*>(ws + L.eact));
+    int e = pq::dispatch_lcp(q, li, PREC_FP64, handle->layout[pq::q_index(q)][0], s);
+    if (e != PAQIF_OK) return e;
+    // Steps 3-4: reduced band rows
+    hipLaunchKernelGGL(pq::part_reduce_kernel, dim3(pq::nblk(K)), dim3(256), 0, s, g, band, b,
+                       bounded, ex, rband, rrhs, rbnd);
+    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    // Steps 4-5: the reduced system (half-bandwidth 2q), projected in clip
+    // mode; one system, so lane layout 0 (a whole wavefront on it)
+    pq::LcpArgs lr = pq::lcp_args(1, roffs, rband, rrhs, rbnd, mode, rx, rst,
+                                  reinterpret_cast<int32_t*>(ws + L.rit), ws + L.rrec,
+                                  reinterpret_cast<uint8_t*>(ws + L.ract));
+    e = pq::dispatch_lcp(2 * q, lr, PREC_FP64, 0, s);
+    if (e != PAQIF_OK) return e;
+    // Steps 6-7: inner unknowns
+    hipLaunchKernelGGL(pq::part_combine_kernel, dim3(pq::nblk(n)), dim3(256), 0, s, g, bounded,
+                       mode == LCP_CLIP ? 1 : 0, ex, rx, u);
+    hipLaunchKernelGGL(pq::part_status_kernel, dim3(1), dim3(256), 0, s, est, cnt, rst, status);
+    return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+}  // extern "C"

@@ -145,3 +145,31 @@ def autotune(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None, m
                                    _ptr(bounded), mode, prec, max_iter, _ptr(u), _ptr(st),
                                    _ptr(workspace), _stream(), times), "paqif_autotune")
     return get_layout(batch.q, prec), [float(t) for t in times]
+
+
+def partitioned_workspace_bytes(n, q, r):
+    return int(B.lib().paqif_partitioned_workspace_bytes(int(n), int(q), int(r)))
+
+
+def solve_partitioned(band, b, r, mode=B.LCP_LINEAR, bounded=None, workspace=None):
+    """Partitioned PAQIF solve of one long band system over r blocks
+    (``band``: (n, 2q+1) FP64 device tensor, ``b``: (n,)).  Returns
+    (u, status) with status a one-element int32 device tensor."""
+    _need(band, torch.float64, "band")
+    _need(b, torch.float64, "b")
+    if bounded is not None:
+        _need(bounded, torch.uint8, "bounded")
+    n, w = int(band.shape[0]), int(band.shape[1])
+    q = (w - 1) // 2
+    if tuple(b.shape) != (n,) or w != 2 * q + 1:
+        raise ValueError("band must be (n, 2q+1) and b (n,)")
+    u = torch.empty(n, dtype=torch.float64, device=band.device)
+    st = torch.empty(1, dtype=torch.int32, device=band.device)
+    if workspace is None:
+        nb = partitioned_workspace_bytes(n, q, r)
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=band.device)
+    code = B.lib().paqif_solve_partitioned(handle(), n, q, int(r), _ptr(band), _ptr(b),
+                                           _ptr(bounded), int(mode), _ptr(u), _ptr(st),
+                                           _ptr(workspace), _stream())
+    B.check(code, "paqif_solve_partitioned")
+    return u, st
