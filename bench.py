@@ -211,9 +211,13 @@ def partitioned_leg(P, torch, synth, args):
     with the CPU leg on, the oracle's serial AQIF solve of the same system."""
     import time as _t
     out = {}
-    for n, q, rs in ((1 << 20, 2, (128, 256, 512, 1024, 2048)),
-                     (1 << 20, 4, (128, 256, 512, 1024)),
-                     (1 << 22, 2, (512, 1024, 2048, 4096))):
+    cases = ((1 << 20, 2, (128, 256, 512, 1024, 2048)),
+             (1 << 20, 4, (128, 256, 512, 1024)),
+             (1 << 22, 2, (512, 1024, 2048, 4096)))
+    if args.part_case:  # one (n, q, r) only, no unpartitioned or CPU run (for profiling)
+        n_, q_, r_ = (int(v) for v in args.part_case.split(":"))
+        cases = ((n_, q_, (r_,)),)
+    for n, q, rs in cases:
         band_h, f_h = synth.long_system(n, q, seed=args.seed)
         band = torch.as_tensor(band_h, device="cuda")
         f = torch.as_tensor(f_h, device="cuda")
@@ -235,8 +239,28 @@ def partitioned_leg(P, torch, synth, args):
             del ws
         best = min(res, key=lambda k: res[k]["ms"])
         entry = dict(n=n, q=q, r=res, best_r=int(best), best_ms=res[best]["ms"],
-                     rows_per_s=round(n / (res[best]["ms"] / 1e3), 1))
-        if n == 1 << 20:
+                     rows_per_s=round(n / (res[best]["ms"] / 1e3), 1),
+                     layout=P.paqif.get_layout(q))
+        if not args.part_case:
+            # the block solves at the best r with each lane layout of the kernel
+            keep = P.paqif.get_layout(q)
+            ws = torch.empty(P.paqif.partitioned_workspace_bytes(n, q, int(best)),
+                             dtype=torch.uint8, device="cuda")
+            lay = {}
+            for L in range(P.paqif.layout_count(q)):
+                P.paqif.set_layout(q, P.PREC_FP64, L)
+                P.paqif.solve_partitioned(band, f, int(best), workspace=ws)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                P.paqif.solve_partitioned(band, f, int(best), workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                lay[str(L)] = round(e0.elapsed_time(e1), 4)
+            P.paqif.set_layout(q, P.PREC_FP64, keep)
+            entry["ms_by_layout_at_best_r"] = lay
+            del ws
+        if n == 1 << 20 and not args.part_case:
             # the unpartitioned system alone: lane layout 0 (a wavefront per system)
             keep = P.paqif.get_layout(q)
             P.paqif.set_layout(q, P.PREC_FP64, 0)
@@ -356,6 +380,8 @@ def main():
     ap.add_argument("--partitioned-only", action="store_true",
                     help="run only the partitioned long-system leg (one JSON object)")
     ap.add_argument("--no-partitioned", action="store_true")
+    ap.add_argument("--part-case", default="",
+                    help="n:q:r -- the partitioned leg on this one case only")
     ap.add_argument("--convdiff-only", action="store_true",
                     help="run only the convection-diffusion leg (one JSON object)")
     args = ap.parse_args()

@@ -204,7 +204,7 @@ int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *
  *  status   : DEVICE out, int32[1]: the largest SYS_* code of the block and
  *             reduced solves (SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE).
  *  workspace: DEVICE, paqif_partitioned_workspace_bytes(n, q, r) bytes
- *             (about (2q+1)^2 n doubles; 0 = invalid arguments).
+ *             (about (2q+1)(4q+5) n doubles; 0 = invalid arguments).
  * Returns PAQIF_EINVAL for invalid arguments before any launch.
  * The block solves use the handle's lane layout for q; the reduced system
  * (one system) runs with layout 0.

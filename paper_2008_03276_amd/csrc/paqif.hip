@@ -118,7 +118,7 @@ __device__ const double kZeroBand[32] = {};
 __device__ const uint8_t kZeroFlags[32] = {};
 
 PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8_t* pin,
-                         const double* rhs, int bw)
+                         const double* rhs, int bw, int64_t boff)
 {
     SysView v;
     if (n <= 0) {
@@ -145,7 +145,7 @@ PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8
         v.P1_0 = s - 1;
         v.P2_0 = s;
     }
-    v.band = GLB(const double, band + off * bw);
+    v.band = GLB(const double, band + boff * bw);
     v.pin = pin ? GLB(const uint8_t, pin + off) : nullptr;
     v.rhs = rhs ? GLB(const double, rhs + off) : nullptr;
     return v;
@@ -817,7 +817,7 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
     constexpr int BW = G::BW;
     GLB_PTR(const double) u = GLB(const double, A.u + off);
     GLB_PTR(const double) bb = GLB(const double, A.b + off);
-    GLB_PTR(const double) band = GLB(const double, A.band + off * BW);
+    GLB_PTR(const double) band = v.band;
     GLB_PTR(double) wout = A.w ? GLB(double, A.w + off) : nullptr;
     GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
@@ -963,12 +963,14 @@ __global__ void __launch_bounds__(64)
     if (live && A.skip && A.skip[sys]) live = false;
     int64_t off = live ? A.offsets[sys] : 0;
     int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    int64_t boff = live && A.band_off ? A.band_off[sys] : off;
     if constexpr (G::SPW == 1) {  // one system per wave: keep its scalars in SGPRs
         sys = __builtin_amdgcn_readfirstlane(sys);
         off = uniform64(off);
         n = uniform64(n);
+        boff = uniform64(boff);
     }
-    SysView v = make_view(off, n, A.band, A.act, A.b, G::BW);
+    SysView v = make_view(off, n, A.band, A.act, A.b, G::BW, boff);
     if (!live) {
         v.n = 0;
         v.npair = 0;
@@ -1137,7 +1139,7 @@ __global__ void __launch_bounds__(64)
         off = uniform64(off);
         n = uniform64(n);
     }
-    SysView v = make_view(off, n, A.band, A.pinned, nullptr, G::BW);
+    SysView v = make_view(off, n, A.band, A.pinned, nullptr, G::BW, off);
     if (!live) {
         v.n = 0;
         v.npair = 0;
@@ -1174,7 +1176,7 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
         off = uniform64(off);
         n = uniform64(n);
     }
-    SysView v = make_view(off, n, nullptr, A.pinned, nullptr, G::BW);
+    SysView v = make_view(off, n, nullptr, A.pinned, nullptr, G::BW, off);
     if (!live) {
         v.n = 0;
         v.npair = 0;
@@ -1412,7 +1414,8 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
     if (live && A.skip && A.skip[sys]) live = false;
     const int64_t off = live ? A.offsets[sys] : 0;
     const int64_t n = live ? A.offsets[sys + 1] - off : 0;
-    SysView v = make_view(off, n, A.band, A.act, A.b, BW);
+    const int64_t boff = live && A.band_off ? A.band_off[sys] : off;
+    SysView v = make_view(off, n, A.band, A.act, A.b, BW, boff);
     if (!live) {
         v.n = 0;
         v.npair = 0;
@@ -1420,7 +1423,7 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
     GLB_PTR(double) rec = GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * ZR);
     GLB_PTR(double) u = GLB(double, A.u + off);
     GLB_PTR(const double) bb = GLB(const double, A.b + off);
-    GLB_PTR(const double) band = GLB(const double, A.band + off * BW);
+    GLB_PTR(const double) band = v.band;
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
     GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
     const bool exact = A.mode == LCP_EXACT;

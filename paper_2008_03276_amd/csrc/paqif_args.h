@@ -38,6 +38,9 @@ struct LcpArgs {
     double* r;     // refinement residual (total_rows), FP32_IR only
     const uint8_t* skip;  // per system: nonzero = leave untouched (may be null)
     int warm;  // exact mode: start from the flags already in act (bounded rows only)
+    // per system: first row of its band rows in `band` (null = offsets[sys]);
+    // lets several systems (e.g. one matrix with several right-hand sides) share rows
+    const int64_t* band_off = nullptr;
 };
 
 struct FactorArgs {

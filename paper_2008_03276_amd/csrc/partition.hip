@@ -17,11 +17,13 @@
 // half-bandwidth 2q - 1 and order 2 q r.
 //
 // GPU realisation, five launches on one stream:
-//   1. part_expand: (2q+1) copies of every block's inner band, one per
-//      right-hand side: f_i and the 2q columns of A_io (nonzero on q rows
-//      each);
+//   1. part_rhs: the 2q+1 right-hand sides of every block's inner system:
+//      f_i and the 2q columns of A_io (nonzero on q rows each);
 //   2. one batched PAQIF launch (plain linear mode) over the (2q+1) r inner
 //      systems -- all blocks and right-hand sides in parallel (Steps 1-2);
+//      the 2q+1 systems of a block read the same rows of the caller's band
+//      (the kernel ignores the entries whose column falls outside the inner
+//      system, which are exactly the couplings A_io);
 //   3. part_reduce: S_m, g_m from the solutions next to the outer rows, and
 //      the reduced band rows with the couplings L-, L+ (Steps 3-4);
 //   4. one PAQIF launch on the reduced system (half-bandwidth 2q), in clip
@@ -86,7 +88,9 @@ PQ_DEV int64_t outer_col(const PartGeo& g, int m, int j)
     return j < g.q ? pstart(g, m) + j : pstart(g, m + 1) - 2 * g.q + j;
 }
 
-__global__ void part_offsets_kernel(PartGeo g, int64_t* eoffs)
+// system k = t r + m: rows of its right-hand side / solution in the
+// expanded arrays, and its first band row in the caller's band
+__global__ void part_offsets_kernel(PartGeo g, int64_t* eoffs, int64_t* eboff)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cnt = (int64_t)(2 * g.q + 1) * g.r;
@@ -97,13 +101,13 @@ __global__ void part_offsets_kernel(PartGeo g, int64_t* eoffs)
     }
     const int64_t t = k / g.r, m = k % g.r;
     eoffs[k] = t * g.Ni + ioff(g, m);
+    eboff[k] = pstart(g, m) + g.q;
 }
 
 // Expanded row e = t * Ni + ir: inner row ir of its block with right-hand
 // side t (0: f, 1 + j: column of outer unknown j).
-__global__ void part_expand_kernel(PartGeo g, const double* __restrict__ band,
-                                   const double* __restrict__ f, double* __restrict__ eband,
-                                   double* __restrict__ erhs)
+__global__ void part_rhs_kernel(PartGeo g, const double* __restrict__ band,
+                                const double* __restrict__ f, double* __restrict__ erhs)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int W = 2 * g.q + 1;
@@ -112,9 +116,6 @@ __global__ void part_expand_kernel(PartGeo g, const double* __restrict__ band,
     const int64_t ir = e - (int64_t)t * g.Ni;
     const int m = block_of_inner(g, ir);
     const int64_t row = ir + 2 * (int64_t)g.q * m + g.q;  // global row
-    const double* src = band + row * W;
-    double* dst = eband + e * W;
-    for (int d = 0; d < W; d++) dst[d] = src[d];
     erhs[e] = t == 0 ? f[row] : band_at(g, band, row, outer_col(g, m, t - 1));
 }
 
@@ -210,7 +211,7 @@ __global__ void part_status_kernel(const int32_t* __restrict__ est, int cnt,
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PartLayout {
-    size_t eoffs, eband, erhs, ex, est, eit, erec, eact;
+    size_t eoffs, eboff, erhs, ex, est, eit, erec, eact;
     size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, total;
 };
 
@@ -236,7 +237,7 @@ PartLayout part_layout(int64_t N, int q, int32_t r)
         return at;
     };
     L.eoffs = take((cnt + 1) * sizeof(int64_t));
-    L.eband = take(E * W * sizeof(double));
+    L.eboff = take(cnt * sizeof(int64_t));
     L.erhs = take(E * sizeof(double));
     L.ex = take(E * sizeof(double));
     L.est = take(cnt * sizeof(int32_t));
@@ -323,7 +324,7 @@ int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, co
     const int32_t cnt = W * r;
     const int64_t E = (int64_t)W * g.Ni, K = 2 * (int64_t)q * r;
     int64_t* eoffs = reinterpret_cast<int64_t*>(ws + L.eoffs);
-    double* eband = reinterpret_cast<double*>(ws + L.eband);
+    int64_t* eboff = reinterpret_cast<int64_t*>(ws + L.eboff);
     double* erhs = reinterpret_cast<double*>(ws + L.erhs);
     double* ex = reinterpret_cast<double*>(ws + L.ex);
     int32_t* est = reinterpret_cast<int32_t*>(ws + L.est);
@@ -334,15 +335,16 @@ int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, co
     uint8_t* rbnd = reinterpret_cast<uint8_t*>(ws + L.rbnd);
     int32_t* rst = reinterpret_cast<int32_t*>(ws + L.rst);
 
-    hipLaunchKernelGGL(pq::part_offsets_kernel, dim3(pq::nblk(cnt + 1)), dim3(256), 0, s, g, eoffs);
+    hipLaunchKernelGGL(pq::part_offsets_kernel, dim3(pq::nblk(cnt + 1)), dim3(256), 0, s, g, eoffs,
+                       eboff);
     hipLaunchKernelGGL(pq::part_roffs_kernel, dim3(1), dim3(64), 0, s, K, roffs);
-    hipLaunchKernelGGL(pq::part_expand_kernel, dim3(pq::nblk(E)), dim3(256), 0, s, g, band, b,
-                       eband, erhs);
+    hipLaunchKernelGGL(pq::part_rhs_kernel, dim3(pq::nblk(E)), dim3(256), 0, s, g, band, b, erhs);
     if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
     // Steps 1-2: every block's inner system with its 2q+1 right-hand sides
-    pq::LcpArgs li = pq::lcp_args(cnt, eoffs, eband, erhs, nullptr, LCP_LINEAR, ex, est,
+    pq::LcpArgs li = pq::lcp_args(cnt, eoffs, band, erhs, nullptr, LCP_LINEAR, ex, est,
                                   reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec,
                                   reinterpret_cast<uint8_t*>(ws + L.eact));
+    li.band_off = eboff;
     int e = pq::dispatch_lcp(q, li, PREC_FP64, handle->layout[pq::q_index(q)][0], s);
     if (e != PAQIF_OK) return e;
     // Steps 3-4: reduced band rows
