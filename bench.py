@@ -211,9 +211,9 @@ def partitioned_leg(P, torch, synth, args):
     with the CPU leg on, the oracle's serial AQIF solve of the same system."""
     import time as _t
     out = {}
-    cases = ((1 << 20, 2, (128, 256, 512, 1024, 2048)),
+    cases = ((1 << 20, 2, (256, 512, 1024, 2048, 4096)),
              (1 << 20, 4, (128, 256, 512, 1024)),
-             (1 << 22, 2, (512, 1024, 2048, 4096)))
+             (1 << 22, 2, (512, 1024, 2048, 4096, 8192)))
     if args.part_case:  # one (n, q, r) only, no unpartitioned or CPU run (for profiling)
         n_, q_, r_ = (int(v) for v in args.part_case.split(":"))
         cases = ((n_, q_, (r_,)),)

@@ -26,13 +26,17 @@
 //      system, which are exactly the couplings A_io);
 //   3. part_reduce: S_m, g_m from the solutions next to the outer rows, and
 //      the reduced band rows with the couplings L-, L+ (Steps 3-4);
-//   4. one PAQIF launch on the reduced system (half-bandwidth 2q), in clip
-//      mode for the projection of U_F, U_L (Steps 4-5) -- a direct solve in
-//      place of the paper's normal equations;
-//   5. part_combine: u_M = x_f - X_io u_o, projected on bounded rows in clip
-//      mode (Steps 6-7), and u_o scattered back.
+//   4. the reduced system (half-bandwidth 2q) solved directly, in place of
+//      the paper's normal equations: one PAQIF launch on one wavefront or,
+//      for q = 2 and at least 512 reduced rows, the same partitioned scheme
+//      once more (half-bandwidth 4 over about sqrt(K/8) blocks, its own
+//      reduced system of half-bandwidth 8 solved whole);
+//   5. part_combine: the outer unknowns projected on bounded rows in clip
+//      mode (Step 5), u_M = x_f - X_io u_o with those values (Step 6),
+//      projected (Step 7).
 #include <algorithm>
 #include <climits>
+#include <cmath>
 
 #include "common.h"
 #include "paqif_args.h"
@@ -167,9 +171,16 @@ __global__ void part_reduce_kernel(PartGeo g, const double* __restrict__ band,
     rbnd[R] = bounded ? (bounded[row] ? 1 : 0) : 1;
 }
 
+// outer unknown R of the reduced solution, projected in clip mode (Step 5)
+PQ_DEV double outer_value(const double* rx, const uint8_t* rbnd, int clip, int64_t R)
+{
+    const double v = rx[R];
+    return (clip && rbnd[R]) ? (v > 0.0 ? v : 0.0) : v;
+}
+
 __global__ void part_combine_kernel(PartGeo g, const uint8_t* __restrict__ bounded, int clip,
                                     const double* __restrict__ ex, const double* __restrict__ rx,
-                                    double* __restrict__ u)
+                                    const uint8_t* __restrict__ rbnd, double* __restrict__ u)
 {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= g.N) return;
@@ -178,16 +189,18 @@ __global__ void part_combine_kernel(PartGeo g, const uint8_t* __restrict__ bound
     const int64_t p0 = pstart(g, m), p1 = pstart(g, m + 1);
     const int64_t base = (int64_t)N2 * m;
     if (row < p0 + q) {
-        u[row] = rx[base + (row - p0)];
+        u[row] = outer_value(rx, rbnd, clip, base + (row - p0));
         return;
     }
     if (row >= p1 - q) {
-        u[row] = rx[base + q + (row - (p1 - q))];
+        u[row] = outer_value(rx, rbnd, clip, base + q + (row - (p1 - q)));
         return;
     }
+    // Step 6 with the projected outer unknowns, then Step 7
     const int64_t ir = ioff(g, m) + (row - p0 - q);
     double v = ex[ir];
-    for (int j = 0; j < N2; j++) v -= ex[(int64_t)(1 + j) * g.Ni + ir] * rx[base + j];
+    for (int j = 0; j < N2; j++)
+        v -= ex[(int64_t)(1 + j) * g.Ni + ir] * outer_value(rx, rbnd, clip, base + j);
     if (clip && (!bounded || bounded[row])) v = v > 0.0 ? v : 0.0;
     u[row] = v;
 }
@@ -212,8 +225,21 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PartLayout {
     size_t eoffs, eboff, erhs, ex, est, eit, erec, eact;
-    size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, total;
+    size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, sub, total;
 };
+
+// q = 2: a reduced system of at least kNestRows rows (half-bandwidth 4) is
+// itself solved by the partitioned scheme, over sub_blocks() blocks; its own
+// reduced system (half-bandwidth 8) is solved whole.
+constexpr int64_t kNestRows = 512;
+bool nests(int q, int64_t K) { return q == 2 && K >= kNestRows; }
+int32_t sub_blocks(int64_t K, int q2)
+{
+    // balance the block levels (K / r) / 2 against the reduced levels q2 r
+    int64_t r = (int64_t)std::sqrt((double)K / (2.0 * q2));
+    r = std::max<int64_t>(1, std::min<int64_t>(r, K / (2 * q2 + 1)));
+    return (int32_t)r;
+}
 
 bool part_valid(int64_t N, int q, int32_t r)
 {
@@ -253,6 +279,9 @@ PartLayout part_layout(int64_t N, int q, int32_t r)
     L.rit = take(sizeof(int32_t));
     L.rrec = take(((K + 1) / 2 + 1) * (size_t)record_stride(2 * q, true) * sizeof(double));
     L.ract = take(K);
+    L.sub = nests(q, (int64_t)K) ? take(part_layout((int64_t)K, 2 * q,
+                                                    sub_blocks((int64_t)K, 2 * q)).total)
+                                 : p;
     L.total = p;
     return L;
 }
@@ -294,28 +323,12 @@ LcpArgs lcp_args(int32_t count, const int64_t* offs, const double* band, const d
     return la;
 }
 
-}  // namespace
-}  // namespace pq
-
-extern "C" {
-
-size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r)
+int part_run(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
+             const double* b, const uint8_t* bounded, int mode, double* u, int32_t* status,
+             char* ws, hipStream_t s)
 {
-    if (!pq::part_valid(n, q, r)) return 0;
-    return pq::part_layout(n, q, r).total;
-}
-
-int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
-                            const double* b, const uint8_t* bounded, int mode, double* u,
-                            int32_t* status, void* workspace, void* stream)
-{
-    if (!handle || !pq::part_valid(n, q, r) || !(mode == LCP_LINEAR || mode == LCP_CLIP) ||
-        !band || !b || !u || !status || !workspace)
-        return PAQIF_EINVAL;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const pq::PartLayout L = pq::part_layout(n, q, r);
-    char* ws = static_cast<char*>(workspace);
-    pq::PartGeo g;
+    const PartLayout L = part_layout(n, q, r);
+    PartGeo g;
     g.N = n;
     g.q = q;
     g.r = r;
@@ -335,34 +348,61 @@ int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, co
     uint8_t* rbnd = reinterpret_cast<uint8_t*>(ws + L.rbnd);
     int32_t* rst = reinterpret_cast<int32_t*>(ws + L.rst);
 
-    hipLaunchKernelGGL(pq::part_offsets_kernel, dim3(pq::nblk(cnt + 1)), dim3(256), 0, s, g, eoffs,
-                       eboff);
-    hipLaunchKernelGGL(pq::part_roffs_kernel, dim3(1), dim3(64), 0, s, K, roffs);
-    hipLaunchKernelGGL(pq::part_rhs_kernel, dim3(pq::nblk(E)), dim3(256), 0, s, g, band, b, erhs);
-    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    hipLaunchKernelGGL(part_offsets_kernel, dim3(nblk(cnt + 1)), dim3(256), 0, s, g, eoffs, eboff);
+    hipLaunchKernelGGL(part_rhs_kernel, dim3(nblk(E)), dim3(256), 0, s, g, band, b, erhs);
+    if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
     // Steps 1-2: every block's inner system with its 2q+1 right-hand sides
-    pq::LcpArgs li = pq::lcp_args(cnt, eoffs, band, erhs, nullptr, LCP_LINEAR, ex, est,
-                                  reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec,
-                                  reinterpret_cast<uint8_t*>(ws + L.eact));
+    LcpArgs li = lcp_args(cnt, eoffs, band, erhs, nullptr, LCP_LINEAR, ex, est,
+                          reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec,
+                          reinterpret_cast<uint8_t*>(ws + L.eact));
     li.band_off = eboff;
-    int e = pq::dispatch_lcp(q, li, PREC_FP64, handle->layout[pq::q_index(q)][0], s);
+    int e = dispatch_lcp(q, li, PREC_FP64, handle->layout[q_index(q)][0], s);
     if (e != PAQIF_OK) return e;
     // Steps 3-4: reduced band rows
-    hipLaunchKernelGGL(pq::part_reduce_kernel, dim3(pq::nblk(K)), dim3(256), 0, s, g, band, b,
-                       bounded, ex, rband, rrhs, rbnd);
-    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
-    // Steps 4-5: the reduced system (half-bandwidth 2q), projected in clip
-    // mode; one system, so lane layout 0 (a whole wavefront on it)
-    pq::LcpArgs lr = pq::lcp_args(1, roffs, rband, rrhs, rbnd, mode, rx, rst,
-                                  reinterpret_cast<int32_t*>(ws + L.rit), ws + L.rrec,
-                                  reinterpret_cast<uint8_t*>(ws + L.ract));
-    e = pq::dispatch_lcp(2 * q, lr, PREC_FP64, 0, s);
+    hipLaunchKernelGGL(part_reduce_kernel, dim3(nblk(K)), dim3(256), 0, s, g, band, b, bounded, ex,
+                       rband, rrhs, rbnd);
+    if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    // Step 4: the reduced system (half-bandwidth 2q) in plain linear mode;
+    // its projection (Step 5) is applied where its values are read
+    if (nests(q, K)) {
+        e = part_run(handle, K, 2 * q, sub_blocks(K, 2 * q), rband, rrhs, nullptr, LCP_LINEAR, rx,
+                     rst, ws + L.sub, s);
+    } else {
+        // one system: lane layout 0 (a whole wavefront on it)
+        hipLaunchKernelGGL(part_roffs_kernel, dim3(1), dim3(64), 0, s, K, roffs);
+        LcpArgs lr = lcp_args(1, roffs, rband, rrhs, nullptr, LCP_LINEAR, rx, rst,
+                              reinterpret_cast<int32_t*>(ws + L.rit), ws + L.rrec,
+                              reinterpret_cast<uint8_t*>(ws + L.ract));
+        e = dispatch_lcp(2 * q, lr, PREC_FP64, 0, s);
+    }
     if (e != PAQIF_OK) return e;
-    // Steps 6-7: inner unknowns
-    hipLaunchKernelGGL(pq::part_combine_kernel, dim3(pq::nblk(n)), dim3(256), 0, s, g, bounded,
-                       mode == LCP_CLIP ? 1 : 0, ex, rx, u);
-    hipLaunchKernelGGL(pq::part_status_kernel, dim3(1), dim3(256), 0, s, est, cnt, rst, status);
-    return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+    // Steps 5-7: projected outer unknowns, inner unknowns, their projection
+    hipLaunchKernelGGL(part_combine_kernel, dim3(nblk(n)), dim3(256), 0, s, g, bounded,
+                       mode == LCP_CLIP ? 1 : 0, ex, rx, rbnd, u);
+    hipLaunchKernelGGL(part_status_kernel, dim3(1), dim3(256), 0, s, est, cnt, rst, status);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+}  // namespace
+}  // namespace pq
+
+extern "C" {
+
+size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r)
+{
+    if (!pq::part_valid(n, q, r)) return 0;
+    return pq::part_layout(n, q, r).total;
+}
+
+int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
+                            const double* b, const uint8_t* bounded, int mode, double* u,
+                            int32_t* status, void* workspace, void* stream)
+{
+    if (!handle || !pq::part_valid(n, q, r) || !(mode == LCP_LINEAR || mode == LCP_CLIP) ||
+        !band || !b || !u || !status || !workspace)
+        return PAQIF_EINVAL;
+    return pq::part_run(handle, n, q, r, band, b, bounded, mode, u, status,
+                        static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -7,7 +7,8 @@ oracle uses dense W0/Z0 factors and the W0-scaled reduced rows; both are
 FP64 on strictly diagonally dominant systems (condition numbers below ~50),
 so the results differ by rounding order only: 1e-11 relative.
   * small cases (ragged splits, odd/even blocks, one block, minimum blocks
-    of 2q+1 rows) in linear and clip mode, all rows or a mask bounded;
+    of 2q+1 rows, q = 2 cases whose reduced system is partitioned again) in
+    linear and clip mode, all rows or a mask bounded;
   * mid-size cases against the oracle's monolithic AQIF solve (linear) and
     the oracle's partitioned solve (clip);
   * the benchmark's size (n = 2^20, q = 2, r = 512, linear) against the
@@ -25,7 +26,9 @@ from oracle import partitioned as OP
 pytestmark = pytest.mark.gpu
 
 CASES = [(60, 2, 4), (61, 2, 4), (97, 2, 7), (50, 2, 1), (35, 2, 7), (200, 4, 6), (203, 4, 5),
-         (72, 4, 8), (1000, 2, 33), (1001, 4, 21)]
+         (72, 4, 8), (1000, 2, 33), (1001, 4, 21),
+         # q = 2 with at least 512 reduced rows: the reduced system is partitioned again
+         (3000, 2, 128), (2601, 2, 131)]
 
 
 def _gpu(P, band, f, r, mode, bounded=None):
@@ -56,7 +59,7 @@ def test_parity_small(gpu, N, q, r, mode, masked):
     assert _rel(u, ref) <= 1e-11
 
 
-@pytest.mark.parametrize("N,q,r", [(20000, 2, 64), (20011, 4, 40)])
+@pytest.mark.parametrize("N,q,r", [(20000, 2, 64), (20000, 2, 256), (20011, 4, 40)])
 def test_parity_mid(gpu, N, q, r):
     print(f"partitioned mid N={N} q={q} r={r}", flush=True)
     band, f = synth.long_system(N, q, seed=11)
