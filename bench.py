@@ -32,6 +32,111 @@ def algorithmic_bytes_per_row(q):
     return 8 * (2 * q + 1) + 8 + 8 + 2 * 8 * (2 * q + 1)
 
 
+def minimum_bytes_per_row(q):
+    # band, b and u read once per active-set iteration (no factor traffic)
+    return 8 * (2 * q + 1) + 8 + 8
+
+
+def copy_bandwidth(torch):
+    # device copy of 2^25 doubles (read + write), HIP events, best of 5
+    src = torch.rand(1 << 25, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * (1 << 25) * 8 / (best / 1e3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def deformation_leg(P, torch, args):
+    """MFMA use of the elastic deformation (2N^2 B flops for a line grid,
+    2 (Nx Ny)^2 B for a point grid): N = 4097 with B = 170 instances (the
+    largest sweep group) and the 257 x 257 point grid, B = 1, in each
+    precision the library offers; HIP events, median of 5."""
+    # precision codes of the library: 0 FP64, 3 FP32, 2 split BF16 (three
+    # BF16 products per FP32-like product; flops counted algorithmically)
+    peaks = {0: 78.6, 3: 157.3, 2: 2500.0}
+    names = {0: "fp64", 3: "fp32", 2: "split_bf16"}
+    out = {}
+    for tag, grid, shape, flops in (
+            ("line_N4097_B170", P.ehl.line_grid(4097), (170, 4097), 2.0 * 4097 ** 2 * 170),
+            ("point_257x257", P.ehl.point_grid(257, 257), (1, 257, 257), 2.0 * (257 * 257) ** 2)):
+        Pf = torch.rand(shape, dtype=torch.float64, device="cuda")
+        res = {}
+        for prec in (0, 3, 2):
+            try:
+                P.ehl.deformation(Pf, grid, prec=prec)
+            except (RuntimeError, ValueError):
+                continue
+            ts = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                P.ehl.deformation(Pf, grid, prec=prec)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            tf = flops / (ms / 1e3) / 1e12
+            res[names[prec]] = dict(ms=round(ms, 4), tflops=round(tf, 2),
+                                    peak_tflops=peaks[prec], frac=round(tf / peaks[prec], 4))
+        out[tag] = res
+        log(f"deformation {tag}: " + ", ".join(f"{k} {v['ms']} ms ({v['frac']:.1%})"
+                                               for k, v in res.items()))
+    return out
+
+
+def active30_leg(P, torch, synth, args):
+    """Config 2 with b ~ N(0.55, 1) (about 30 % active): one warm-up and
+    three timed solves per q, FP64 exact LCP."""
+    out = {}
+    tot_ms = 0.0
+    for q in QS:
+        offs, band, f = synth.lcp_batch(COUNT, q, seed=args.seed, rhs_mean=0.55)
+        bt = P.paqif.Batch(offs, q, order="lpt")
+        bd = torch.as_tensor(band, device="cuda")
+        fd = torch.as_tensor(f, device="cuda")
+        ws = bt.workspace(P.PREC_FP64)
+        r = P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT, workspace=ws)
+        ts = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.mean(ts))
+        tot_ms += ms
+        out[str(q)] = dict(avg_ms=round(ms, 4), active_frac=round(float(r["active"].float().mean()), 4),
+                           iters_mean=round(float(r["iters"].float().mean()), 3),
+                           status_ok=bool((r["status"] == 0).all().item()))
+        del bd, fd, ws
+    out["solves_per_s"] = round(len(QS) * COUNT / (tot_ms / 1e3), 1)
+    log(f"config 2 at ~30% active: {out['solves_per_s']:.0f} solves/s")
+    return out
+
+
 def cpu_baseline(batches, sample, nthreads):
     import oracle
     t_total = 0.0
@@ -88,6 +193,13 @@ def ehl_legs(P, torch, synth, dev, args):
     out["config1"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 3),
                           status=int(r["status"][0]), newton_steps=int(r["iters"][0]),
                           H0=float(r["H0"][0]), Hmin=float(r["Hmin"][0]))
+    if not args.no_cpu:
+        # the oracle (numpy, one process) on the same instance
+        from oracle import ehl_line as OE
+        t0 = _t.perf_counter()
+        ro = OE.solve_line(20.0, 10.0, 257)
+        out["config1"]["oracle"] = dict(seconds=round(_t.perf_counter() - t0, 3),
+                                        status=int(ro["status"]), newton_steps=int(ro["iters"]))
     # the same contact with the kappa-scheme convection instead of van Leer
     kap = {}
     for kappa in (0.0, 1.0 / 3.0, -1.0):
@@ -135,6 +247,18 @@ def ehl_legs(P, torch, synth, dev, args):
         log(f"ehl sweep N={N}: {dt:.2f} s, converged {int(ok.sum())}/{len(idx)}")
     res.update(seconds=round(t_all, 3), converged=conv_all,
                solves_per_s=round(nb / t_all, 3), converged_per_s=round(conv_all / t_all, 3))
+    if not args.no_cpu:
+        # the oracle on a seeded subset: the first instance of the N = 1025
+        # group (the full sweep would take the oracle hours)
+        from oracle import ehl_line as OE
+        i0 = int(idx1025[0])
+        t0 = _t.perf_counter()
+        ro = OE.solve_line(float(M[i0]), float(L[i0]), 1025, max_newton=3000, stall_steps=600)
+        res["oracle_subset"] = dict(instances=1, N=1025, M=float(M[i0]), L=float(L[i0]),
+                                    seconds=round(_t.perf_counter() - t0, 3),
+                                    status=int(ro["status"]), newton_steps=int(ro["iters"]),
+                                    gpu_seconds_per_instance_in_batch=round(
+                                        res["groups"]["1025"]["seconds"] / len(idx1025), 4))
     opts = P.ehl.default_opts(deform_prec=P.PREC_FP32, max_newton=3000, lcp_max_iter=8,
                               stall_steps=600)
     torch.cuda.synchronize()
@@ -364,7 +488,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-ehl", action="store_true")
     ap.add_argument("--ehl-sweep", type=int, default=512,
@@ -502,8 +626,11 @@ def main():
                                          max(1.0, float(u64.abs().max()))))
         mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
 
+    active30 = active30_leg(P, torch, synth, args)
     ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
+    deform = deformation_leg(P, torch, args) if not args.no_ehl else None
     part = partitioned_leg(P, torch, synth, args) if not args.no_partitioned else None
+    copy_gbs = copy_bandwidth(torch)
 
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
     tr = measured_traffic(dom)
@@ -512,6 +639,11 @@ def main():
                 traffic=None if tr is None else round(tr / 1e9, 3),
                 kernel=f"paqif_lcp_kernel<{dom},double>",
                 algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
+    rows_it = per_q[dom]["bytes"] / algorithmic_bytes_per_row(dom)
+    min_gbs = rows_it * minimum_bytes_per_row(dom) / (per_q[dom]["avg_ms"] / 1e3) / 1e9
+    roof["frac_minimum_bytes"] = round(min_gbs / HBM_PEAK_GBS, 4)
+    roof["copy_kernel_gbs"] = round(copy_gbs, 1)
+    roof["frac_vs_copy"] = round(per_q[dom]["gbs"] / copy_gbs, 4)
     if tr is not None:
         roof["traffic_unit"] = "GB per launch (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)"
         roof["measured_hbm_gbs"] = round(tr / (per_q[dom]["avg_ms"] / 1e3) / 1e9, 2)
@@ -523,8 +655,10 @@ def main():
         nthreads = os.cpu_count() or 1
         v = cpu_baseline(batches, args.cpu_sample, nthreads)
         cpu = dict(value=round(v, 2), unit="LCP solves/s", cores=nthreads, kind="oracle",
-                   sample=f"first {args.cpu_sample} systems of each q batch, exact LCP, "
-                          f"OpenMP over systems")
+                   cpu_model=cpu_model(),
+                   sample=(f"all {COUNT} systems of each q batch" if args.cpu_sample >= COUNT
+                           else f"first {args.cpu_sample} systems of each q batch")
+                          + ", exact LCP, OpenMP over systems")
 
     line = {
         "metric": "PAQIF banded-LCP solves/s (exact LCP, FP64)",
@@ -552,6 +686,8 @@ def main():
         "autotune": tune,
         "ehl": ehl,
         "partitioned": part,
+        "config2_active30": active30,
+        "deformation_mfma": deform,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
