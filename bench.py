@@ -349,17 +349,18 @@ def partitioned_leg(P, torch, synth, args):
         for r in rs:
             ws = torch.empty(P.paqif.partitioned_workspace_bytes(n, q, r), dtype=torch.uint8,
                              device="cuda")
-            u, st = P.paqif.solve_partitioned(band, f, r, workspace=ws)
+            res_p = P.paqif.solve_partitioned(band, f, r, workspace=ws)
             times = []
             for _ in range(5):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                u, st = P.paqif.solve_partitioned(band, f, r, workspace=ws)
+                res_p = P.paqif.solve_partitioned(band, f, r, workspace=ws)
                 e1.record()
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
-            res[str(r)] = dict(ms=round(float(np.median(times)), 4), status=int(st.cpu()[0]))
+            res[str(r)] = dict(ms=round(float(np.median(times)), 4),
+                               status=int(res_p["status"].cpu()[0]))
             del ws
         best = min(res, key=lambda k: res[k]["ms"])
         entry = dict(n=n, q=q, r=res, best_r=int(best), best_ms=res[best]["ms"],
@@ -401,7 +402,17 @@ def partitioned_leg(P, torch, synth, args):
             torch.cuda.synchronize()
             mono = e0.elapsed_time(e1)
             P.paqif.set_layout(q, P.PREC_FP64, keep)
-            u, _ = P.paqif.solve_partitioned(band, f, int(best))
+            u = P.paqif.solve_partitioned(band, f, int(best))["u"]
+            # the exact LCP (eq. 14) by the active-set iteration around the
+            # partitioned solve (host-synchronised after each solve)
+            P.paqif.solve_partitioned(band, f, int(best), mode=P.LCP_EXACT)
+            t0 = _t.perf_counter()
+            rx = P.paqif.solve_partitioned(band, f, int(best), mode=P.LCP_EXACT)
+            torch.cuda.synchronize()
+            entry["exact"] = dict(ms=round((_t.perf_counter() - t0) * 1e3, 3),
+                                  solves=int(rx["iters"].cpu()[0]),
+                                  status=int(rx["status"].cpu()[0]),
+                                  active_frac=round(float(rx["active"].float().mean()), 4))
             d = float((u - r1["u"]).abs().max() / r1["u"].abs().max())
             entry["unpartitioned_ms"] = round(mono, 3)
             entry["speedup_vs_unpartitioned"] = round(mono / res[best]["ms"], 1)
@@ -412,6 +423,10 @@ def partitioned_leg(P, torch, synth, args):
                 t0 = _t.perf_counter()
                 oracle.aqif_solve(band_h, f_h)
                 entry["oracle_serial_ms"] = round((_t.perf_counter() - t0) * 1e3, 2)
+                t0 = _t.perf_counter()
+                ro = oracle.lcp_solve(band_h, f_h, mode=oracle.EXACT, max_iter=64)
+                entry["exact"]["oracle_serial_ms"] = round((_t.perf_counter() - t0) * 1e3, 2)
+                entry["exact"]["oracle_solves"] = int(ro["iters"])
         out[f"n{n}_q{q}"] = entry
         log(f"partitioned n={n} q={q}: best r={best} {res[best]['ms']:.3f} ms"
             + (f", unpartitioned {entry['unpartitioned_ms']:.1f} ms"

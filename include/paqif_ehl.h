@@ -189,20 +189,30 @@ int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *
  * blocks.  Every block's inner unknowns are eliminated in parallel (one
  * batched PAQIF launch over the r blocks and their 2q+1 right-hand sides),
  * the reduced system on the 2 q r outer unknowns (a band of half-bandwidth
- * 2q - 1, solved directly by the PAQIF kernel in place of the paper's normal
- * equations) is solved and, in LCP_CLIP mode, projected (Step 5), then the
- * inner unknowns follow from their blocks and are projected (Steps 6-7).
+ * 2q - 1, solved directly in place of the paper's normal equations; for
+ * q = 2 and at least 512 reduced rows by the same scheme once more) is
+ * solved and, in LCP_CLIP mode, projected (Step 5), then the inner unknowns
+ * follow from their blocks and are projected (Steps 6-7).
  *  n, q, r  : q in {2, 4}; every block needs at least 2q+1 rows
  *             (n / r >= 2q + 1); n <= 2^31.
  *  band     : DEVICE, n x (2q+1) doubles; b: DEVICE, n doubles.
- *  bounded  : DEVICE uint8[n] or NULL (all rows bounded); clip mode only.
- *  mode     : LCP_LINEAR (u = A^{-1} b) or LCP_CLIP (the paper's projected
+ *  bounded  : DEVICE uint8[n] or NULL (all rows bounded); clip and exact.
+ *  mode     : LCP_LINEAR (u = A^{-1} b); LCP_CLIP (the paper's projected
  *             partitioned solve; not the same as clipping A^{-1} b, since the
- *             inner unknowns use the projected outer ones).  LCP_EXACT is
- *             refused.
+ *             inner unknowns use the projected outer ones); LCP_EXACT (the
+ *             LCP of eq. 14 by the active-set iteration of paqif_solve_lcp,
+ *             A_0 = {bounded i : b_i <= 0}, each iteration one partitioned
+ *             solve with the rows and columns of A_k replaced by the identity
+ *             and b = 0 there; the host reads the number of changes after
+ *             every solve, so this mode synchronises `stream`).
+ *  max_iter : exact mode: at most this many solves (>= 1); else ignored.
  *  u        : DEVICE out, n doubles.
+ *  active_out: DEVICE out or NULL, uint8[n]: exact mode the final active
+ *             set, clip mode the projected rows, linear mode zeros.
  *  status   : DEVICE out, int32[1]: the largest SYS_* code of the block and
- *             reduced solves (SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE).
+ *             reduced solves of the last solve (SYS_OK, SYS_ZERO_PIVOT,
+ *             SYS_NONFINITE), or SYS_LCP_NOT_CONVERGED after max_iter solves.
+ *  iters    : DEVICE out or NULL, int32[1]: number of partitioned solves.
  *  workspace: DEVICE, paqif_partitioned_workspace_bytes(n, q, r) bytes
  *             (about (2q+1)(4q+5) n doubles; 0 = invalid arguments).
  * Returns PAQIF_EINVAL for invalid arguments before any launch.
@@ -211,8 +221,9 @@ int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *
  */
 size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r);
 int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double *band,
-                            const double *b, const uint8_t *bounded, int mode, double *u,
-                            int32_t *status, void *workspace, void *stream);
+                            const double *b, const uint8_t *bounded, int mode, int max_iter,
+                            double *u, uint8_t *active_out, int32_t *status, int32_t *iters,
+                            void *workspace, void *stream);
 
 /* ------------------------------------------------------------------------
  * Elastohydrodynamic lubrication (Sec. 3.3 of the paper)

@@ -104,8 +104,8 @@ def lib():
                                ctypes.POINTER(EhlOpts), vp, vp, vp, vp, vp, vp, d, ctypes.c_int,
                                vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_partitioned_workspace_bytes": ([i64, ctypes.c_int, i32], ctypes.c_size_t),
-        "paqif_solve_partitioned": ([vp, i64, ctypes.c_int, i32, vp, vp, vp, ctypes.c_int, vp,
-                                     vp, vp, vp], ctypes.c_int),
+        "paqif_solve_partitioned": ([vp, i64, ctypes.c_int, i32, vp, vp, vp, ctypes.c_int,
+                                     ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "cd_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
         "cd_example": ([ctypes.c_int, d, d, d, vp, vp, vp], ctypes.c_int),
         "cd_line_relax": ([vp, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp, vp,

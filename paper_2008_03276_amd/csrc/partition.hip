@@ -110,8 +110,11 @@ __global__ void part_offsets_kernel(PartGeo g, int64_t* eoffs, int64_t* eboff)
 
 // Expanded row e = t * Ni + ir: inner row ir of its block with right-hand
 // side t (0: f, 1 + j: column of outer unknown j).
+// With pins (the exact mode's active set): the inner systems' flags are
+// set from them, and the column of a pinned outer unknown is zero.
 __global__ void part_rhs_kernel(PartGeo g, const double* __restrict__ band,
-                                const double* __restrict__ f, double* __restrict__ erhs)
+                                const double* __restrict__ f, const uint8_t* __restrict__ pin,
+                                double* __restrict__ erhs, uint8_t* __restrict__ eact)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int W = 2 * g.q + 1;
@@ -120,15 +123,26 @@ __global__ void part_rhs_kernel(PartGeo g, const double* __restrict__ band,
     const int64_t ir = e - (int64_t)t * g.Ni;
     const int m = block_of_inner(g, ir);
     const int64_t row = ir + 2 * (int64_t)g.q * m + g.q;  // global row
-    erhs[e] = t == 0 ? f[row] : band_at(g, band, row, outer_col(g, m, t - 1));
+    if (pin) eact[e] = pin[row];
+    double v;
+    if (t == 0) {
+        v = f[row];
+    } else {
+        const int64_t col = outer_col(g, m, t - 1);
+        v = (pin && pin[col]) ? 0.0 : band_at(g, band, row, col);
+    }
+    erhs[e] = v;
 }
 
 // Reduced row R = 2 q m + c: S_m and g_m from the inner solutions next to
 // the outer row, plus the couplings to the neighbouring blocks.
+// A pinned outer unknown gets an identity row, and its column is zero in
+// the other rows (the inner solutions already vanish on pinned inner rows).
 __global__ void part_reduce_kernel(PartGeo g, const double* __restrict__ band,
                                    const double* __restrict__ f, const uint8_t* __restrict__ bounded,
-                                   const double* __restrict__ ex, double* __restrict__ rband,
-                                   double* __restrict__ rrhs, uint8_t* __restrict__ rbnd)
+                                   const uint8_t* __restrict__ pin, const double* __restrict__ ex,
+                                   double* __restrict__ rband, double* __restrict__ rrhs,
+                                   uint8_t* __restrict__ rbnd)
 {
     const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = g.q, N2 = 2 * q, RW = 4 * q + 1;
@@ -139,9 +153,16 @@ __global__ void part_reduce_kernel(PartGeo g, const double* __restrict__ band,
     const int64_t io = ioff(g, m);
     double* out = rband + R * RW;
     for (int s = 0; s < RW; s++) out[s] = 0.0;
+    rbnd[R] = bounded ? (bounded[row] ? 1 : 0) : 1;
+    if (pin && pin[row]) {
+        out[N2] = 1.0;
+        rrhs[R] = 0.0;
+        return;
+    }
     // S_m row c and g_m[c]
     double gv = f[row];
     for (int j = 0; j < N2; j++) {
+        if (pin && pin[outer_col(g, m, j)]) continue;
         double s = band_at(g, band, row, outer_col(g, m, j));
         for (int d = -q; d <= q; d++) {
             const int64_t col = row + d;
@@ -159,16 +180,17 @@ __global__ void part_reduce_kernel(PartGeo g, const double* __restrict__ band,
     if (c < q && m > 0) {
         for (int j = 0; j < q; j++) {
             const int64_t col = pstart(g, m) - q + j;
+            if (pin && pin[col]) continue;
             out[(int64_t)N2 * (m - 1) + q + j - R + N2] += band_at(g, band, row, col);
         }
     } else if (c >= q && m + 1 < g.r) {
         for (int j = 0; j < q; j++) {
             const int64_t col = pstart(g, m + 1) + j;
+            if (pin && pin[col]) continue;
             out[(int64_t)N2 * (m + 1) + j - R + N2] += band_at(g, band, row, col);
         }
     }
     rrhs[R] = gv;
-    rbnd[R] = bounded ? (bounded[row] ? 1 : 0) : 1;
 }
 
 // outer unknown R of the reduced solution, projected in clip mode (Step 5)
@@ -206,12 +228,18 @@ __global__ void part_combine_kernel(PartGeo g, const uint8_t* __restrict__ bound
 }
 
 // status = the largest code over the inner systems and the reduced system
+// (pinned inner solves run one active-set pass whose "not converged" code
+// carries no meaning here and is dropped)
 __global__ void part_status_kernel(const int32_t* __restrict__ est, int cnt,
-                                   const int32_t* __restrict__ rst, int32_t* __restrict__ status)
+                                   const int32_t* __restrict__ rst, int drop_lcp,
+                                   int32_t* __restrict__ status)
 {
     __shared__ int32_t red[256];
     int32_t v = threadIdx.x == 0 ? rst[0] : 0;
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) v = max(v, est[k]);
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        const int32_t c = est[k];
+        v = max(v, (drop_lcp && c == SYS_LCP_NOT_CONVERGED) ? SYS_OK : c);
+    }
     red[threadIdx.x] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -225,7 +253,9 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PartLayout {
     size_t eoffs, eboff, erhs, ex, est, eit, erec, eact;
-    size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, sub, total;
+    size_t roffs, rband, rrhs, rx, rbnd, rst, rit, rrec, ract, sub;
+    size_t mask, cnt;  // exact mode (top level only)
+    size_t total;
 };
 
 // q = 2: a reduced system of at least kNestRows rows (half-bandwidth 4) is
@@ -282,6 +312,8 @@ PartLayout part_layout(int64_t N, int q, int32_t r)
     L.sub = nests(q, (int64_t)K) ? take(part_layout((int64_t)K, 2 * q,
                                                     sub_blocks((int64_t)K, 2 * q)).total)
                                  : p;
+    L.mask = take((size_t)N);
+    L.cnt = take(sizeof(unsigned long long));
     L.total = p;
     return L;
 }
@@ -323,9 +355,11 @@ LcpArgs lcp_args(int32_t count, const int64_t* offs, const double* band, const d
     return la;
 }
 
+// One partitioned solve.  pin (or null): rows fixed at 0 (identity rows and
+// columns, right-hand side 0), the exact mode's current active set.
 int part_run(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
-             const double* b, const uint8_t* bounded, int mode, double* u, int32_t* status,
-             char* ws, hipStream_t s)
+             const double* b, const uint8_t* bounded, const uint8_t* pin, int mode, double* u,
+             int32_t* status, char* ws, hipStream_t s)
 {
     const PartLayout L = part_layout(n, q, r);
     PartGeo g;
@@ -349,24 +383,31 @@ int part_run(paqif_handle handle, int64_t n, int q, int32_t r, const double* ban
     int32_t* rst = reinterpret_cast<int32_t*>(ws + L.rst);
 
     hipLaunchKernelGGL(part_offsets_kernel, dim3(nblk(cnt + 1)), dim3(256), 0, s, g, eoffs, eboff);
-    hipLaunchKernelGGL(part_rhs_kernel, dim3(nblk(E)), dim3(256), 0, s, g, band, b, erhs);
+    uint8_t* eact = reinterpret_cast<uint8_t*>(ws + L.eact);
+    hipLaunchKernelGGL(part_rhs_kernel, dim3(nblk(E)), dim3(256), 0, s, g, band, b, pin, erhs,
+                       eact);
     if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
     // Steps 1-2: every block's inner system with its 2q+1 right-hand sides
     LcpArgs li = lcp_args(cnt, eoffs, band, erhs, nullptr, LCP_LINEAR, ex, est,
-                          reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec,
-                          reinterpret_cast<uint8_t*>(ws + L.eact));
+                          reinterpret_cast<int32_t*>(ws + L.eit), ws + L.erec, eact);
     li.band_off = eboff;
+    if (pin) {
+        // the kernel's exact mode, one solve, started from the pins in eact:
+        // the solve with those rows and columns replaced by the identity
+        li.mode = LCP_EXACT;
+        li.warm = 1;
+    }
     int e = dispatch_lcp(q, li, PREC_FP64, handle->layout[q_index(q)][0], s);
     if (e != PAQIF_OK) return e;
     // Steps 3-4: reduced band rows
-    hipLaunchKernelGGL(part_reduce_kernel, dim3(nblk(K)), dim3(256), 0, s, g, band, b, bounded, ex,
-                       rband, rrhs, rbnd);
+    hipLaunchKernelGGL(part_reduce_kernel, dim3(nblk(K)), dim3(256), 0, s, g, band, b, bounded, pin,
+                       ex, rband, rrhs, rbnd);
     if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
     // Step 4: the reduced system (half-bandwidth 2q) in plain linear mode;
     // its projection (Step 5) is applied where its values are read
     if (nests(q, K)) {
-        e = part_run(handle, K, 2 * q, sub_blocks(K, 2 * q), rband, rrhs, nullptr, LCP_LINEAR, rx,
-                     rst, ws + L.sub, s);
+        e = part_run(handle, K, 2 * q, sub_blocks(K, 2 * q), rband, rrhs, nullptr, nullptr,
+                     LCP_LINEAR, rx, rst, ws + L.sub, s);
     } else {
         // one system: lane layout 0 (a whole wavefront on it)
         hipLaunchKernelGGL(part_roffs_kernel, dim3(1), dim3(64), 0, s, K, roffs);
@@ -379,8 +420,83 @@ int part_run(paqif_handle handle, int64_t n, int q, int32_t r, const double* ban
     // Steps 5-7: projected outer unknowns, inner unknowns, their projection
     hipLaunchKernelGGL(part_combine_kernel, dim3(nblk(n)), dim3(256), 0, s, g, bounded,
                        mode == LCP_CLIP ? 1 : 0, ex, rx, rbnd, u);
-    hipLaunchKernelGGL(part_status_kernel, dim3(1), dim3(256), 0, s, est, cnt, rst, status);
+    hipLaunchKernelGGL(part_status_kernel, dim3(1), dim3(256), 0, s, est, cnt, rst,
+                       pin ? 1 : 0, status);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+// active flags of the linear / clip modes: clip mode marks the bounded rows
+// whose value is 0 after the projection
+__global__ void part_clipped_kernel(int64_t n, const uint8_t* __restrict__ bounded, int clip,
+                                    const double* __restrict__ u, uint8_t* __restrict__ act)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    act[i] = (clip && (!bounded || bounded[i]) && u[i] == 0.0) ? 1 : 0;
+}
+
+// exact mode: A_0 = {bounded i : b_i <= 0}
+__global__ void part_act0_kernel(int64_t n, const double* __restrict__ b,
+                                 const uint8_t* __restrict__ bounded, uint8_t* __restrict__ mask)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    mask[i] = ((!bounded || bounded[i]) && b[i] <= 0.0) ? 1 : 0;
+}
+
+__global__ void part_zero_kernel(unsigned long long* __restrict__ cnt)
+{
+    if (threadIdx.x == 0) cnt[0] = 0ull;
+}
+
+// w = A u - b with the caller's band; on bounded rows the next active set
+// {i in A : w_i > 0} u {i not in A : u_i < 0}; counts the changes and the
+// non-finite u.
+__global__ void part_update_kernel(PartGeo g, const double* __restrict__ band,
+                                   const double* __restrict__ b, const uint8_t* __restrict__ bounded,
+                                   const double* __restrict__ u, uint8_t* __restrict__ mask,
+                                   unsigned long long* __restrict__ cnt)
+{
+    // low 32 bits: active-set changes, high 32 bits: non-finite u
+    __shared__ unsigned long long red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long ch = 0;
+    if (i < g.N) {
+        const int q = g.q;
+        double w = -b[i];
+        for (int d = -q; d <= q; d++) {
+            const int64_t j = i + d;
+            if (j >= 0 && j < g.N) w = __builtin_fma(band[i * (2 * q + 1) + d + q], u[j], w);
+        }
+        const double ui = u[i];
+        if (!isfinite(ui)) ch += 1ull << 32;
+        if (!bounded || bounded[i]) {
+            const int cur = mask[i] != 0;
+            const int nxt = cur ? (w > 0.0) : (ui < 0.0);
+            if (nxt != cur) {
+                ch += 1;
+                mask[i] = (uint8_t)nxt;
+            }
+        }
+    }
+    red[threadIdx.x] = ch;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicAdd(cnt, red[0]);
+}
+
+__global__ void part_finish_kernel(int32_t* __restrict__ status, int32_t* __restrict__ iters,
+                                   int it, int converged, int nonfinite)
+{
+    if (threadIdx.x != 0) return;
+    int32_t st = status[0];
+    if (st == SYS_OK && nonfinite) st = SYS_NONFINITE;
+    if (st == SYS_OK && !converged) st = SYS_LCP_NOT_CONVERGED;
+    status[0] = st;
+    if (iters) iters[0] = it;
 }
 
 }  // namespace
@@ -395,14 +511,65 @@ size_t paqif_partitioned_workspace_bytes(int64_t n, int q, int32_t r)
 }
 
 int paqif_solve_partitioned(paqif_handle handle, int64_t n, int q, int32_t r, const double* band,
-                            const double* b, const uint8_t* bounded, int mode, double* u,
-                            int32_t* status, void* workspace, void* stream)
+                            const double* b, const uint8_t* bounded, int mode, int max_iter,
+                            double* u, uint8_t* active_out, int32_t* status, int32_t* iters,
+                            void* workspace, void* stream)
 {
-    if (!handle || !pq::part_valid(n, q, r) || !(mode == LCP_LINEAR || mode == LCP_CLIP) ||
-        !band || !b || !u || !status || !workspace)
+    if (!handle || !pq::part_valid(n, q, r) ||
+        !(mode == LCP_LINEAR || mode == LCP_CLIP || mode == LCP_EXACT) ||
+        (mode == LCP_EXACT && max_iter < 1) || !band || !b || !u || !status || !workspace)
         return PAQIF_EINVAL;
-    return pq::part_run(handle, n, q, r, band, b, bounded, mode, u, status,
-                        static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pq::PartLayout L = pq::part_layout(n, q, r);
+    uint8_t* mask = reinterpret_cast<uint8_t*>(ws + L.mask);
+    if (mode != LCP_EXACT) {
+        int e = pq::part_run(handle, n, q, r, band, b, bounded, nullptr, mode, u, status, ws, s);
+        if (e != PAQIF_OK) return e;
+        hipLaunchKernelGGL(pq::part_finish_kernel, dim3(1), dim3(64), 0, s, status, iters, 1, 1, 0);
+        if (active_out) {  // clip mode: the rows projected to 0; linear: none
+            hipLaunchKernelGGL(pq::part_clipped_kernel, dim3(pq::nblk(n)), dim3(256), 0, s, n,
+                               bounded, mode == LCP_CLIP ? 1 : 0, u, active_out);
+        }
+        return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+    }
+    // exact mode: active-set iteration around the partitioned solve; the
+    // host reads the number of changes after every solve (synchronises s)
+    pq::PartGeo g;
+    g.N = n;
+    g.q = q;
+    g.r = r;
+    g.Ni = n - 2 * (int64_t)q * r;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ws + L.cnt);
+    hipLaunchKernelGGL(pq::part_act0_kernel, dim3(pq::nblk(n)), dim3(256), 0, s, n, b, bounded,
+                       mask);
+    int it = 0, converged = 0, nonfinite = 0;
+    while (it < max_iter) {
+        int e = pq::part_run(handle, n, q, r, band, b, bounded, mask, LCP_LINEAR, u, status, ws, s);
+        if (e != PAQIF_OK) return e;
+        it++;
+        hipLaunchKernelGGL(pq::part_zero_kernel, dim3(1), dim3(64), 0, s, cnt);
+        hipLaunchKernelGGL(pq::part_update_kernel, dim3(pq::nblk(n)), dim3(256), 0, s, g, band, b,
+                           bounded, u, mask, cnt);
+        unsigned long long h = 0;
+        if (!pq::hip_ok(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s)) ||
+            !pq::hip_ok(hipStreamSynchronize(s)))
+            return PAQIF_EHIP;
+        nonfinite = (h >> 32) != 0;
+        if (nonfinite) break;
+        if ((h & 0xffffffffull) == 0) {
+            converged = 1;
+            break;
+        }
+    }
+    // the loop ends with the flags of the next iteration when not converged;
+    // the solution u belongs to the last solve
+    hipLaunchKernelGGL(pq::part_finish_kernel, dim3(1), dim3(64), 0, s, status, iters, it,
+                       converged, nonfinite);
+    if (active_out &&
+        !pq::hip_ok(hipMemcpyAsync(active_out, mask, (size_t)n, hipMemcpyDeviceToDevice, s)))
+        return PAQIF_EHIP;
+    return pq::hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
 }  // extern "C"

@@ -151,10 +151,11 @@ def partitioned_workspace_bytes(n, q, r):
     return int(B.lib().paqif_partitioned_workspace_bytes(int(n), int(q), int(r)))
 
 
-def solve_partitioned(band, b, r, mode=B.LCP_LINEAR, bounded=None, workspace=None):
+def solve_partitioned(band, b, r, mode=B.LCP_LINEAR, bounded=None, max_iter=64, workspace=None):
     """Partitioned PAQIF solve of one long band system over r blocks
     (``band``: (n, 2q+1) FP64 device tensor, ``b``: (n,)).  Returns
-    (u, status) with status a one-element int32 device tensor."""
+    dict(u, active, status, iters) with status and iters one-element int32
+    device tensors.  The exact mode synchronises the current stream."""
     _need(band, torch.float64, "band")
     _need(b, torch.float64, "b")
     if bounded is not None:
@@ -163,13 +164,17 @@ def solve_partitioned(band, b, r, mode=B.LCP_LINEAR, bounded=None, workspace=Non
     q = (w - 1) // 2
     if tuple(b.shape) != (n,) or w != 2 * q + 1:
         raise ValueError("band must be (n, 2q+1) and b (n,)")
-    u = torch.empty(n, dtype=torch.float64, device=band.device)
-    st = torch.empty(1, dtype=torch.int32, device=band.device)
+    dev = band.device
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    act = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    it = torch.empty(1, dtype=torch.int32, device=dev)
     if workspace is None:
         nb = partitioned_workspace_bytes(n, q, r)
-        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=band.device)
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
     code = B.lib().paqif_solve_partitioned(handle(), n, q, int(r), _ptr(band), _ptr(b),
-                                           _ptr(bounded), int(mode), _ptr(u), _ptr(st),
-                                           _ptr(workspace), _stream())
+                                           _ptr(bounded), int(mode), int(max_iter), _ptr(u),
+                                           _ptr(act), _ptr(st), _ptr(it), _ptr(workspace),
+                                           _stream())
     B.check(code, "paqif_solve_partitioned")
-    return u, st
+    return dict(u=u, active=act, status=st, iters=it)

@@ -13,6 +13,10 @@ so the results differ by rounding order only: 1e-11 relative.
     the oracle's partitioned solve (clip);
   * the benchmark's size (n = 2^20, q = 2, r = 512, linear) against the
     oracle's monolithic AQIF solve in full;
+  * exact mode (the LCP of eq. 14 by an active-set iteration around the
+    partitioned solve): u within 1e-11 of the oracle's exact LCP solver and
+    the same active set, element by element (the solution of an LCP with a
+    strictly diagonally dominant matrix is unique), small to n = 2^20;
   * argument checks.
 """
 import numpy as np
@@ -31,13 +35,16 @@ CASES = [(60, 2, 4), (61, 2, 4), (97, 2, 7), (50, 2, 1), (35, 2, 7), (200, 4, 6)
          (3000, 2, 128), (2601, 2, 131)]
 
 
-def _gpu(P, band, f, r, mode, bounded=None):
+def _gpu(P, band, f, r, mode, bounded=None, full=False):
     dev = torch.device("cuda")
     bnd = None if bounded is None else torch.as_tensor(bounded, dtype=torch.uint8, device=dev)
-    u, st = P.paqif.solve_partitioned(torch.as_tensor(band, device=dev),
-                                      torch.as_tensor(f, device=dev), r, mode=mode, bounded=bnd)
+    res = P.paqif.solve_partitioned(torch.as_tensor(band, device=dev),
+                                    torch.as_tensor(f, device=dev), r, mode=mode, bounded=bnd)
     torch.cuda.synchronize()
-    return u.cpu().numpy(), int(st.cpu()[0])
+    out = {k: v.cpu().numpy() for k, v in res.items()}
+    if full:
+        return out
+    return out["u"], int(out["status"][0])
 
 
 def _rel(a, b):
@@ -86,11 +93,61 @@ def test_parity_bench_size(gpu):
     assert _rel(u, ref) <= 1e-11
 
 
+EXACT_CASES = [(60, 2, 4), (97, 2, 7), (50, 2, 1), (200, 4, 6), (1001, 4, 21), (3000, 2, 128),
+               (20000, 2, 256), (20011, 4, 40)]
+
+
+@pytest.mark.parametrize("N,q,r", EXACT_CASES)
+@pytest.mark.parametrize("masked", [False, True])
+def test_exact_matches_oracle_lcp(gpu, N, q, r, masked):
+    print(f"partitioned exact N={N} q={q} r={r} masked={masked}", flush=True)
+    band, f = synth.long_system(N, q, seed=3 * N + r)
+    bounded = None
+    if masked:
+        bounded = (np.random.default_rng(N + 1).random(N) < 0.7).astype(np.uint8)
+    g = _gpu(gpu, band, f, r, oracle.EXACT, bounded, full=True)
+    assert int(g["status"][0]) == 0
+    o = oracle.lcp_solve(band, f, bounded=bounded, mode=oracle.EXACT, max_iter=64)
+    assert o["status"] == 0
+    assert _rel(g["u"], o["u"]) <= 1e-11
+    assert np.array_equal(g["active"], o["active"])
+    assert 1 <= int(g["iters"][0]) <= 64
+
+
+def test_exact_bench_size(gpu):
+    N, q, r = 1 << 20, 2, 2048
+    print(f"partitioned exact full N={N} q={q} r={r}", flush=True)
+    band, f = synth.long_system(N, q, seed=5)
+    g = _gpu(gpu, band, f, r, oracle.EXACT, full=True)
+    assert int(g["status"][0]) == 0
+    o = oracle.lcp_solve(band, f, mode=oracle.EXACT, max_iter=64)
+    assert o["status"] == 0
+    assert _rel(g["u"], o["u"]) <= 1e-11
+    assert np.array_equal(g["active"], o["active"])
+
+
+def test_exact_not_converged_status(gpu):
+    # one active-set solve is not enough from A_0 here: status says so
+    band, f = synth.long_system(2000, 2, seed=9)
+    dev = torch.device("cuda")
+    res = gpu.paqif.solve_partitioned(torch.as_tensor(band, device=dev),
+                                      torch.as_tensor(f, device=dev), 16, mode=oracle.EXACT,
+                                      max_iter=1)
+    torch.cuda.synchronize()
+    assert int(res["status"].cpu()[0]) == oracle.LCP_NOT_CONVERGED
+    assert int(res["iters"].cpu()[0]) == 1
+
+
 def test_invalid_arguments(gpu):
     band, f = synth.long_system(100, 2, seed=1)
-    for r, mode in ((0, 0), (21, 0), (4, oracle.EXACT)):      # r = 21: blocks of 4 < 2q+1 rows
+    for r, mode in ((0, 0), (21, 0), (4, 7)):      # r = 21: blocks of 4 < 2q+1 rows; mode 7
         with pytest.raises(RuntimeError):
             _gpu(gpu, band, f, r, mode)
+    dev = torch.device("cuda")
+    with pytest.raises(RuntimeError):
+        gpu.paqif.solve_partitioned(torch.as_tensor(band, device=dev),
+                                    torch.as_tensor(f, device=dev), 4, mode=oracle.EXACT,
+                                    max_iter=0)
     band8, f8 = synth.long_system(200, 8, seed=1)            # q = 8: reduced band 16 unsupported
     with pytest.raises(RuntimeError):
         _gpu(gpu, band8, f8, 4, oracle.LINEAR)
