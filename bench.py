@@ -384,6 +384,29 @@ def partitioned_leg(P, torch, synth, args):
                 lay[str(L)] = round(e0.elapsed_time(e1), 4)
             P.paqif.set_layout(q, P.PREC_FP64, keep)
             entry["ms_by_layout_at_best_r"] = lay
+            # the same solve replayed from a captured graph (launch overhead
+            # of its ~10 kernels removed)
+            st_ = torch.cuda.Stream()
+            st_.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st_):
+                P.paqif.solve_partitioned(band, f, int(best), workspace=ws)
+            torch.cuda.current_stream().wait_stream(st_)
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                P.paqif.solve_partitioned(band, f, int(best), workspace=ws)
+            gr.replay()
+            gts = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                gr.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                gts.append(e0.elapsed_time(e1))
+            entry["graph_replay_ms_at_best_r"] = round(float(np.median(gts)), 4)
+            del gr
             del ws
         if n == 1 << 20 and not args.part_case:
             # the unpartitioned system alone: lane layout 0 (a wavefront per system)

@@ -153,3 +153,36 @@ def test_invalid_arguments(gpu):
         _gpu(gpu, band8, f8, 4, oracle.LINEAR)
     assert gpu.paqif.partitioned_workspace_bytes(100, 2, 21) == 0
     assert gpu.paqif.partitioned_workspace_bytes(100, 2, 20) > 0
+
+
+def test_graph_replay_matches_eager(gpu):
+    # linear and clip modes launch kernels only (no host synchronisation, no
+    # memset), so the solve can be captured; every replay, with other work
+    # between replays, must give the eager result bit for bit
+    N, q, r = 20000, 2, 256
+    band_h, f_h = synth.long_system(N, q, seed=21)
+    dev = torch.device("cuda")
+    band = torch.as_tensor(band_h, device=dev)
+    f = torch.as_tensor(f_h, device=dev)
+    ws = torch.empty(gpu.paqif.partitioned_workspace_bytes(N, q, r), dtype=torch.uint8, device=dev)
+    for mode in (oracle.LINEAR, oracle.CLIP):
+        eager = gpu.paqif.solve_partitioned(band, f, r, mode=mode, workspace=ws)["u"].clone()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gpu.paqif.solve_partitioned(band, f, r, mode=mode, workspace=ws)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = gpu.paqif.solve_partitioned(band, f, r, mode=mode, workspace=ws)
+        for k in range(3):
+            junk = torch.randn(1 << 16, device=dev).sum()   # eager work between replays
+            torch.cuda.synchronize()
+            out["u"].zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out["u"], eager), (mode, k)
+            assert int(out["status"].cpu()[0]) == 0
+            del junk
