@@ -7,8 +7,8 @@ U(-1, 1), diagonal = sum|off-diagonals| + U(0.5, 1.5), right-hand side
 N(0, 1).  One step = the exact LCP solve (active-set PAQIF, FP64) of all three
 batches, 12288 solves; inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
-GPU (batches would shard by total rows across GPUs with no exchange).
+Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark runs on
+one GPU (batches would shard by total rows across GPUs with no exchange).
 """
 import argparse
 import json
@@ -548,8 +548,8 @@ def main():
                     help="run only the convection-diffusion leg (one JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on a single GPU; --gpus above 1 is not supported "
-              "(batches shard by rows across GPUs with no exchange; see the design notes)",
+        print("bench.py: runs on a single GPU; --gpus above 1 is not supported "
+              "(batches shard by rows across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 
