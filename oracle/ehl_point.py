@@ -17,7 +17,8 @@ Discretisation (eqs. 62-65 on the 2D grid, flow in +X): for interior (i, j)
          - [(rho H)*_{i+1/2,j} - (rho H)*_{i-1/2,j}] / hx,
 face values eps_{i+-1/2,j} = (eps_ij + eps_{i+-1,j}) / 2 (eq. 63) and the TVD
 flux of each x-row exactly as in the line contact (van Leer, psi = 0 at the
-inlet face).
+inlet face; optionally the kappa-scheme slope of Sec. 2, eqs. 57-59, as in
+ehl_line.slope).
 
 Iteration (alternating line sweeps, eqs. 60, 62, 66-75): one step is an
 x-sweep followed by a y-sweep.  A sweep solves, for every interior line of
@@ -86,17 +87,18 @@ def film(P, H0, X, Y, hx, hy, rough=None):
     return H if rough is None else H + rough
 
 
-def x_flux(rH):
+def x_flux(rH, kappa=None):
     """(rho H)* at the faces i+1/2 of every x-row, f[t, :] for t = 0..Nx-2,
-    and the limiter derivatives pa = dpsi/dD+, pb = dpsi/dD- at nodes 1..Nx-2."""
-    psi, pa, pb = EL.vanleer(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1])
+    and the slope derivatives pa = dpsi/dD+, pb = dpsi/dD- at nodes 1..Nx-2
+    (van Leer; with kappa given the kappa-scheme slope of Sec. 2, eqs. 57-59)."""
+    psi, pa, pb = EL.slope(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1], kappa)
     f = np.empty((rH.shape[0] - 1, rH.shape[1]))
     f[0] = rH[0]
     f[1:] = rH[1:-1] + 0.5 * psi
     return f, pa, pb
 
 
-def residual(P, H, ph, lam, hx, hy):
+def residual(P, H, ph, lam, hx, hy, kappa=None):
     """R_ij on the interior nodes, shape (Nx-2, Ny-2), plus the state."""
     s = EL.state(P, H, ph, lam)
     eps, rH = s["eps"], s["rH"]
@@ -104,7 +106,7 @@ def residual(P, H, ph, lam, hx, hy):
     ey = 0.5 * (eps[:, :-1] + eps[:, 1:])        # faces j+1/2
     dPx = P[1:, :] - P[:-1, :]
     dPy = P[:, 1:] - P[:, :-1]
-    f, _, _ = x_flux(rH)
+    f, _, _ = x_flux(rH, kappa)
     Rx = (ex[1:, 1:-1] * dPx[1:, 1:-1] - ex[:-1, 1:-1] * dPx[:-1, 1:-1]) / hx ** 2
     Ry = (ey[1:-1, 1:] * dPy[1:-1, 1:] - ey[1:-1, :-1] * dPy[1:-1, :-1]) / hy ** 2
     Rc = (f[1:, 1:-1] - f[:-1, 1:-1]) / hx
@@ -126,7 +128,8 @@ def classify(P, eps, hx, hy):
     return d
 
 
-def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=EL.LIMJAC):
+def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=EL.LIMJAC,
+                  kappa=None):
     """Band systems of every interior line of one sweep direction.
 
     axis = 0: x-lines (one per interior j, positions i); axis = 1: y-lines.
@@ -204,13 +207,14 @@ def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=
     dist_c = dist[lines][:, 1:-1]
     if axis == 0:
         pa, pb = EL.limiter_jacobian(rH[lines][:, 1:-1] - rH[lines][:, :-2],
-                                     rH[lines][:, 2:] - rH[lines][:, 1:-1], limjac)  # node t at [:, t-1]
+                                     rH[lines][:, 2:] - rH[lines][:, 1:-1], limjac,
+                                     kappa)  # node t at [:, t-1]
     else:
         # the x-flux of row j depends on rho H at x-columns l-2 .. l+1; their
         # response to sigma on column l: the -sigma/4 moved to the columns
         # l +- 1 and the distributed kernel at x-offset a
         pa_all, pb_all = EL.limiter_jacobian(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1],
-                                             limjac)  # row t-1 -> column t
+                                             limjac, kappa)  # row t-1 -> column t
 
         def kx(a, d):
             return kv(k2[abs(a)], d)
@@ -281,7 +285,7 @@ def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=
         dR = along + across - conv
         J[:, :, s + 4] = np.where(valid[None, :], dR, 0.0)
     A = -J
-    R2, _ = residual(P, H, ph, lam, hx, hy)
+    R2, _ = residual(P, H, ph, lam, hx, hy, kappa)
     Rl = T(R2)                                   # (lines, n)
     b = np.einsum("lrs,lrs->lr", A, _shifted(P_l[:, 1:-1])) + Rl
     dr = T(direct)[lines]
@@ -325,14 +329,16 @@ def sweep_update(P, sigma_g, direct, omega):
     return Pn
 
 
-def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color):
+def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color,
+                kappa=None):
     """Solve the lines of one sweep direction (color None: all lines, else
     the lines whose index has that parity) and apply their changes."""
     _, lam, ph = moes_point(M, L)
     H = film(P, H0, X, Y, hx, hy, rough)
     st = EL.state(P, H, ph, lam)
     direct = classify(P, st["eps"], hx, hy)
-    A, b, bounded = sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms)
+    A, b, bounded = sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms,
+                                  kappa=kappa)
     T = (lambda a: a.T) if axis == 0 else (lambda a: a)
     Pl = T(P)[1:-1, 1:-1]
     frozen = ~T(direct)[1:-1, 1:-1] if axis == 1 else np.zeros(Pl.shape, dtype=bool)
@@ -347,14 +353,16 @@ def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, 
     return sweep_update(P, sigma_g, direct, omega)
 
 
-def half_sweep(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, c_h0, kterms, lcp, rough=None):
+def half_sweep(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, c_h0, kterms, lcp, rough=None,
+               kappa=None):
     """One sweep direction then the H0 update.  The lines are solved in two
     colours (odd lines, then even ones with the film re-evaluated): with all
     lines at once the weighted changes of neighbouring lines can cancel
     (sigma != 0 with zero net change, a false fixed point), and for y-lines
     the x-flux couples each column to its upstream neighbours."""
     for color in (1, 0):
-        P = _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color)
+        P = _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color,
+                        kappa)
     H0n = H0 - c_h0 * (LOAD - hx * hy * P.sum())
     return P, H0n
 
@@ -371,7 +379,7 @@ def start_h0(X, Y, hx, hy, M):
 
 
 def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.02, kterms=2, max_steps=400, tol=1e-12,
-                rough=None, P=None, H0=None, lcp=None):
+                rough=None, P=None, H0=None, lcp=None, kappa=None):
     """Alternating x/y line sweeps to convergence.  Stops when max |P change|
     over one x+y step <= t max(1, |P|_inf) and |2pi/3 - hx hy sum P| <= t,
     t = max(tol, 4 max(Nx, Ny) eps) (status 0), else status 6.  Returns dict(P, H0, H, Hmin, iters, status,
@@ -388,8 +396,10 @@ def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.02, kterms=2, max_steps=400, tol
     tl = max(tol, 4.0 * max(Nx, Ny) * np.finfo(np.float64).eps)
     it = 0
     for it in range(1, max_steps + 1):
-        P1, H0 = half_sweep(P, H0, X, Y, hx, hy, k2, M, L, 0, omega, c_h0, kterms, lcp, rough)
-        P2, H0 = half_sweep(P1, H0, X, Y, hx, hy, k2, M, L, 1, omega, c_h0, kterms, lcp, rough)
+        P1, H0 = half_sweep(P, H0, X, Y, hx, hy, k2, M, L, 0, omega, c_h0, kterms, lcp, rough,
+                            kappa)
+        P2, H0 = half_sweep(P1, H0, X, Y, hx, hy, k2, M, L, 1, omega, c_h0, kterms, lcp, rough,
+                            kappa)
         dP = np.abs(P2 - P).max()
         P = P2
         if not np.isfinite(dP):

@@ -5,13 +5,15 @@
     (a^3 p_h), M = W (2U)^(-3/4), L = G (2U)^(1/4));
   * the line Jacobians of both sweep directions against finite differences of
     the 2D residual where the line model is exact (rigid film, all nodes
-    direct);
+    direct), with the van Leer slope and with the kappa-scheme (kappa = 0,
+    1/3, -1);
   * the 2D residual in flux form: its sum over the interior telescopes to the
     boundary fluxes;
   * the weighted change of eq. 69 conserves the change of an interior
     distributive node (sigma - 4 sigma/4 = 0);
-  * the converged 33 x 33 contact: complementarity, load balance 2 pi/3,
-    y-mirror symmetry, positive film.
+  * the converged 33 x 33 contact (van Leer, and the kappa-scheme with
+    kappa = 1/3): complementarity, load balance 2 pi/3, y-mirror symmetry,
+    positive film.
 """
 import numpy as np
 import pytest
@@ -48,14 +50,15 @@ def _rigid_state(Nx, Ny, M=20.0, seed=0):
 
 
 @pytest.mark.parametrize("axis", [0, 1])
-def test_line_jacobian_matches_finite_differences_rigid_direct(axis):
+@pytest.mark.parametrize("kappa", [None, 0.0, 1.0 / 3.0, -1.0])
+def test_line_jacobian_matches_finite_differences_rigid_direct(axis, kappa):
     Nx, Ny = 15, 11
     X, Y, hx, hy, P, H, lam, ph = _rigid_state(Nx, Ny)
     st = OL.state(P, H, ph, lam)
     direct = np.ones((Nx, Ny), dtype=bool)
     k2 = np.zeros((Nx, Ny))                       # rigid film: H does not move
-    A, _, _ = OP.sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, 2, limjac=0)
-    R0, _ = OP.residual(P, H, ph, lam, hx, hy)
+    A, _, _ = OP.sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, 2, limjac=0,
+                               kappa=kappa)
     nl, nn = (Ny, Nx) if axis == 0 else (Nx, Ny)
     e = 1e-7
     worst = 0.0
@@ -65,8 +68,8 @@ def test_line_jacobian_matches_finite_differences_rigid_direct(axis):
             Pp, Pm = P.copy(), P.copy()
             Pp[node] += e
             Pm[node] -= e
-            Rp, _ = OP.residual(Pp, H, ph, lam, hx, hy)
-            Rm, _ = OP.residual(Pm, H, ph, lam, hx, hy)
+            Rp, _ = OP.residual(Pp, H, ph, lam, hx, hy, kappa)
+            Rm, _ = OP.residual(Pm, H, ph, lam, hx, hy, kappa)
             col = (Rp - Rm) / (2 * e)
             col_line = col[:, l - 1] if axis == 0 else col[l - 1, :]
             for s in range(-4, 5):
@@ -139,3 +142,23 @@ def test_converged_point_contact(converged):
     # Hertzian size (the outlet lobes of EHL can exceed the centre value)
     i, j = np.unravel_index(np.argmax(P), P.shape)
     assert r["X"][i] ** 2 + r["Y"][j] ** 2 < 1.0 and 0.8 < P.max() < 1.5
+
+
+def test_converged_point_contact_kappa_scheme():
+    # kappa = 1/3: complementarity of the kappa-scheme residual, load balance,
+    # y-mirror symmetry and a positive film, like the van Leer contact
+    k = 1.0 / 3.0
+    r = OP.solve_point(20.0, 10.0, 33, 33, tol=1e-11, max_steps=1200, kappa=k)
+    assert r["status"] == 0
+    P, H, hx, hy = r["P"], r["H"], r["hx"], r["hy"]
+    _, lam, ph = OP.moes_point(20.0, 10.0)
+    R, st = OP.residual(P, H, ph, lam, hx, hy, k)
+    Pi = P[1:-1, 1:-1]
+    scale = np.abs(st["rH"]).max() / hx
+    press = Pi > 1e-8
+    assert (P >= 0).all()
+    assert np.abs(R[press]).max() <= 1e-6 * scale
+    assert (-R[~press] >= -1e-6 * scale).all()
+    assert abs(hx * hy * P.sum() - OP.LOAD) <= 1e-10
+    assert np.abs(P - P[:, ::-1]).max() <= 1e-12
+    assert H.min() > 0
