@@ -310,6 +310,8 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
     pa.B = B;
     pa.kterms = opts->kernel_terms;
     pa.limjac = opts->limiter_jacobian;
+    pa.conv = opts->convection;
+    pa.kappa = opts->kappa;
     pa.hx = hx;
     pa.hy = hy;
     pa.k2 = dws;
@@ -560,7 +562,6 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H0 || !Hmin || !status || !iters || !workspace) return PAQIF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (valid_point(grid) && opts->convection != 0) return PAQIF_EINVAL;  // van Leer only
     if (valid_point(grid)) {
         if (rough) return PAQIF_EINVAL;  // roughness is a line-contact input
         return point_newton(handle, grid, params, B, opts, P, H0, H, Hmin, status, iters,
@@ -771,7 +772,7 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
         return PAQIF_EINVAL;
     if ((axis != 0 && axis != 1) || (color != 0 && color != 1)) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
-    if (opts->convection != 0) return PAQIF_EINVAL;  // point contact: van Leer only
+    if (!valid_convection(opts)) return PAQIF_EINVAL;
     if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H_el || !H0 || !band || !rhs || !bounded || !workspace)
@@ -817,6 +818,8 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
     pa.color = color;
     pa.kterms = opts->kernel_terms;
     pa.limjac = opts->limiter_jacobian;
+    pa.conv = opts->convection;
+    pa.kappa = opts->kappa;
     pa.hx = na.hx;
     pa.hy = na.hy;
     pa.k2 = k2;

@@ -89,6 +89,8 @@ int launch_point_nodes(const PointNodeArgs& a, hipStream_t s);
 
 struct PointAssembleArgs {
     int Nx, Ny, B, axis, color, kterms, limjac;
+    int conv;      // 0 van Leer slope, 1 kappa-scheme slope (Sec. 2)
+    double kappa;
     double hx, hy;
     const double* k2;  // Nx x Ny kernel table
     const double *P, *eps, *rH, *rho, *drhoH, *eP, *eH;

@@ -108,4 +108,14 @@ PQ_DEV void convective_slope(int conv, double kappa, int limjac, double dm, doub
     limiter_jacobian(limjac, dm, dp, pa, pb);
 }
 
+// Partials of the slope only (the Newton-matrix coefficients pa = d/dD+,
+// pb = d/dD-): limiter_jacobian(limjac) for van Leer, the kappa-scheme's
+// constants for conv 1 (zero with limjac 2, the first-order matrix).
+PQ_DEV void slope_partials(int conv, double kappa, int limjac, double dm, double dp, double& pa,
+                           double& pb)
+{
+    double psi;
+    convective_slope(conv, kappa, limjac, dm, dp, psi, pa, pb);
+}
+
 }  // namespace pq

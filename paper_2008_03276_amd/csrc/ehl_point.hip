@@ -188,13 +188,13 @@ __global__ void __launch_bounds__(256) point_assemble_kernel(PointAssembleArgs a
         const double eym = 0.5 * (at(a.eps, i, j) + at(a.eps, i, j - 1));
         const double Pc = at(P, i, j);
         double psi, pa, pb;
-        van_leer(at(a.rH, i, j) - at(a.rH, i - 1, j), at(a.rH, i + 1, j) - at(a.rH, i, j), psi,
-                 pa, pb);
+        convective_slope(a.conv, a.kappa, a.limjac, at(a.rH, i, j) - at(a.rH, i - 1, j),
+                         at(a.rH, i + 1, j) - at(a.rH, i, j), psi, pa, pb);
         const double fi = at(a.rH, i, j) + 0.5 * psi;
         double fm;
         if (i - 1 >= 1) {
-            van_leer(at(a.rH, i - 1, j) - at(a.rH, i - 2, j), at(a.rH, i, j) - at(a.rH, i - 1, j),
-                     psi, pa, pb);
+            convective_slope(a.conv, a.kappa, a.limjac, at(a.rH, i - 1, j) - at(a.rH, i - 2, j),
+                             at(a.rH, i, j) - at(a.rH, i - 1, j), psi, pa, pb);
             fm = at(a.rH, i - 1, j) + 0.5 * psi;
         } else {
             fm = at(a.rH, 0, j);
@@ -222,13 +222,17 @@ __global__ void __launch_bounds__(256) point_assemble_kernel(PointAssembleArgs a
     double pa0 = 0, pb0 = 0, pa1 = 0, pb1 = 0;
     const int lj = a.limjac;
     if (a.axis == 0) {
-        limiter_jacobian(lj, rH(l, p) - rH(l, p - 1), rH(l, p + 1) - rH(l, p), pa0, pb0);
+        slope_partials(a.conv, a.kappa, lj, rH(l, p) - rH(l, p - 1), rH(l, p + 1) - rH(l, p), pa0,
+                       pb0);
         if (p - 1 >= 1)
-            limiter_jacobian(lj, rH(l, p - 1) - rH(l, p - 2), rH(l, p) - rH(l, p - 1), pa1, pb1);
+            slope_partials(a.conv, a.kappa, lj, rH(l, p - 1) - rH(l, p - 2),
+                           rH(l, p) - rH(l, p - 1), pa1, pb1);
     } else {
-        limiter_jacobian(lj, rH(l, p) - rH(l - 1, p), rH(l + 1, p) - rH(l, p), pa0, pb0);
+        slope_partials(a.conv, a.kappa, lj, rH(l, p) - rH(l - 1, p), rH(l + 1, p) - rH(l, p), pa0,
+                       pb0);
         if (l - 1 >= 1)
-            limiter_jacobian(lj, rH(l - 1, p) - rH(l - 2, p), rH(l, p) - rH(l - 1, p), pa1, pb1);
+            slope_partials(a.conv, a.kappa, lj, rH(l - 1, p) - rH(l - 2, p),
+                           rH(l, p) - rH(l - 1, p), pa1, pb1);
     }
     double contrib = 0.0;
     {

@@ -219,7 +219,5 @@ def test_kappa_scheme_rejected_where_not_supported(gpu):
     P = gpu.ehl
     # the library refuses the options (the workspace query returns 0 for
     # invalid options, the solve returns PAQIF_EINVAL)
-    with pytest.raises((RuntimeError, ValueError)):  # point contact: van Leer only
-        P.solve_point([200.0], [10.0], 17, 17, opts=P.default_opts(convection=1, kappa=0.0))
     with pytest.raises((RuntimeError, ValueError)):  # out of range
         P.solve_line([20.0], [10.0], 65, opts=P.default_opts(convection=1, kappa=1.5))

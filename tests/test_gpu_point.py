@@ -4,7 +4,10 @@
     every line against the oracle's sweep systems, FP64 elementwise formulas
     in another evaluation order: 1e-11 of the row scale plus 1e-14 of the
     instance scale (the line-contact assembly bound), masks exact;
-  * converged alternating-sweep solution on 33 x 33 nodes: P, H0, Hmin
+  * the same with the kappa-scheme convection (kappa = 0, 1/3, -1; exact and
+    first-order Newton matrix);
+  * converged alternating-sweep solution on 33 x 33 nodes (van Leer, and
+    the kappa-scheme with kappa = 1/3): P, H0, Hmin
     within 1e-9 relative (both sides stop at max |dP| <= 1e-12 per step;
     with a contraction of about 0.97 per step each is within ~3e-11 of the
     fixed point);
@@ -39,13 +42,26 @@ def _state(Nx, Ny, seed):
 @pytest.mark.parametrize("kterms", [1, 2])
 @pytest.mark.parametrize("limjac", [0, 1])
 def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms, limjac):
+    _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, None)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("limjac", [0, 2])
+@pytest.mark.parametrize("kappa", [0.0, 1.0 / 3.0, -1.0])
+def test_point_sweep_assembly_kappa_scheme(gpu, axis, limjac, kappa):
+    _check_assembly(gpu, 17, 13, axis, 2, limjac, kappa)
+
+
+def _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, kappa):
     E = gpu.ehl
     Ms, Ls, H0s = [20.0, 200.0], [10.0, 8.0], [-0.5, -0.9]
     X, Y, hx, hy, _ = _state(Nx, Ny, 0)
     Ps = np.stack([_state(Nx, Ny, s)[4] for s in (1, 2)])
     Hel = np.stack([odef.point_deformation(Ps[b], hx, hy) for b in range(2)])
     k2 = odef.point_kernel(Nx, Ny, hx, hy)
-    opts = E.default_opts(kernel_terms=kterms, limiter_jacobian=limjac)
+    opts = E.default_opts(kernel_terms=kterms, limiter_jacobian=limjac,
+                          convection=0 if kappa is None else 1,
+                          kappa=0.0 if kappa is None else kappa)
     grid = E.point_grid(Nx, Ny)
     for color in (1, 0):
         g = E.point_sweep_assemble(grid, E.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
@@ -61,7 +77,7 @@ def test_point_sweep_assembly(gpu, Nx, Ny, axis, kterms, limjac):
             st = OL.state(Ps[b], H, ph, lam)
             direct = OP.classify(Ps[b], st["eps"], hx, hy)
             A, rhs, bounded = OP.sweep_systems(Ps[b], H, st, ph, lam, hx, hy, k2, direct, axis,
-                                               kterms, limjac)
+                                               kterms, limjac, kappa)
             assert (g["direct"][b] == direct.astype(np.uint8)).all()
             inst = np.abs(A).max()
             for slot, l in enumerate(lines):
@@ -87,6 +103,22 @@ def test_point_newton_matches_oracle(gpu, oracle_33):
     o = oracle_33
     r = E.solve_point([20.0], [10.0], 33, 33,
                       opts=E.default_opts(tol=1e-12, max_newton=1500, c_h0=0.02))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    P = r["P"][0].cpu().numpy()
+    assert np.abs(P - o["P"]).max() <= 1e-9 * np.abs(o["P"]).max()
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-9 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-9 * abs(o["Hmin"])
+
+
+def test_point_newton_kappa_scheme_matches_oracle(gpu):
+    k = 1.0 / 3.0
+    o = OP.solve_point(20.0, 10.0, 33, 33, tol=1e-12, max_steps=1500, kappa=k)
+    assert o["status"] == 0
+    E = gpu.ehl
+    r = E.solve_point([20.0], [10.0], 33, 33,
+                      opts=E.default_opts(tol=1e-12, max_newton=1500, c_h0=0.02, convection=1,
+                                          kappa=k))
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 0
     P = r["P"][0].cpu().numpy()
