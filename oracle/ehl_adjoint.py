@@ -27,9 +27,10 @@ from . import deform
 from . import ehl_line as E
 
 
-def partials(P, H, ph, lam, h):
+def partials(P, H, ph, lam, h, kappa=None):
     """Dense partial derivatives of R_i (interior rows) with respect to the
-    node pressures P_m (at fixed film), the node films H_m, lam and p_h.
+    node pressures P_m (at fixed film), the node films H_m, lam and p_h
+    (van Leer slope; with kappa given the kappa-scheme slope of ehl_line).
 
     Returns (RP, RH, Rlam, Rph): RP, RH of shape (N-2, N)."""
     N = len(P)
@@ -41,7 +42,7 @@ def partials(P, H, ph, lam, h):
     eH = 3.0 * rho * H ** 2 / lam_eta                 # d eps / dH
     dm = rH[1:-1] - rH[:-2]
     dp = rH[2:] - rH[1:-1]
-    _, pa, pb = E.vanleer(dm, dp)                     # index t -> node t+1
+    _, pa, pb = E.slope(dm, dp, kappa)                # index t -> node t+1
     Reps = np.zeros((n, N))
     RrH = np.zeros((n, N))
     Rp = np.zeros((n, N))
@@ -78,7 +79,7 @@ def partials(P, H, ph, lam, h):
     return RP, RH, Rlam, Rph
 
 
-def adjoint_gradients(P, H0, M, L, N, rough=None):
+def adjoint_gradients(P, H0, M, L, N, rough=None, kappa=None):
     """Gradients of H0 and Hmin at a converged state.
 
     Returns dict with dH0_dM, dH0_dL, dHmin_dM, dHmin_dL, dH0_drough (N),
@@ -87,7 +88,7 @@ def adjoint_gradients(P, H0, M, L, N, rough=None):
     K = deform.line_matrix(N, h)
     _, lam, ph = E.moes_line(M, L)
     H = E.film(P, H0, x, deform.line_kernel(N, h), rough)
-    RP, RH, Rlam, Rph = partials(P, H, ph, lam, h)
+    RP, RH, Rlam, Rph = partials(P, H, ph, lam, h, kappa)
     inact = np.where(P[1:-1] > 0.0)[0]           # rows r (node r+1) with P > 0
     cols = inact + 1                              # node indices
     nI = len(inact)

@@ -4,7 +4,11 @@
     kernel) and to H0 against central finite differences of the residual map;
   * the adjoint gradients dH0/dM, dH0/dL, dHmin/dM, dHmin/dL and dHmin/droughness
     against central differences of re-converged solutions (step 1e-6
-    relative), with the active set and arg-min checked unchanged.
+    relative), with the active set and arg-min checked unchanged;
+  * with the kappa-scheme convection (kappa = 1/3): every pressurised column
+    of the dense Jacobian against central differences (the slope is linear,
+    so no branch switches), and dH0/dM, dHmin/dM, dH0/dL against central
+    differences of re-converged kappa-scheme solutions.
 """
 import numpy as np
 import pytest
@@ -117,3 +121,58 @@ def test_adjoint_roughness_vs_central_differences(base):
                                                                             g["dHmin_drough"][m])
         fd0 = (rp["H0"] - rm["H0"]) / (2 * step)
         assert abs(fd0 - g["dH0_drough"][m]) <= 1e-5 * max(1.0, abs(fd0))
+
+
+KAPPA = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def base_kappa():
+    r = E.solve_line(20.0, 10.0, N, kappa=KAPPA)
+    assert r["status"] == 0
+    return r
+
+
+def test_dense_jacobian_kappa_scheme(base_kappa):
+    r = base_kappa
+    x, h, kvec = r["x"], r["h"], r["kvec"]
+    _, lam, ph = E.moes_line(20.0, 10.0)
+    P, H0 = r["P"], r["H0"]
+    RP, RH, _, _ = A.partials(P, E.film(P, H0, x, kvec), ph, lam, h, KAPPA)
+    K = deform.line_matrix(N, h)
+    J = RP[:, 1:-1] + RH @ K[:, 1:-1]
+    inact = np.where(P[1:-1] > 0)[0]
+    worst = 0.0
+    for j in inact[::7]:
+        e = 1e-6 * max(1.0, abs(P[j + 1]))
+        Pp, Pm = P.copy(), P.copy()
+        Pp[j + 1] += e
+        Pm[j + 1] -= e
+        Rp, _ = E.residual(Pp, E.film(Pp, H0, x, kvec), ph, lam, h, KAPPA)
+        Rm, _ = E.residual(Pm, E.film(Pm, H0, x, kvec), ph, lam, h, KAPPA)
+        fd = (Rp - Rm) / (2 * e)
+        sc = np.abs(fd[inact]).max()
+        worst = max(worst, np.abs(fd - J[:, j])[inact].max() / sc)
+    assert worst <= 1e-5, worst
+
+
+def test_adjoint_kappa_scheme_vs_central_differences(base_kappa):
+    M, L = 20.0, 10.0
+    g = A.adjoint_gradients(base_kappa["P"], base_kappa["H0"], M, L, N, kappa=KAPPA)
+    step = 1e-6
+
+    def solve(M_, L_):
+        r = E.solve_line(M_, L_, N, kappa=KAPPA)
+        assert r["status"] == 0
+        return r
+
+    rp, rm = solve(M * (1 + step), L), solve(M * (1 - step), L)
+    assert (rp["P"][1:-1] > 0).tolist() == (rm["P"][1:-1] > 0).tolist()
+    assert rp["argmin"] == rm["argmin"] == g["argmin"]
+    fdH0 = (rp["H0"] - rm["H0"]) / (2 * step * M)
+    fdHm = (rp["Hmin"] - rm["Hmin"]) / (2 * step * M)
+    assert abs(fdH0 - g["dH0_dM"]) <= 1e-5 * abs(fdH0)
+    assert abs(fdHm - g["dHmin_dM"]) <= 1e-5 * abs(fdHm)
+    rp, rm = solve(M, L * (1 + step)), solve(M, L * (1 - step))
+    fdH0 = (rp["H0"] - rm["H0"]) / (2 * step * L)
+    assert abs(fdH0 - g["dH0_dL"]) <= 1e-5 * abs(fdH0)
