@@ -270,8 +270,8 @@ typedef struct {
     int32_t convection;  /* convective face value (rho H)_{i+1/2} = (rho H)_i
                             + psi/2: 0 van Leer limited slope (TVD, default);
                             1 kappa-scheme psi = (1+kappa)/2 D+ + (1-kappa)/2
-                            D- (Sec. 2, eqs. 57-59; line and point contact;
-                            the adjoint returns PAQIF_EINVAL)                */
+                            D- (Sec. 2, eqs. 57-59; line and point contact
+                            and the line-contact adjoint)                    */
     double kappa;        /* -1 <= kappa <= 1 for convection 1                */
 } ehl_opts;
 

@@ -74,6 +74,8 @@ struct AdjPartialArgs {
     const ehl_params* params;
     const double *P, *Hel, *H0, *rough;
     double *RPb, *RHb, *FM, *FL;
+    int conv = 0;  // 0 van Leer slope, 1 kappa-scheme slope (Sec. 2)
+    double kappa = 0.0;
 };
 
 __global__ void __launch_bounds__(PT) line_adjoint_partials_kernel(AdjPartialArgs a)
@@ -125,7 +127,9 @@ __global__ void __launch_bounds__(PT) line_adjoint_partials_kernel(AdjPartialArg
     {
         // -(f_i - f_{i-1}) / h with f_t = (rho H)_t + psi_t / 2 (t >= 1), f_0 = (rho H)_0
         double psi, pa, pb;
-        van_leer(at(sRH, i) - at(sRH, i - 1), at(sRH, i + 1) - at(sRH, i), psi, pa, pb);
+        // exact slope derivatives (limiter_jacobian mode 0)
+        convective_slope(a.conv, a.kappa, 0, at(sRH, i) - at(sRH, i - 1),
+                         at(sRH, i + 1) - at(sRH, i), psi, pa, pb);
         const double sg = -1.0 / h;
         cF[1] += sg * 0.5 * (-pb);
         cF[2] += sg * (1.0 + 0.5 * (pb - pa));
@@ -134,7 +138,8 @@ __global__ void __launch_bounds__(PT) line_adjoint_partials_kernel(AdjPartialArg
         if (i - 1 == 0) {
             cF[1] += sm;
         } else {
-            van_leer(at(sRH, i - 1) - at(sRH, i - 2), at(sRH, i) - at(sRH, i - 1), psi, pa, pb);
+            convective_slope(a.conv, a.kappa, 0, at(sRH, i - 1) - at(sRH, i - 2),
+                             at(sRH, i) - at(sRH, i - 1), psi, pa, pb);
             cF[0] += sm * 0.5 * (-pb);
             cF[1] += sm * (1.0 + 0.5 * (pb - pa));
             cF[2] += sm * 0.5 * pa;
@@ -605,7 +610,9 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid* grid, const ehl_param
     if (!handle || !adj_valid_grid(grid) || B < 0 || !opts) return PAQIF_EINVAL;
     if (!(opts->kernel_terms == 1 || opts->kernel_terms == 2)) return PAQIF_EINVAL;
     if (opts->limiter_jacobian < 0 || opts->limiter_jacobian > 2) return PAQIF_EINVAL;
-    if (opts->convection != 0) return PAQIF_EINVAL;  // the adjoint differentiates van Leer
+    if (!(opts->convection == 0 ||
+          (opts->convection == 1 && opts->kappa >= -1.0 && opts->kappa <= 1.0)))
+        return PAQIF_EINVAL;
     if (!(rtol > 0.0 && rtol < 1.0) || max_iter < 1) return PAQIF_EINVAL;
     if (B == 0) return PAQIF_OK;
     if (!params || !P || !H0 || !dM || !dL || !drough || !status || !iters || !workspace)
@@ -626,6 +633,8 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid* grid, const ehl_param
 
     AdjPartialArgs pa{N, B, h, grid->x0, params, P, hel, H0, rough,
                       D(L.RPb), D(L.RHb), D(L.FM), D(L.FL)};
+    pa.conv = opts->convection;
+    pa.kappa = opts->kappa;
     hipLaunchKernelGGL(line_adjoint_partials_kernel, dim3((n + PT - 1) / PT, B), dim3(PT), 0, s,
                        pa);
 
@@ -635,8 +644,8 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid* grid, const ehl_param
     aa.B = B;
     aa.kterms = opts->kernel_terms;
     aa.limjac = opts->limiter_jacobian;
-    aa.conv = 0;
-    aa.kappa = 0.0;
+    aa.conv = opts->convection;  // the preconditioner uses the same slope
+    aa.kappa = opts->kappa;
     aa.h = h;
     aa.x0 = grid->x0;
     aa.switch_ratio = opts->switch_ratio;

@@ -8,6 +8,7 @@
     GMRES to a relative residual of 1e-12) agree to about cond * 1e-16;
   * GPU gradients against central differences (step 1e-6 relative) of
     re-converged GPU solutions, within 1e-5 relative;
+  * the same at the oracle's converged kappa-scheme state (kappa = 1/3);
   * the autograd wrapper and a batch of instances with different M on a
     2049-node grid.
 """
@@ -65,6 +66,31 @@ def test_adjoint_matches_oracle_at_oracle_state(gpu, oracle_states):
             for p in ("M", "L"):
                 v, ref = float(a[f"d{p}"][0]), g[f"d{name}_d{p}"]
                 assert abs(v - ref) <= 1e-7 * abs(ref), (M, L, name, p, v, ref)
+
+
+def test_adjoint_kappa_scheme_matches_oracle(gpu):
+    """kappa-scheme convection (kappa = 1/3): GPU gradients at the oracle's
+    converged kappa-scheme state against the oracle's dense adjoint."""
+    E = gpu.ehl
+    k, M, L = 1.0 / 3.0, 20.0, 10.0
+    r = OE.solve_line(M, L, N, kappa=k)
+    assert r["status"] == 0
+    g = OA.adjoint_gradients(r["P"], r["H0"], M, L, N, kappa=k)
+    opts = E.default_opts(convection=1, kappa=k)
+    P, H0 = _t(r["P"][None]), _t([r["H0"]])
+    a0 = E.adjoint([M], [L], N, P, H0, gH0=_t([1.0]), opts=opts)
+    gH = np.zeros((1, N))
+    gH[0, g["argmin"]] = 1.0
+    a1 = E.adjoint([M], [L], N, P, H0, gH=_t(gH), opts=opts)
+    torch.cuda.synchronize()
+    assert int(a0["status"][0]) == 0 and int(a1["status"][0]) == 0
+    for a, name in ((a0, "H0"), (a1, "Hmin")):
+        dr = a["drough"][0].cpu().numpy()
+        ref = g[f"d{name}_drough"]
+        assert np.abs(dr - ref).max() <= 1e-7 * np.abs(ref).max(), name
+        for p in ("M", "L"):
+            v, ref = float(a[f"d{p}"][0]), g[f"d{name}_d{p}"]
+            assert abs(v - ref) <= 1e-7 * abs(ref), (name, p, v, ref)
 
 
 def _solve(E, M, L, rough=None):
