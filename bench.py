@@ -542,6 +542,8 @@ def main():
     ap.add_argument("--partitioned-only", action="store_true",
                     help="run only the partitioned long-system leg (one JSON object)")
     ap.add_argument("--no-partitioned", action="store_true")
+    ap.add_argument("--no-active30", action="store_true",
+                    help="skip the config-2 run at ~30%% active (keeps counter runs to one batch)")
     ap.add_argument("--part-case", default="",
                     help="n:q:r -- the partitioned leg on this one case only")
     ap.add_argument("--convdiff-only", action="store_true",
@@ -664,7 +666,7 @@ def main():
                                          max(1.0, float(u64.abs().max()))))
         mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
 
-    active30 = active30_leg(P, torch, synth, args)
+    active30 = active30_leg(P, torch, synth, args) if not args.no_active30 else None
     ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
     deform = deformation_leg(P, torch, args) if not args.no_ehl else None
     part = partitioned_leg(P, torch, synth, args) if not args.no_partitioned else None
