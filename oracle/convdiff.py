@@ -22,6 +22,16 @@ whole operator along the line (kappa convection and diffusion; lower
 dominant, so the interlocking factorisation's 2 x 2 pivots stay regular)
 plus the diagonal of the across-line part, then u += omega sigma; x-lines
 and y-lines alternate.  At the fixed point L_h u = f.  Pins: tests/test_oracle_convdiff.py.
+
+Distributive line relaxation (Ls3 of Sec. 2, the "kappa-distributive"
+splitting): the change of a node is distributed, u_ij += s_ij - (s_{i+-1,j}
++ s_{i,j+-1})/4 (eq. 51), so a line solves for ghost changes s* whose
+distributed pattern cancels the line's defect: row (i, l) of the line matrix
+is L_h applied to the pattern of a unit ghost change at node (k, l), read at
+(i, l).  The paper prints the resulting five-band coefficients in a garbled
+form; here the matrix is that definition evaluated (its half-bandwidth is 3).
+Lines of one direction are taken in two colours (odd, then even line
+indices), since neighbouring lines' patterns overlap.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -176,3 +186,72 @@ def solve(n, kappa, eps=1e-6, omega=1.0, tol=1e-10, max_iter=500, a=1.0, b=1.0):
                 l1=np.abs(e).sum() / np.abs(ue).sum(),
                 l2=np.sqrt((e ** 2).sum() / (ue ** 2).sum()))
     return dict(u=u, iters=it, defect=res, fmax=fmax, **errs)
+
+
+def pattern(n, node):
+    """Distributed change of a unit ghost change at an interior node."""
+    d = np.zeros((n, n))
+    i, j = node
+    d[i, j] = 1.0
+    for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        if 1 <= i + di <= n - 2 and 1 <= j + dj <= n - 2:
+            d[i + di, j + dj] -= 0.25
+    return d
+
+
+def ls3_line_matrix(n, axis, l, kappa, eps, a=1.0, b=1.0):
+    """(n-2) x (n-2) matrix of line l: column k = L_h(pattern at the line's
+    node k+1) on the line's nodes."""
+    m = n - 2
+    A = np.zeros((m, m))
+    for k in range(m):
+        node = (k + 1, l) if axis == 0 else (l, k + 1)
+        col = operator(pattern(n, node), kappa, eps, a, b)
+        A[:, k] = col[1:-1, l] if axis == 0 else col[l, 1:-1]
+    return A
+
+
+def ls3_half_step(u, f, axis, color, kappa, eps, omega, a=1.0, b=1.0):
+    """Lines of one direction and colour (line index parity): ghost changes
+    from the line matrices, then u += omega * (distributed changes)."""
+    n = u.shape[0]
+    r = defect(u, f, kappa, eps, a, b)
+    g = np.zeros_like(u)
+    for l in range(1, n - 1):
+        if l % 2 != color:
+            continue
+        rl = r[1:-1, l] if axis == 0 else r[l, 1:-1]
+        s = np.linalg.solve(ls3_line_matrix(n, axis, l, kappa, eps, a, b), rl)
+        if axis == 0:
+            g[1:-1, l] = s
+        else:
+            g[l, 1:-1] = s
+    du = g.copy()
+    du[1:, :] -= 0.25 * g[:-1, :]
+    du[:-1, :] -= 0.25 * g[1:, :]
+    du[:, 1:] -= 0.25 * g[:, :-1]
+    du[:, :-1] -= 0.25 * g[:, 1:]
+    du[0, :] = du[-1, :] = du[:, 0] = du[:, -1] = 0.0
+    return u + omega * du
+
+
+def ls3_iteration(u, f, kappa, eps, omega, a=1.0, b=1.0):
+    """One iteration: x-lines (odd, even), then y-lines (odd, even)."""
+    for axis in (0, 1):
+        for color in (1, 0):
+            u = ls3_half_step(u, f, axis, color, kappa, eps, omega, a, b)
+    return u
+
+
+def solve_ls3(n, kappa, eps=1e-6, omega=1.0, tol=1e-10, max_iter=500, a=1.0, b=1.0):
+    """Ls3 iterations until max |f - L_h u| <= tol max|f|."""
+    f = rhs(n, eps, a, b)
+    u = start(n)
+    fmax = np.abs(f[1:-1, 1:-1]).max()
+    it, res = 0, np.inf
+    for it in range(1, max_iter + 1):
+        u = ls3_iteration(u, f, kappa, eps, omega, a, b)
+        res = np.abs(defect(u, f, kappa, eps, a, b)).max()
+        if res <= tol * fmax:
+            break
+    return dict(u=u, iters=it, defect=res, fmax=fmax)

@@ -8,7 +8,12 @@
     direct sparse solve of the operator assembled column by column from unit
     vectors (brute force, no line structure);
   * grid convergence against u = x^4 + y^4: order >= 1.9 in the max norm
-    from 17 to 33 to 65 nodes per side, for kappa = 0, 1/3, -1.
+    from 17 to 33 to 65 nodes per side, for kappa = 0, 1/3, -1;
+  * distributive line relaxation (Ls3): the line matrix has half-bandwidth 3
+    (the pattern reaches one node either side of a stencil of offsets -2..1)
+    and its entries equal the kappa stencil composed with the pattern by
+    hand on a row far from the boundary; the iteration converges (slowly,
+    as the paper warns) to the direct solution on 9 x 9 nodes.
 The absolute errors of the paper's printed table are not reproduced (the
 paper does not give a(x, y), b(x, y) nor its boundary closure): parity
 unpinned there.
@@ -64,3 +69,41 @@ def test_second_order_convergence(kappa):
     errs = [C.solve(n, kappa, tol=1e-12, max_iter=400)["linf"] for n in (17, 33, 65)]
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert (orders >= 1.9).all(), (errs, orders)
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_ls3_line_matrix_band_and_stencil(kappa):
+    n, eps, a, b = 15, 0.2, 1.0, 1.0
+    _, h = C.grid(n)
+    l = 6
+    A = C.ls3_line_matrix(n, 0, l, kappa, eps, a, b)
+    m = n - 2
+    off = np.subtract.outer(np.arange(m), np.arange(m))      # row - column
+    assert np.all(A[(off > 3) | (off < -2)] == 0.0)
+    # interior row: along-line stencil c(-2..1) of the kappa scheme plus
+    # diffusion, composed with the pattern (1 at the node, -1/4 either side);
+    # across-line neighbours of the node get -1/4 through the across stencil
+    k = kappa
+    al = {-2: a / h * (1 - k) / 4, -1: a / h * (3 * k - 5) / 4 - eps / h ** 2,
+          0: a / h * (3 - 3 * k) / 4 + 2 * eps / h ** 2, 1: a / h * (1 + k) / 4 - eps / h ** 2}
+    ac = {-1: b / h * (3 * k - 5) / 4 - eps / h ** 2, 1: b / h * (1 + k) / 4 - eps / h ** 2}
+    ac0 = b / h * (3 - 3 * k) / 4 + 2 * eps / h ** 2
+    coef = dict(al)
+    coef[0] = al[0] + ac0                   # the node's whole diagonal
+    i = 7                                   # row of node i + 1 = 8
+    for dc in range(-3, 3):
+        ref = 0.0
+        for s_, w in ((0, 1.0), (-1, -0.25), (1, -0.25)):
+            ref += w * coef.get(dc + s_, 0.0)
+        if dc == 0:
+            ref -= 0.25 * (ac[-1] + ac[1])
+        assert abs(A[i, i + dc] - ref) <= 1e-12 * max(1.0, abs(ref)), (dc, A[i, i + dc], ref)
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_ls3_converges_to_the_direct_solution(kappa):
+    n = 9
+    r = C.solve_ls3(n, kappa, tol=1e-11, max_iter=600)
+    assert r["defect"] <= 1e-11 * r["fmax"]
+    d = C.solve(n, kappa, tol=1e-13, max_iter=500)
+    assert np.abs(r["u"] - d["u"]).max() <= 1e-9 * np.abs(d["u"]).max()
