@@ -440,6 +440,25 @@ int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a
                   double omega, double tol, int max_iter, const double *f, double *u,
                   int32_t *iters, double *defect, void *workspace, void *stream);
 
+/*
+ * cd_distributive_relax -- the distributive line relaxation (Ls3 of Sec. 2,
+ * eq. 51) of the same problem: a node's change is distributed,
+ * u_ij += s_ij - (s_{i+-1,j} + s_{i,j+-1}) / 4, and every line solves for
+ * ghost changes s whose distributed pattern cancels its defect (row (i, l),
+ * column k: L_h of the pattern of a unit ghost change at the line's node k,
+ * read at (i, l); half-bandwidth 3, one batched PAQIF launch in plain linear
+ * mode per colour).  One iteration: x-lines odd then even, y-lines odd then
+ * even (line index parity; neighbouring lines' patterns overlap), then the
+ * defect test.  The paper notes this splitting is not robust: it converges
+ * far more slowly than cd_line_relax.  Arguments as for cd_line_relax;
+ * workspace: cd_ls3_workspace_bytes(n) bytes (0 = invalid n).
+ */
+size_t cd_ls3_workspace_bytes(int n);
+int cd_distributive_relax(paqif_handle handle, int n, double kappa, double eps, double a,
+                          double b, double omega, double tol, int max_iter, const double *f,
+                          double *u, int32_t *iters, double *defect, void *workspace,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,9 @@ def lib():
         "paqif_solve_partitioned": ([vp, i64, ctypes.c_int, i32, vp, vp, vp, ctypes.c_int,
                                      ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "cd_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
+        "cd_ls3_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
+        "cd_distributive_relax": ([vp, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp, vp,
+                                   ctypes.POINTER(i32), ctypes.POINTER(d), vp, vp], ctypes.c_int),
         "cd_example": ([ctypes.c_int, d, d, d, vp, vp, vp], ctypes.c_int),
         "cd_line_relax": ([vp, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp, vp,
                            ctypes.POINTER(i32), ctypes.POINTER(d), vp, vp], ctypes.c_int),

@@ -1,7 +1,8 @@
 """Linear convection-diffusion workload: binding of ``cd_example`` and
 ``cd_line_relax`` (argument marshalling only; the work runs in the HIP
 library).  (a u)_x + (b u)_y - eps Lap u = f on [-1, 1]^2, kappa-scheme
-convection, line relaxation with batched PAQIF line solves."""
+convection, line relaxation with batched PAQIF line solves (defect correction,
+and the distributive Ls3 splitting)."""
 import ctypes
 
 import torch
@@ -39,4 +40,25 @@ def line_relax(f, u, kappa, eps=1e-6, a=1.0, b=1.0, omega=1.0, tol=1e-10, max_it
                                   float(omega), float(tol), int(max_iter), _ptr(f), _ptr(u),
                                   ctypes.byref(it), ctypes.byref(res), _ptr(workspace),
                                   _stream()), "cd_line_relax")
+    return int(it.value), float(res.value)
+
+
+def distributive_relax(f, u, kappa, eps=1e-6, a=1.0, b=1.0, omega=1.0, tol=1e-10, max_iter=500,
+                       workspace=None):
+    """Distributive line relaxation (Ls3) on u in place; returns
+    (iterations, final max defect)."""
+    _need(f, torch.float64, "f")
+    _need(u, torch.float64, "u")
+    n = int(u.shape[0])
+    if tuple(u.shape) != (n, n) or tuple(f.shape) != (n, n):
+        raise ValueError("f and u must be n x n")
+    if workspace is None:
+        workspace = torch.empty(max(1, B.lib().cd_ls3_workspace_bytes(n)), dtype=torch.uint8,
+                                device=u.device)
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    B.check(B.lib().cd_distributive_relax(handle(), n, float(kappa), float(eps), float(a),
+                                          float(b), float(omega), float(tol), int(max_iter),
+                                          _ptr(f), _ptr(u), ctypes.byref(it), ctypes.byref(res),
+                                          _ptr(workspace), _stream()), "cd_distributive_relax")
     return int(it.value), float(res.value)

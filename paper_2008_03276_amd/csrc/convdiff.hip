@@ -102,6 +102,75 @@ __global__ void cd_update_kernel(int n, int axis, double omega, const double* si
     u[(int64_t)p * n + q] += omega * sigma[(int64_t)(l - 1) * m + (i - 1)];
 }
 
+// ---------------------------------------------------------------------------
+// Distributive line relaxation (Ls3 of Sec. 2, eq. 51): the change of a node
+// is distributed, u += s - (sum of the four neighbours' s) / 4, and a line
+// solves for ghost changes whose distributed pattern cancels its defect.
+// Row (i, l) of the line matrix, column k: L_h applied to the pattern of a
+// unit ghost change at the line's node k, read at (i, l) (half-bandwidth 3,
+// stored as a band of half-bandwidth 4).  Lines of one direction run in two
+// colours (line index parity): neighbouring lines' patterns overlap.
+// ---------------------------------------------------------------------------
+
+// L_h at interior node (i, j) of the field U(ii, jj)
+template <class F>
+PQ_DEV double op_at(const CdArgs& A, int i, int j, F U)
+{
+    const double c = U(i, j);
+    const double cx = conv_line(i >= 2 ? U(i - 2, j) : 0.0, U(i - 1, j), c, U(i + 1, j), i, A.kappa);
+    const double cy = conv_line(j >= 2 ? U(i, j - 2) : 0.0, U(i, j - 1), c, U(i, j + 1), j, A.kappa);
+    const double lap = (U(i + 1, j) + U(i - 1, j) + U(i, j + 1) + U(i, j - 1) - 4.0 * c) /
+                       (A.h * A.h);
+    return A.a * cx / A.h + A.b * cy / A.h - A.eps * lap;
+}
+
+// thread per row of the colour's lines (line slot k: line l = first + 2k)
+__global__ void cd_ls3_assemble_kernel(CdArgs A, int axis, int first, int cnt, double* band,
+                                       double* rhs)
+{
+    const int n = A.n, m = n - 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)cnt * m) return;
+    const int k = (int)(t / m), r = (int)(t % m);
+    const int l = first + 2 * k, i = r + 1;
+    const int p = axis == 0 ? i : l, q = axis == 0 ? l : i;
+    rhs[t] = defect_at(A, p, q);
+    double* b = band + t * 9;
+    for (int s = 0; s < 9; s++) {
+        const int c = r + s - 4;  // column: the line's node c + 1
+        double v = 0.0;
+        if (c >= 0 && c < m && c - r >= -3 && c - r <= 2) {
+            const int ci = axis == 0 ? c + 1 : l, cj = axis == 0 ? l : c + 1;
+            auto pat = [&](int x, int y) {
+                if (x == ci && y == cj) return 1.0;
+                const int dist = abs(x - ci) + abs(y - cj);
+                const bool inner = x >= 1 && x <= n - 2 && y >= 1 && y <= n - 2;
+                return (dist == 1 && inner) ? -0.25 : 0.0;
+            };
+            v = op_at(A, p, q, pat);
+        }
+        b[s] = v;
+    }
+}
+
+// u += omega * (distributed ghost changes of the colour's lines)
+__global__ void cd_ls3_update_kernel(int n, int axis, int first, double omega,
+                                     const double* sigma, double* u)
+{
+    const int m = n - 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * m) return;
+    const int p = (int)(t / m) + 1, q = (int)(t % m) + 1;
+    auto g = [&](int x, int y) {
+        if (x < 1 || x > n - 2 || y < 1 || y > n - 2) return 0.0;
+        const int l = axis == 0 ? y : x, i = axis == 0 ? x : y;
+        if (l < first || ((l - first) & 1)) return 0.0;
+        return sigma[(int64_t)((l - first) / 2) * m + (i - 1)];
+    };
+    const double du = g(p, q) - 0.25 * (g(p + 1, q) + g(p - 1, q) + g(p, q + 1) + g(p, q - 1));
+    u[(int64_t)p * n + q] += omega * du;
+}
+
 // max over the interior of |f - L_h u| (mode 0) or |f| (mode 1), as the bit
 // pattern of a non-negative double (ordered like the value) into *out
 __global__ void cd_norm_kernel(CdArgs A, int mode, unsigned long long* out)
@@ -170,6 +239,30 @@ CdLayout cd_layout(int n)
     L.lit = take(m * sizeof(int32_t));
     L.norm = take(2 * sizeof(unsigned long long));
     L.rec = take(((rows + m) / 2 + 1) * (size_t)record_stride(2, true) * sizeof(double));
+    L.act = take(rows);
+    L.total = p;
+    return L;
+}
+
+// Ls3 workspace: the same arrays, a band of half-bandwidth 4 and its records
+CdLayout cd3_layout(int n)
+{
+    const size_t m = (size_t)n - 2, rows = m * m;
+    CdLayout L;
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p += a256(bytes);
+        return at;
+    };
+    L.offs = take((m + 1) * sizeof(int64_t));
+    L.band = take(rows * 9 * sizeof(double));
+    L.rhs = take(rows * sizeof(double));
+    L.sigma = take(rows * sizeof(double));
+    L.lst = take(m * sizeof(int32_t));
+    L.lit = take(m * sizeof(int32_t));
+    L.norm = take(2 * sizeof(unsigned long long));
+    L.rec = take(((rows + m) / 2 + 1) * (size_t)record_stride(4, true) * sizeof(double));
     L.act = take(rows);
     L.total = p;
     return L;
@@ -270,6 +363,105 @@ int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a
             hipLaunchKernelGGL(pq::cd_update_kernel, dim3(nb), dim3(256), 0, s, n, axis, omega,
                                sigma, u);
             if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+        }
+        hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm);
+        hipLaunchKernelGGL(pq::cd_norm_kernel, dim3(nb), dim3(256), 0, s, A, 0, nrm);
+        if (!pq::hip_ok(hipGetLastError()) ||
+            hipMemcpyAsync(host, nrm, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PAQIF_EHIP;
+        double v;
+        memcpy(&v, &host[0], sizeof v);
+        res = v;
+        memcpy(&fmax, &host[1], sizeof fmax);
+        if (res <= tol * fmax || !std::isfinite(res)) break;
+    }
+    *iters = std::min(it, max_iter);
+    *defect = res;
+    return PAQIF_OK;
+}
+
+size_t cd_ls3_workspace_bytes(int n)
+{
+    if (n < 5 || n > 16385) return 0;
+    return pq::cd3_layout(n).total;
+}
+
+int cd_distributive_relax(paqif_handle handle, int n, double kappa, double eps, double a,
+                          double b, double omega, double tol, int max_iter, const double* f,
+                          double* u, int32_t* iters, double* defect, void* workspace,
+                          void* stream)
+{
+    if (!handle || !pq::cd_valid(n, kappa, eps, a, b) || !(omega > 0.0 && omega < 2.0) ||
+        !(tol >= 0.0) || max_iter < 1 || !f || !u || !iters || !defect || !workspace)
+        return PAQIF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pq::CdLayout L = pq::cd3_layout(n);
+    char* ws = static_cast<char*>(workspace);
+    const int m = n - 2;
+    const int64_t rows = (int64_t)m * m;
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offs);
+    double* band = reinterpret_cast<double*>(ws + L.band);
+    double* rhs = reinterpret_cast<double*>(ws + L.rhs);
+    double* sigma = reinterpret_cast<double*>(ws + L.sigma);
+    unsigned long long* nrm = reinterpret_cast<unsigned long long*>(ws + L.norm);
+
+    pq::CdArgs A;
+    A.n = n;
+    A.kappa = kappa;
+    A.eps = eps;
+    A.a = a;
+    A.b = b;
+    A.h = 2.0 / (n - 1);
+    A.f = f;
+    A.u = u;
+
+    pq::LcpArgs la;
+    la.offsets = offs;
+    la.order = nullptr;
+    la.band = band;
+    la.b = rhs;
+    la.bounded = nullptr;
+    la.mode = LCP_LINEAR;
+    la.max_iter = 1;
+    la.refine_tol = 0.0;
+    la.u = sigma;
+    la.w = nullptr;
+    la.active_out = nullptr;
+    la.status = reinterpret_cast<int32_t*>(ws + L.lst);
+    la.iters = reinterpret_cast<int32_t*>(ws + L.lit);
+    la.rec = ws + L.rec;
+    la.act = reinterpret_cast<uint8_t*>(ws + L.act);
+    la.r = nullptr;
+    la.skip = nullptr;
+    la.warm = 0;
+
+    const unsigned nb = (unsigned)((rows + 255) / 256);
+    hipLaunchKernelGGL(pq::cd_offsets_kernel, dim3((m + 256) / 256), dim3(256), 0, s, m, offs);
+    hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm + 1);
+    hipLaunchKernelGGL(pq::cd_norm_kernel, dim3(nb), dim3(256), 0, s, A, 1, nrm + 1);
+    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    unsigned long long host[2];
+    const int layout = handle->layout[pq::q_index(4)][0];
+    int it = 0;
+    double res = INFINITY, fmax = 0.0;
+    for (it = 1; it <= max_iter; it++) {
+        for (int axis = 0; axis < 2; axis++) {
+            for (int color = 1; color >= 0; color--) {
+                const int first = color == 1 ? 1 : 2;  // lines first, first + 2, ...
+                if (first > m) continue;
+                const int cnt = (m - first) / 2 + 1;
+                la.count = cnt;
+                const unsigned nbl = (unsigned)(((int64_t)cnt * m + 255) / 256);
+                hipLaunchKernelGGL(pq::cd_ls3_assemble_kernel, dim3(nbl), dim3(256), 0, s, A,
+                                   axis, first, cnt, band, rhs);
+                if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+                int e = pq::dispatch_lcp(4, la, PREC_FP64, layout, s);
+                if (e) return e;
+                hipLaunchKernelGGL(pq::cd_ls3_update_kernel, dim3(nb), dim3(256), 0, s, n, axis,
+                                   first, omega, sigma, u);
+                if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+            }
         }
         hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm);
         hipLaunchKernelGGL(pq::cd_norm_kernel, dim3(nb), dim3(256), 0, s, A, 0, nrm);

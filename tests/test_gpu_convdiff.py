@@ -9,6 +9,10 @@
     line order) and 65 (several superblocks, ragged last one);
   * at convergence (max defect <= 1e-12 max|f|): the same iteration count
     within one and the same discrete solution within 1e-10;
+  * the distributive line relaxation (Ls3): the iterate after a fixed number
+    of iterations within 1e-10 of the oracle's (n = 13, 34), and on 9 x 9
+    nodes the converged solution within 1e-10 with the iteration count
+    within one;
   * argument checks.
 """
 import numpy as np
@@ -69,3 +73,30 @@ def test_invalid_arguments(gpu):
             gpu.convdiff.line_relax(f, u, **kw)
     with pytest.raises(RuntimeError):
         gpu.convdiff.example(4)
+
+
+@pytest.mark.parametrize("n", [13, 34])
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_ls3_fixed_iterations_match_oracle(gpu, n, kappa):
+    eps, omega, k = 1e-6, 0.9, 4
+    f, u = gpu.convdiff.example(n, eps)
+    it, _ = gpu.convdiff.distributive_relax(f, u, kappa, eps, omega=omega, tol=0.0, max_iter=k)
+    torch.cuda.synchronize()
+    assert it == k
+    ref = C.start(n)
+    fr = C.rhs(n, eps)
+    for _ in range(k):
+        ref = C.ls3_iteration(ref, fr, kappa, eps, omega)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_ls3_converged_matches_oracle(gpu, kappa):
+    n = 9
+    o = C.solve_ls3(n, kappa, tol=1e-11, max_iter=600)
+    f, u = gpu.convdiff.example(n, 1e-6)
+    it, res = gpu.convdiff.distributive_relax(f, u, kappa, tol=1e-11, max_iter=600)
+    torch.cuda.synchronize()
+    assert res <= 1e-11 * o["fmax"]
+    assert abs(it - o["iters"]) <= 1
+    assert np.abs(u.cpu().numpy() - o["u"]).max() <= 1e-10 * np.abs(o["u"]).max()
