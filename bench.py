@@ -315,6 +315,26 @@ def convdiff_leg(P, torch, args):
         out[f"n{n}"] = res_n
         log(f"convdiff n={n}: " + ", ".join(f"{k} {v['iterations']} it {v['ms']} ms"
                                              for k, v in res_n.items()))
+    # the distributive line relaxation (Ls3) on 65 x 65 nodes: the paper's
+    # warning that it is not robust shows as slow convergence
+    n = 65
+    ws3 = torch.empty(P.lib().cd_ls3_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    ls3 = {}
+    for kappa in (0.0, 1.0 / 3.0, -1.0):
+        f, u = P.convdiff.example(n)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        it, res = P.convdiff.distributive_relax(f, u, kappa, tol=1e-10, max_iter=2000,
+                                                workspace=ws3)
+        torch.cuda.synchronize()
+        dt = _t.perf_counter() - t0
+        fmax = float(f[1:-1, 1:-1].abs().max())
+        ls3[f"kappa_{kappa:.3f}"] = dict(iterations=it, ms=round(dt * 1e3, 3),
+                                         ms_per_iteration=round(dt * 1e3 / it, 4),
+                                         rel_defect=res / fmax, converged=bool(res <= 1e-10 * fmax))
+    out["ls3_n65"] = ls3
+    log("convdiff Ls3 n=65: " + ", ".join(f"{k} {v['iterations']} it rel. defect {v['rel_defect']:.1e}"
+                                          for k, v in ls3.items()))
     if not args.no_cpu:
         from oracle import convdiff as OC
         cpu = {}
