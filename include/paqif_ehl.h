@@ -270,7 +270,7 @@ typedef struct {
     int32_t convection;  /* convective face value (rho H)_{i+1/2} = (rho H)_i
                             + psi/2: 0 van Leer limited slope (TVD, default);
                             1 kappa-scheme psi = (1+kappa)/2 D+ + (1-kappa)/2
-                            D- (Sec. 2, eqs. 57-59; line and point contact
+                            D- (Sec. 3.3, eqs. 56-59; line and point contact
                             and the line-contact adjoint)                    */
     double kappa;        /* -1 <= kappa <= 1 for convection 1                */
 } ehl_opts;
@@ -405,7 +405,7 @@ int ehl_adjoint_solve(paqif_handle handle, const ehl_grid *grid, const ehl_param
 
 /* ------------------------------------------------------------------------
  * Linear convection-diffusion workload (Sec. 4, linear case study of
- * Example 1, kappa-schemes of Sec. 2): the banded solver on non-symmetric,
+ * Example 1, kappa-schemes of Sec. 3.1): the banded solver on non-symmetric,
  * non-complementarity line systems.
  * ------------------------------------------------------------------------ */
 
@@ -441,8 +441,8 @@ int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a
                   int32_t *iters, double *defect, void *workspace, void *stream);
 
 /*
- * cd_distributive_relax -- the distributive line relaxation (Ls3 of Sec. 2,
- * eq. 51) of the same problem: a node's change is distributed,
+ * cd_distributive_relax -- the distributive line relaxation (Ls3 of Sec. 3.1,
+ * eqs. 51-54) of the same problem: a node's change is distributed,
  * u_ij += s_ij - (s_{i+-1,j} + s_{i,j+-1}) / 4, and every line solves for
  * ghost changes s whose distributed pattern cancels its defect (row (i, l),
  * column k: L_h of the pattern of a unit ghost change at the line's node k,

@@ -40,13 +40,15 @@ def lib():
         L.or_aqif_factor_dense.argtypes = [i64, i32, d, u8, d, d]
         L.or_lcp_solve.argtypes = [i64, i32, d, d, u8, i32, i32, d, d, u8,
                                    ctypes.POINTER(ctypes.c_int)]
+        L.or_lcp_solve_start.argtypes = [i64, i32, d, d, u8, u8, i32, d, d, u8,
+                                         ctypes.POINTER(ctypes.c_int)]
         L.or_lcp_pgs.argtypes = [i64, i32, d, d, u8, ctypes.c_double, i32, ctypes.c_double, d,
                                  ctypes.POINTER(ctypes.c_int)]
         L.or_lcp_batch.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int64), d, d, u8, i32, i32,
                                    d, d, u8, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), i32]
-        for f in (L.or_aqif_solve, L.or_aqif_factor_dense, L.or_lcp_solve, L.or_lcp_pgs,
-                  L.or_lcp_batch):
+        for f in (L.or_aqif_solve, L.or_aqif_factor_dense, L.or_lcp_solve, L.or_lcp_solve_start,
+                  L.or_lcp_pgs, L.or_lcp_batch):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -113,6 +115,25 @@ def lcp_solve(band, f, bounded=None, mode=EXACT, max_iter=64):
     it = ctypes.c_int(0)
     st = lib().or_lcp_solve(n, q, _dp(band), _dp(f), _u8(bounded), mode, max_iter, _dp(u),
                             _dp(w), _u8(act), ctypes.byref(it))
+    return dict(u=u, w=w, active=act, iters=it.value, status=st)
+
+
+def lcp_solve_start(band, f, bounded=None, start=None, max_iter=64):
+    """Exact banded LCP by the active-set iteration from the start set
+    ``start`` (None: the empty set).  Returns dict(u, w, active, iters,
+    status)."""
+    band = _f64(band)
+    n, wd = band.shape
+    q = (wd - 1) // 2
+    f = _f64(f)
+    bounded = _mask(bounded)
+    start = _mask(start)
+    u = np.zeros(n)
+    w = np.zeros(n)
+    act = np.zeros(n, dtype=np.uint8)
+    it = ctypes.c_int(0)
+    st = lib().or_lcp_solve_start(n, q, _dp(band), _dp(f), _u8(bounded), _u8(start), max_iter,
+                                  _dp(u), _dp(w), _u8(act), ctypes.byref(it))
     return dict(u=u, w=w, active=act, iters=it.value, status=st)
 
 

@@ -359,17 +359,21 @@ static void band_residual(int64_t n, int q, const double *band, const double *u,
  * mode OR_LINEAR: u = A^{-1} f (no projection).
  * mode OR_CLIP:   u = max(0, A^{-1} f) on bounded rows (projection of the
  *                 linear solve, the literal PAQIF step).
- * mode OR_EXACT:  primal-dual active set.  A_0 = {bounded i : f_i <= 0}
- *                 (the sign of f predicts the active constraints of a
- *                 diagonally dominant system); solve with the rows
- *                 and columns of A_k replaced by the identity and f = 0
- *                 there; w = A u - f;
+ * mode OR_EXACT:  primal-dual active set from a start set A_0: solve with
+ *                 the rows and columns of A_k replaced by the identity and
+ *                 f = 0 there; w = A u - f;
  *                 A_{k+1} = {i in A_k : w_i > 0} u {i not in A_k : u_i < 0}
  *                 (bounded rows only); stop when A_{k+1} = A_k.
+ *                 or_lcp_solve_start takes A_0 from the caller (NULL: the
+ *                 empty set); or_lcp_solve starts from {bounded i : f_i <= 0},
+ *                 which predicts the binding constraints of a diagonally
+ *                 dominant system.  Where the LCP has one solution (a
+ *                 P-matrix) the start changes only the number of solves.
  * `iters` returns the number of AQIF solves.
  */
-int or_lcp_solve(int64_t n, int q, const double *band, const double *f, const uint8_t *bounded,
-                 int mode, int max_iter, double *u, double *w, uint8_t *active, int *iters)
+static int lcp_solve_impl(int64_t n, int q, const double *band, const double *f,
+                          const uint8_t *bounded, int mode, int max_iter, int sign_start,
+                          const uint8_t *start, double *u, double *w, uint8_t *active, int *iters)
 {
     if (iters) *iters = 0;
     if (n <= 0) return OR_OK;
@@ -380,8 +384,10 @@ int or_lcp_solve(int64_t n, int q, const double *band, const double *f, const ui
     int it = 0;
     if (mode == OR_EXACT) {
         st = OR_LCP_NOT_CONVERGED;
-        for (int64_t i = 0; i < n; i++)
-            act[i] = (uint8_t)((bounded ? bounded[i] != 0 : 1) && f[i] <= 0.0);
+        for (int64_t i = 0; i < n; i++) {
+            int in0 = sign_start ? f[i] <= 0.0 : (start ? start[i] != 0 : 0);
+            act[i] = (uint8_t)((bounded ? bounded[i] != 0 : 1) && in0);
+        }
         while (it < max_iter) {
             int s2 = or_aqif_solve(n, q, band, act, f, u);
             it++;
@@ -424,6 +430,20 @@ int or_lcp_solve(int64_t n, int q, const double *band, const double *f, const ui
     free(nxt);
     free(wt);
     return st;
+}
+
+int or_lcp_solve(int64_t n, int q, const double *band, const double *f, const uint8_t *bounded,
+                 int mode, int max_iter, double *u, double *w, uint8_t *active, int *iters)
+{
+    return lcp_solve_impl(n, q, band, f, bounded, mode, max_iter, 1, NULL, u, w, active, iters);
+}
+
+int or_lcp_solve_start(int64_t n, int q, const double *band, const double *f,
+                       const uint8_t *bounded, const uint8_t *start, int max_iter, double *u,
+                       double *w, uint8_t *active, int *iters)
+{
+    return lcp_solve_impl(n, q, band, f, bounded, OR_EXACT, max_iter, 0, start, u, w, active,
+                          iters);
 }
 
 /*

@@ -8,7 +8,7 @@ the exact solution u = x^4 + y^4, eps = 1e-6.  The paper leaves a and b
 unspecified; constant a = b = 1 is used (the kappa-scheme derivation assumes
 a constant positive a).
 
-Discretisation (Sec. 2 kappa-schemes): on a uniform (n x n)-node grid,
+Discretisation (Sec. 3.1 kappa-schemes, eqs. 40-42): on a uniform (n x n)-node grid,
 h = 2/(n-1), node (i, j) at (x_i, y_j); for a > 0 the convective term is the
 flux difference a (u_{i+1/2} - u_{i-1/2}) / h with the kappa interface value
 u_{i+1/2} = u_i + (1+kappa)/4 (u_{i+1} - u_i) + (1-kappa)/4 (u_i - u_{i-1});
@@ -23,7 +23,7 @@ dominant, so the interlocking factorisation's 2 x 2 pivots stay regular)
 plus the diagonal of the across-line part, then u += omega sigma; x-lines
 and y-lines alternate.  At the fixed point L_h u = f.  Pins: tests/test_oracle_convdiff.py.
 
-Distributive line relaxation (Ls3 of Sec. 2, the "kappa-distributive"
+Distributive line relaxation (Ls3 of Sec. 3.1, eqs. 51-54, the "kappa-distributive"
 splitting): the change of a node is distributed, u_ij += s_ij - (s_{i+-1,j}
 + s_{i,j+-1})/4 (eq. 51), so a line solves for ghost changes s* whose
 distributed pattern cancels the line's defect: row (i, l) of the line matrix

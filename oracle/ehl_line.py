@@ -116,8 +116,8 @@ def vanleer(dm, dp):
 def slope(dm, dp, kappa=None):
     """Slope psi of the convective face value (rH)_{i+1/2} = (rH)_i + psi/2
     and its partials wrt D+ and D-: the van Leer limited slope (TVD, the
-    method's default), or with kappa given the kappa-scheme of Sec. 2 (eqs.
-    57-59), psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear and unlimited."""
+    method's default), or with kappa given the kappa-scheme of Sec. 3.3 (eqs.
+    56-59), psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear and unlimited."""
     if kappa is None:
         return vanleer(dm, dp)
     return (0.5 * (1.0 + kappa) * dp + 0.5 * (1.0 - kappa) * dm,
@@ -316,7 +316,7 @@ def hybrid_direct(P, eps, h):
 
 def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2, limjac=LIMJAC,
                 kappa=None):
-    """One Lhs1 step (kappa given: the kappa-scheme convection of Sec. 2
+    """One Lhs1 step (kappa given: the kappa-scheme convection of Sec. 3.3
     instead of the limited slope); returns (P_new, H0_new, info)."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
@@ -366,7 +366,8 @@ def lcp_exact(A, b, bounded):
 
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
-               rough=None, P=None, H0=None, limjac=None, stall_steps=0, kappa=None):
+               rough=None, P=None, H0=None, limjac=None, stall_steps=0, kappa=None,
+               rigid=False):
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
@@ -375,9 +376,12 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     max |P change| has set no new minimum for stall_steps steps (status 6;
     0 = never), else status 6 after max_newton steps.  Returns a dict
     with P (N nodes), H0, H, Hmin (min over all nodes, first index), the
-    number of steps and the status."""
+    number of steps and the status.  ``rigid`` drops the elastic
+    deformation (K = 0); with L = 0 (p_h = 0) the lubricant is
+    incompressible and isoviscous (rho = eta = 1), the rigid-isoviscous
+    problem the paper names for incompressible flow."""
     x, h = grid(N)
-    kvec = deform.line_kernel(N, h)
+    kvec = np.zeros(N) if rigid else deform.line_kernel(N, h)
     if P is None:
         P = hertz_start(x)
         P[0] = P[-1] = 0.0

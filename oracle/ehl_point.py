@@ -17,7 +17,7 @@ Discretisation (eqs. 62-65 on the 2D grid, flow in +X): for interior (i, j)
          - [(rho H)*_{i+1/2,j} - (rho H)*_{i-1/2,j}] / hx,
 face values eps_{i+-1/2,j} = (eps_ij + eps_{i+-1,j}) / 2 (eq. 63) and the TVD
 flux of each x-row exactly as in the line contact (van Leer, psi = 0 at the
-inlet face; optionally the kappa-scheme slope of Sec. 2, eqs. 57-59, as in
+inlet face; optionally the kappa-scheme slope of Sec. 3.3, eqs. 56-59, as in
 ehl_line.slope).
 
 Iteration (alternating line sweeps, eqs. 60, 62, 66-75): one step is an
@@ -90,7 +90,7 @@ def film(P, H0, X, Y, hx, hy, rough=None):
 def x_flux(rH, kappa=None):
     """(rho H)* at the faces i+1/2 of every x-row, f[t, :] for t = 0..Nx-2,
     and the slope derivatives pa = dpsi/dD+, pb = dpsi/dD- at nodes 1..Nx-2
-    (van Leer; with kappa given the kappa-scheme slope of Sec. 2, eqs. 57-59)."""
+    (van Leer; with kappa given the kappa-scheme slope of Sec. 3.3, eqs. 56-59)."""
     psi, pa, pb = EL.slope(rH[1:-1] - rH[:-2], rH[2:] - rH[1:-1], kappa)
     f = np.empty((rH.shape[0] - 1, rH.shape[1]))
     f[0] = rH[0]

@@ -1,7 +1,7 @@
 // Linear convection-diffusion workload (numerical results of the paper,
 // Example 1 with the linear case study): (a u)_x + (b u)_y - eps Lap u = f
 // on [-1, 1]^2 with Dirichlet data, a, b > 0 constant, kappa-scheme
-// convection (Sec. 2), 5-point diffusion, solved by alternating line
+// convection (Sec. 3.1, eqs. 40-42), 5-point diffusion, solved by alternating line
 // relaxation as a defect correction whose line systems are batched PAQIF
 // solves (plain linear mode, half-bandwidth 2).
 //
@@ -103,7 +103,7 @@ __global__ void cd_update_kernel(int n, int axis, double omega, const double* si
 }
 
 // ---------------------------------------------------------------------------
-// Distributive line relaxation (Ls3 of Sec. 2, eq. 51): the change of a node
+// Distributive line relaxation (Ls3 of Sec. 3.1, eqs. 51-54): the change of a node
 // is distributed, u += s - (sum of the four neighbours' s) / 4, and a line
 // solves for ghost changes whose distributed pattern cancels its defect.
 // Row (i, l) of the line matrix, column k: L_h applied to the pattern of a

@@ -74,7 +74,7 @@ struct AdjPartialArgs {
     const ehl_params* params;
     const double *P, *Hel, *H0, *rough;
     double *RPb, *RHb, *FM, *FL;
-    int conv = 0;  // 0 van Leer slope, 1 kappa-scheme slope (Sec. 2)
+    int conv = 0;  // 0 van Leer slope, 1 kappa-scheme slope (Sec. 3.3, eqs. 56-59)
     double kappa = 0.0;
 };
 

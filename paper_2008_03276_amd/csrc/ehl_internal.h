@@ -89,7 +89,7 @@ int launch_point_nodes(const PointNodeArgs& a, hipStream_t s);
 
 struct PointAssembleArgs {
     int Nx, Ny, B, axis, color, kterms, limjac;
-    int conv;      // 0 van Leer slope, 1 kappa-scheme slope (Sec. 2)
+    int conv;      // 0 van Leer slope, 1 kappa-scheme slope (Sec. 3.3, eqs. 56-59)
     double kappa;
     double hx, hy;
     const double* k2;  // Nx x Ny kernel table

@@ -92,8 +92,8 @@ PQ_DEV void limiter_jacobian(int mode, double dm, double dp, double& pa, double&
 
 // Convective slope psi of the face value (rho H)_{i+1/2} = (rho H)_i + psi/2
 // and the coefficients (pa, pb) of the Newton matrix: conv 0 the van Leer
-// slope with limiter_jacobian(limjac); conv 1 the kappa-scheme (Sec. 2,
-// eqs. 57-59) psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear, whose exact
+// slope with limiter_jacobian(limjac); conv 1 the kappa-scheme (Sec. 3.3,
+// eqs. 56-59) psi = (1+kappa)/2 D+ + (1-kappa)/2 D-, linear, whose exact
 // coefficients are used for limjac 0 and 1 (limjac 2: first-order flux).
 PQ_DEV void convective_slope(int conv, double kappa, int limjac, double dm, double dp,
                              double& psi, double& pa, double& pb)

@@ -177,7 +177,7 @@ KAPPA_CASES = [0.0, 1.0 / 3.0, -1.0]
 @pytest.mark.parametrize("limjac", [0, 2])
 @pytest.mark.parametrize("kappa", KAPPA_CASES)
 def test_line_assembly_kappa_scheme(gpu, N, limjac, kappa):
-    """kappa-scheme convection (Sec. 2): band, residual, rhs and masks of the
+    """kappa-scheme convection (Sec. 3.3, eqs. 56-59): band, residual, rhs and masks of the
     GPU assembly against the oracle's, same bounds as the van Leer case."""
     P = gpu.ehl
     Ms, Ls, H0s = [20.0, 100.0], [10.0, 5.0], [-0.3, -0.55]

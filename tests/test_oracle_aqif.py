@@ -170,6 +170,29 @@ def test_lcp_brute_force(q):
                 np.abs(r["u"][r["active"] != sols[0][1]]).max() < 1e-12
 
 
+@pytest.mark.parametrize("q", [1, 2, 4])
+def test_lcp_empty_start_reaches_the_same_solution(q):
+    """The active-set iteration from the empty set (the textbook start) and
+    from the sign of f reach the same, unique, solution; both agree with
+    brute force on small systems and with each other at full size."""
+    for n in [1, 2, 5, 11]:
+        for item in range(3):
+            band, f = synth.lcp_system(n, q, 1, item)
+            sols = brute_force_lcp(dense(band), f)
+            r0 = oracle.lcp_solve_start(band, f)
+            assert r0["status"] == oracle.OK
+            assert np.abs(r0["u"] - sols[0][0]).max() < 1e-12
+    band, f = synth.lcp_system(4097, q, 0, 0)
+    r0 = oracle.lcp_solve_start(band, f)
+    r1 = oracle.lcp_solve(band, f, mode=oracle.EXACT)
+    assert r0["status"] == oracle.OK and r1["status"] == oracle.OK
+    assert (r0["active"] == r1["active"]).all()
+    assert np.abs(r0["u"] - r1["u"]).max() <= 1e-13 * max(1.0, np.abs(r1["u"]).max())
+    # a start equal to the solution's active set ends after one solve
+    r2 = oracle.lcp_solve_start(band, f, start=r1["active"])
+    assert r2["iters"] == 1 and (r2["active"] == r1["active"]).all()
+
+
 def test_lcp_brute_force_with_free_rows():
     q = 2
     for item in range(6):

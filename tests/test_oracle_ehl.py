@@ -242,7 +242,7 @@ def test_newton_stops_when_the_change_stalls(monkeypatch):
 
 @pytest.mark.parametrize("kappa", [0.0, 1.0 / 3.0, -1.0, 0.5])
 def test_kappa_slope_closed_form_on_a_cubic(kappa):
-    """The kappa-scheme face values (rH)_{i+1/2} = (rH)_i + psi/2 of Sec. 2
+    """The kappa-scheme face values (rH)_{i+1/2} = (rH)_i + psi/2 of Sec. 3.3
     on rH = x^3: the flux difference is 3 x^2 + h^2 (3 kappa - 1)/2 exactly
     (third order only for kappa = 1/3); swapping the (1+kappa), (1-kappa)
     weights or halving psi fails it."""
