@@ -273,6 +273,14 @@ typedef struct {
                             D- (Sec. 3.3, eqs. 56-59; line and point contact
                             and the line-contact adjoint)                    */
     double kappa;        /* -1 <= kappa <= 1 for convection 1                */
+    int32_t lcp_fail_steps; /* stop an instance whose linearised LCP failed in this
+                             many consecutive Newton steps (active-set cap hit:
+                             SYS_LCP_NOT_CONVERGED; FP32 + refinement stalled:
+                             SYS_REFINE_STALLED, the status of the last failure);
+                             0 = 16.  A zero or non-finite pivot stops the
+                             instance at once (SYS_ZERO_PIVOT / SYS_NONFINITE).
+                             Point contact: a step fails if any line of any of
+                             its four colour passes failed.                    */
 } ehl_opts;
 
 /*

@@ -359,20 +359,21 @@ def start_h0(x, h, kvec, M):
     return 0.4 / np.sqrt(M) - np.min(g[np.abs(x) <= 1.0])
 
 
-def lcp_exact(A, b, bounded):
+def lcp_exact(A, b, bounded, max_iter=64):
     from . import lcp_solve, EXACT
-    r = lcp_solve(A, b, bounded=bounded, mode=EXACT, max_iter=64)
+    r = lcp_solve(A, b, bounded=bounded, mode=EXACT, max_iter=max_iter)
     return r["u"], r["status"]
 
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
                rough=None, P=None, H0=None, limjac=None, stall_steps=0, kappa=None,
-               rigid=False):
+               rigid=False, lcp_max_iter=64, lcp_fail_steps=LCP_FAIL_STEPS):
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
     <= t, t = max(tol, 4 N eps) (status 0), when the linearised LCP hits its
-    active-set cap in LCP_FAIL_STEPS consecutive steps (status 3), when
+    active-set cap (lcp_max_iter) in lcp_fail_steps consecutive steps
+    (status 3), when
     max |P change| has set no new minimum for stall_steps steps (status 6;
     0 = never), else status 6 after max_newton steps.  Returns a dict
     with P (N nodes), H0, H, Hmin (min over all nodes, first index), the
@@ -391,7 +392,7 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     last = [0]
 
     def lcp(A, b, bnd):
-        u, st = lcp_exact(A, b, bnd)
+        u, st = lcp_exact(A, b, bnd, lcp_max_iter)
         last[0] = st
         return u
 
@@ -413,7 +414,7 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
         if dP <= tl * max(1.0, np.abs(P).max()) and abs(np.pi / 2 - h * P.sum()) <= tl:
             status = 0
             break
-        if fails >= LCP_FAIL_STEPS:
+        if fails >= lcp_fail_steps:
             # the active-set iteration cycles: this linearisation has no
             # solution the iteration reaches, the Newton iteration is lost
             status = LCP_NOT_CONVERGED

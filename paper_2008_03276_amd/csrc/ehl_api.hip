@@ -58,6 +58,9 @@ void host_kernel_head(double h, double kap[4])
     for (int m = 0; m < 4; m++) kap[m] = -(F((m + 0.5) * h) - F((m - 0.5) * h)) / M_PI;
 }
 
+// Consecutive failed linearised LCPs after which an instance stops.
+int fail_steps(const ehl_opts* o) { return o->lcp_fail_steps > 0 ? o->lcp_fail_steps : 16; }
+
 // Rounding floor of the Newton change in FP64 on a line of n nodes: the
 // stopping test uses max(tol, 4 n eps), eps = 2^-52 (measured floors: about
 // 1.5e-13 at n = 1025 and 6e-13 at n = 2049, which a fixed 1e-13 never meets).
@@ -77,7 +80,8 @@ bool valid_opts(const ehl_opts* o)
             o->deform_prec == PREC_SPLIT_BF16) &&
            (o->lcp_prec == PREC_FP64 || o->lcp_prec == PREC_FP32_IR) &&
            o->steps_per_graph >= 1 && o->steps_per_graph <= 64 && o->limiter_jacobian >= 0 &&
-           o->limiter_jacobian <= 2 && o->stall_steps >= 0 && valid_convection(o);
+           o->limiter_jacobian <= 2 && o->stall_steps >= 0 && o->lcp_fail_steps >= 0 &&
+           valid_convection(o);
 }
 
 // Newton workspace layout (line contact)
@@ -142,11 +146,12 @@ __global__ void init_newton_kernel(int B, int n, int64_t* offs, uint8_t* done, i
 }
 
 // Before an FP64 refresh phase: instances that converged under the
-// low-precision deformation go on; non-finite ones stay stopped.
+// low-precision deformation go on; non-finite ones and those whose band
+// matrix had a singular pivot stay stopped.
 __global__ void reopen_kernel(int B, uint8_t* done, int32_t* status)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B && status[i] != SYS_NONFINITE) {
+    if (i < B && status[i] != SYS_NONFINITE && status[i] != SYS_ZERO_PIVOT) {
         done[i] = 0;
         status[i] = SYS_NEWTON_NOT_CONVERGED;
     }
@@ -179,7 +184,7 @@ __global__ void final_status_kernel(int B, const uint8_t* done, const double* Hm
 // ---------------------------------------------------------------------------
 struct PointLayout {
     size_t dws, hel, nodes, direct, q, pstart, band, rhs, v, bounded, done, offs[4], act[4], lst,
-        lit, lcp, total;
+        lit, pst, pfail, lcp, total;
     int nlc[4], nrow[4];  // (axis, colour) -> lines per instance, rows per line
 };
 
@@ -220,18 +225,23 @@ PointLayout point_layout(const ehl_grid* g, int B, const ehl_opts* o)
     for (int k = 0; k < 4; k++) L.act[k] = take((size_t)L.nlc[k] * L.nrow[k] * B);
     L.lst = take((size_t)cnt_max * sizeof(int32_t));
     L.lit = take((size_t)cnt_max * sizeof(int32_t));
+    L.pst = take((size_t)B * sizeof(int32_t));
+    L.pfail = take((size_t)B * sizeof(int32_t));
     L.lcp = take(lcp_ws_bytes(cnt_max, n_max, o ? o->lcp_prec : PREC_FP64));
     L.total = p;
     return L;
 }
 
-__global__ void point_init_kernel(int B, uint8_t* done, int32_t* status, int32_t* iters)
+__global__ void point_init_kernel(int B, uint8_t* done, int32_t* status, int32_t* iters,
+                                  int32_t* pst, int32_t* pfail)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < B) {
         done[i] = 0;
         status[i] = SYS_NEWTON_NOT_CONVERGED;
         iters[i] = 0;
+        pst[i] = SYS_OK;
+        pfail[i] = 0;
     }
 }
 
@@ -262,6 +272,8 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
     uint8_t* done = reinterpret_cast<uint8_t*>(ws + L.done);
     int32_t* lst = reinterpret_cast<int32_t*>(ws + L.lst);
     int32_t* lit = reinterpret_cast<int32_t*>(ws + L.lit);
+    int32_t* pst = reinterpret_cast<int32_t*>(ws + L.pst);
+    int32_t* pfail = reinterpret_cast<int32_t*>(ws + L.pfail);
     char* lcpws = ws + L.lcp;
     int st;
     // kernel table, offsets, flags, start
@@ -272,7 +284,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                            L.nrow[k], reinterpret_cast<int64_t*>(ws + L.offs[k]));
     }
     hipLaunchKernelGGL(point_init_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, done, status,
-                       iters);
+                       iters, pst, pfail);
     if (opts->start_rule) {
         if ((st = pq::launch_point_start(Nx, Ny, B, grid->x0, grid->y0, hx, hy, P, s))) return st;
         if ((st = run_deformation(grid, P, B, PREC_FP64, hel, ws + L.dws, true, s))) return st;
@@ -385,6 +397,9 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
     ha.done = done;
     ha.status = status;
     ha.iters = iters;
+    ha.step_lcp = pst;
+    ha.lcp_fails = pfail;
+    ha.fail_steps = fail_steps(opts);
 
     const int layout = handle->layout[1][opts->lcp_prec == PREC_FP32_IR];
     auto one_step = [&](int dprec) -> int {
@@ -406,6 +421,8 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
                 la.act = reinterpret_cast<uint8_t*>(ws + L.act[k]);
                 if (la.count > 0 && (e = pq::dispatch_lcp(4, la, opts->lcp_prec, layout, s)))
                     return e;
+                // worst LCP status of each instance's lines, folded into its step status
+                if ((e = pq::launch_point_lcp_status(B, L.nlc[k], lst, done, pst, s))) return e;
                 ua.axis = ax;
                 ua.color = c;
                 ua.P = cur;
@@ -673,6 +690,7 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     ua.best_dP = reinterpret_cast<double*>(ws + L.best);
     ua.best_step = reinterpret_cast<int32_t*>(ws + L.bstep);
     ua.stall_steps = opts->stall_steps;
+    ua.fail_steps = fail_steps(opts);
 
     auto one_step = [&](int dprec) -> int {
         int e;

@@ -55,11 +55,27 @@ struct LineUpdateArgs {
     double* best_dP;     // B, smallest max |P change| of the phase so far
     int32_t* best_step;  // B, step (iters count) at which it was reached
     int stall_steps;     // stop after this many steps without a new minimum (0: never)
+    int fail_steps;      // stop after this many consecutive failed step LCPs
 };
-// An instance whose linearised LCP hits the active-set cap in this many
-// consecutive Newton steps stops with SYS_LCP_NOT_CONVERGED (the active-set
-// iteration is cycling: the step's linearisation has no reachable solution)
-constexpr int kLcpFailSteps = 16;
+// Severity of a band LCP's status for an EHL instance: a singular or
+// non-finite pivot stops the instance at once; a capped active-set
+// iteration or a stalled refinement counts as a failed step, and an
+// instance whose step LCP failed in fail_steps consecutive Newton steps
+// stops with the last failure's status (the active-set iteration cycles,
+// or the FP32 factors cannot be refined: the step's linearisation has no
+// solution the iteration reaches).
+PQ_DEV int lcp_severity(int st)
+{
+    switch (st) {
+    case SYS_LCP_NOT_CONVERGED: return 1;
+    case SYS_REFINE_STALLED: return 2;
+    case SYS_NONFINITE: return 3;
+    case SYS_ZERO_PIVOT: return 4;
+    default: return 0;
+    }
+}
+PQ_DEV int lcp_fatal(int st) { return st == SYS_ZERO_PIVOT || st == SYS_NONFINITE; }
+PQ_DEV int lcp_failed(int st) { return st == SYS_LCP_NOT_CONVERGED || st == SYS_REFINE_STALLED; }
 int launch_line_update_ws(const LineUpdateArgs& a, double* Pnew, hipStream_t s);
 
 struct LineInitArgs {
@@ -119,8 +135,14 @@ struct PointH0Args {
     double *Pstart, *H0;
     uint8_t* done;
     int32_t *status, *iters;
+    int32_t* step_lcp;   // B: worst LCP status of the step's colour passes (reset per step)
+    int32_t* lcp_fails;  // B: consecutive steps with a failed LCP
+    int fail_steps;
 };
 int launch_point_h0(const PointH0Args& a, int check, hipStream_t s);
+// fold the worst LCP status of each instance's nlc lines into step_lcp
+int launch_point_lcp_status(int B, int nlc, const int32_t* lst, const uint8_t* done,
+                            int32_t* step_lcp, hipStream_t s);
 int launch_point_start(int Nx, int Ny, int B, double x0, double y0, double hx, double hy,
                        double* P, hipStream_t s);
 int launch_point_h0_rule(int Nx, int Ny, int B, double x0, double y0, double hx, double hy,

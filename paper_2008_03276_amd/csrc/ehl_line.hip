@@ -258,16 +258,20 @@ __global__ void __launch_bounds__(256) line_update_kernel(LineUpdateArgs a, doub
         a.iters[b] += 1;
         a.dP[b] = dmax;
         a.load_err[b] = err;
-        const int fails = a.lcp_status[b] == SYS_LCP_NOT_CONVERGED ? a.lcp_fails[b] + 1 : 0;
+        const int lst = a.lcp_status[b];
+        const int fails = lcp_failed(lst) ? a.lcp_fails[b] + 1 : 0;
         a.lcp_fails[b] = fails;
         if (fin != 0.0 || !isfinite(dmax) || !isfinite(sum)) {
             a.status[b] = SYS_NONFINITE;
             a.done[b] = 1;
+        } else if (lcp_fatal(lst)) {
+            a.status[b] = lst;
+            a.done[b] = 1;
         } else if (dmax <= a.tol * fmax(1.0, pmax) && fabs(err) <= a.tol) {
             a.status[b] = SYS_OK;
             a.done[b] = 1;
-        } else if (fails >= kLcpFailSteps) {
-            a.status[b] = SYS_LCP_NOT_CONVERGED;
+        } else if (fails >= a.fail_steps) {
+            a.status[b] = lst;
             a.done[b] = 1;
         } else if (dmax < a.best_dP[b]) {
             a.best_dP[b] = dmax;

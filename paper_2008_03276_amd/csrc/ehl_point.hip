@@ -390,16 +390,62 @@ __global__ void __launch_bounds__(1024) point_h0_kernel(PointH0Args a, int check
         const double err = a.load_target - a.hx * a.hy * S;
         a.H0[b] -= a.c_h0 * err;
         if (check) {
+            // end of an x+y step: the worst LCP status of its four colour passes
+            const int lst = a.step_lcp[b];
+            a.step_lcp[b] = SYS_OK;
+            const int fails = lcp_failed(lst) ? a.lcp_fails[b] + 1 : 0;
+            a.lcp_fails[b] = fails;
             a.iters[b] += 1;
             if (!isfinite(D) || !isfinite(S)) {
                 a.status[b] = SYS_NONFINITE;
                 a.done[b] = 1;
+            } else if (lcp_fatal(lst)) {
+                a.status[b] = lst;
+                a.done[b] = 1;
             } else if (D <= a.tol * fmax(1.0, Pm) && fabs(err) <= a.tol) {
                 a.status[b] = SYS_OK;
+                a.done[b] = 1;
+            } else if (fails >= a.fail_steps) {
+                a.status[b] = lst;
                 a.done[b] = 1;
             }
         }
     }
+}
+
+// One wavefront per instance: the worst (by lcp_severity) status over the
+// instance's lines of one colour pass, folded into its step status.
+__global__ void __launch_bounds__(64) point_lcp_status_kernel(int nlc, const int32_t* lst,
+                                                             const uint8_t* done, int32_t* step)
+{
+    const int b = blockIdx.x;
+    if (done[b]) return;
+    int worst = SYS_OK, sev = 0;
+    for (int l = threadIdx.x; l < nlc; l += 64) {
+        const int st = lst[(int64_t)b * nlc + l];
+        const int sv = lcp_severity(st);
+        if (sv > sev) {
+            sev = sv;
+            worst = st;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int os = __shfl_xor(sev, m, 64), ow = __shfl_xor(worst, m, 64);
+        if (os > sev) {
+            sev = os;
+            worst = ow;
+        }
+    }
+    if (threadIdx.x == 0 && sev > lcp_severity(step[b])) step[b] = worst;
+}
+
+int launch_point_lcp_status(int B, int nlc, const int32_t* lst, const uint8_t* done,
+                            int32_t* step_lcp, hipStream_t s)
+{
+    if (B <= 0 || nlc <= 0) return PAQIF_OK;
+    hipLaunchKernelGGL(point_lcp_status_kernel, dim3(B), dim3(64), 0, s, nlc, lst, done, step_lcp);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
 int launch_point_h0(const PointH0Args& a, int check, hipStream_t s)

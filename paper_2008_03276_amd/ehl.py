@@ -25,7 +25,8 @@ def point_grid(Nx, Ny, x0=XA, x1=XB, y0=-3.0, y1=3.0):
 def default_opts(**kw):
     o = dict(omega=0.5, c_h0=0.1, switch_ratio=0.6, tol=1e-13, max_newton=4000, kernel_terms=2,
              lcp_max_iter=64, deform_prec=B.PREC_FP64, lcp_prec=B.PREC_FP64, steps_per_graph=16,
-             start_rule=1, limiter_jacobian=2, stall_steps=0, convection=0, kappa=0.0)
+             start_rule=1, limiter_jacobian=2, stall_steps=0, convection=0, kappa=0.0,
+             lcp_fail_steps=16)
     o.update(kw)
     return B.EhlOpts(**o)
 
@@ -214,7 +215,9 @@ class LineEHL(torch.autograd.Function):
     shape (B,) and rough (B, N) or None; the backward pass is the hand-written
     adjoint (ehl_adjoint_solve) and gives gradients for M, L and rough.  An
     output such as Hmin = H.min(dim=1).values is differentiated by torch into
-    the film cotangent at the arg-min."""
+    the film cotangent at the arg-min.  The adjoint is the derivative of the
+    converged fixed point: an instance whose forward solve did not converge
+    (status not SYS_OK) gets NaN gradients."""
 
     @staticmethod
     def forward(ctx, M, L, rough, N, opts=None):
@@ -225,18 +228,23 @@ class LineEHL(torch.autograd.Function):
         Lv = L.detach().to(torch.float64).cpu()
         rg = None if rough is None else rough.detach().to(torch.float64).contiguous()
         r = solve_line(Mv, Lv, N, opts=opts, rough=rg, device=dev)
-        ctx.save_for_backward(r["P"], r["H0"])
+        ctx.save_for_backward(r["P"], r["H0"], r["status"])
         ctx.args = (Mv, Lv, rg, N, opts, M.device, L.device)
         ctx.mark_non_differentiable(r["status"])
         return r["P"], r["H0"], r["H"], r["status"]
 
     @staticmethod
     def backward(ctx, gP, gH0, gH, gstatus):
-        P, H0 = ctx.saved_tensors
+        P, H0, fst = ctx.saved_tensors
         Mv, Lv, rg, N, opts, mdev, ldev = ctx.args
         c = lambda t: None if t is None else t.to(torch.float64).contiguous()
         a = adjoint(Mv, Lv, N, P, H0, gP=c(gP), gH0=c(gH0), gH=c(gH), rough=rg, opts=opts)
-        if (a["status"] != B.SYS_OK).any():
+        conv = fst == B.SYS_OK  # forward converged: the implicit-function adjoint holds
+        bad = conv & (a["status"] != B.SYS_OK)
+        if bad.any():
             raise RuntimeError(f"ehl_adjoint_solve: instance status {a['status'].tolist()}")
-        drough = a["drough"] if rg is not None else None
-        return a["dM"].to(mdev), a["dL"].to(ldev), drough, None, None
+        nan = torch.tensor(float("nan"), dtype=torch.float64, device=P.device)
+        dM = torch.where(conv, a["dM"], nan)
+        dL = torch.where(conv, a["dL"], nan)
+        drough = torch.where(conv[:, None], a["drough"], nan) if rg is not None else None
+        return dM.to(mdev), dL.to(ldev), drough, None, None

@@ -39,6 +39,34 @@ def _need(t, dtype, name):
         raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
 
 
+def _need_len(t, n, name):
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, the batch needs {n}")
+
+
+def _check_system_args(batch, band, b=None, bounded=None):
+    """Sizes of the per-row arguments against the batch (the C ABI takes
+    bare pointers, so a short buffer would be read or written past its end)."""
+    rows = batch.total_rows
+    _need(band, torch.float64, "band")
+    _need_len(band, rows * (2 * batch.q + 1), "band")
+    if b is not None:
+        _need(b, torch.float64, "b")
+        _need_len(b, rows, "b")
+    if bounded is not None:
+        _need(bounded, torch.uint8, "bounded")
+        _need_len(bounded, rows, "bounded")
+
+
+def _check_workspace(batch, workspace, prec, mode):
+    if not (workspace.is_cuda and workspace.is_contiguous()):
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    have = workspace.numel() * workspace.element_size()
+    need = batch.workspace_bytes(prec, mode)
+    if have < need:
+        raise ValueError(f"workspace has {have} bytes, the batch needs {need}")
+
+
 class Batch:
     """Host + device description of a batch of band systems (one q)."""
 
@@ -75,10 +103,7 @@ def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
     """PAQIF solve of the banded LCP for every system of ``batch``.
 
     Returns dict(u, w, active, status, iters) (device tensors)."""
-    _need(band, torch.float64, "band")
-    _need(b, torch.float64, "b")
-    if bounded is not None:
-        _need(bounded, torch.uint8, "bounded")
+    _check_system_args(batch, band, b, bounded)
     dev = band.device
     n = batch.total_rows
     u = torch.empty(n, dtype=torch.float64, device=dev)
@@ -88,6 +113,7 @@ def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
     it = torch.empty(batch.count, dtype=torch.int32, device=dev)
     if workspace is None:
         workspace = batch.workspace(prec, mode)
+    _check_workspace(batch, workspace, prec, mode)
     code = B.lib().paqif_solve_lcp(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
                                    _ptr(bounded), mode, prec, refine_tol, max_iter, _ptr(u),
                                    _ptr(w), _ptr(act), _ptr(st), _ptr(it), _ptr(workspace),
@@ -98,9 +124,10 @@ def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
 
 def factor(batch, band, pinned=None, factors=None):
     """A = W0 Z0 for every system; returns (factors, status)."""
-    _need(band, torch.float64, "band")
+    _check_system_args(batch, band, bounded=pinned)
     if factors is None:
         factors = batch.workspace(B.PREC_FP64, B.LCP_LINEAR)
+    _check_workspace(batch, factors, B.PREC_FP64, B.LCP_LINEAR)
     st = torch.empty(batch.count, dtype=torch.int32, device=band.device)
     code = B.lib().paqif_factor(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(pinned),
                                 B.PREC_FP64, _ptr(factors), _ptr(st), _stream())
@@ -110,6 +137,11 @@ def factor(batch, band, pinned=None, factors=None):
 
 def solve_factored(batch, factors, rhs, pinned=None):
     _need(rhs, torch.float64, "rhs")
+    _need_len(rhs, batch.total_rows, "rhs")
+    if pinned is not None:
+        _need(pinned, torch.uint8, "pinned")
+        _need_len(pinned, batch.total_rows, "pinned")
+    _check_workspace(batch, factors, B.PREC_FP64, B.LCP_LINEAR)
     x = torch.empty_like(rhs)
     code = B.lib().paqif_solve_factored(handle(), ctypes.byref(batch.c), _ptr(factors),
                                         _ptr(pinned), _ptr(rhs), _ptr(x), _stream())
@@ -133,14 +165,14 @@ def autotune(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None, m
              workspace=None):
     """Time every lane layout of the LCP kernel on this batch; the fastest is
     kept in the handle for (q, prec).  Returns (chosen, times_ms)."""
-    _need(band, torch.float64, "band")
-    _need(b, torch.float64, "b")
+    _check_system_args(batch, band, b, bounded)
     nl = layout_count(batch.q)
     times = (ctypes.c_float * nl)()
     u = torch.empty(batch.total_rows, dtype=torch.float64, device=band.device)
     st = torch.empty(batch.count, dtype=torch.int32, device=band.device)
     if workspace is None:
         workspace = batch.workspace(prec, mode)
+    _check_workspace(batch, workspace, prec, mode)
     B.check(B.lib().paqif_autotune(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
                                    _ptr(bounded), mode, prec, max_iter, _ptr(u), _ptr(st),
                                    _ptr(workspace), _stream(), times), "paqif_autotune")

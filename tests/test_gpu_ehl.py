@@ -162,6 +162,36 @@ def test_newton_mixed_deformation_refreshed(gpu, oracle_cfg1):
         assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-8 * abs(o["Hmin"])
 
 
+def test_newton_fp32_refined_lcp_matches_oracle(gpu, oracle_cfg1):
+    """lcp_prec = FP32 factors + FP64 refinement inside every Newton step:
+    the same fixed point within the mixed-path target 1e-8."""
+    P = gpu.ehl
+    o = oracle_cfg1
+    r = P.solve_line([20.0], [10.0], 257, opts=P.default_opts(lcp_prec=P.B.PREC_FP32_IR))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    assert _rel(r["P"][0].cpu().numpy(), o["P"]) < 1e-8
+    assert _rel(r["H"][0].cpu().numpy(), o["H"]) < 1e-8
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-8 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-8 * abs(o["Hmin"])
+
+
+def test_newton_forced_lcp_cap_status(gpu):
+    """An active-set cap of one solve fails the first step's LCP on the GPU
+    (its first step starts from the empty set, which is not the solution's
+    active set); with lcp_fail_steps = 1 the instance stops there with
+    SYS_LCP_NOT_CONVERGED.  The oracle (sign-of-b start, whose first step
+    happens to need one solve) stops with the same status a step later."""
+    P = gpu.ehl
+    o = OE.solve_line(20.0, 10.0, 129, lcp_max_iter=1, lcp_fail_steps=1)
+    r = P.solve_line([20.0, 20.0], [10.0, 10.0], 129,
+                     opts=P.default_opts(lcp_max_iter=1, lcp_fail_steps=1, steps_per_graph=1))
+    torch.cuda.synchronize()
+    assert o["status"] == 3 and o["iters"] <= 3
+    assert r["status"].cpu().tolist() == [3, 3]
+    assert r["iters"].cpu().tolist() == [1, 1]
+
+
 def test_newton_not_converged_status(gpu):
     P = gpu.ehl
     r = P.solve_line([20.0], [10.0], 257, opts=P.default_opts(max_newton=3, steps_per_graph=1))

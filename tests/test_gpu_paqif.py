@@ -116,10 +116,44 @@ def test_invalid_arguments(gpu):
     bt = P.paqif.Batch([0, 5], 3)  # q = 3 unsupported
     n = P.lib().paqif_workspace_bytes(P.paqif.handle(), ctypes.byref(bt.c), 0, 2)
     assert n == 0
-    with pytest.raises(RuntimeError):
-        P.paqif.solve_lcp(bt, torch.zeros(5 * 7, dtype=torch.float64, device="cuda"),
-                          torch.zeros(5, dtype=torch.float64, device="cuda"),
-                          workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    band = torch.zeros(5 * 7, dtype=torch.float64, device="cuda")
+    f = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    # the wrapper refuses it (its workspace query fails) ...
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, band, f, workspace=ws)
+    # ... and so does the C ABI itself, before any launch
+    u = torch.zeros(5, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vp = ctypes.c_void_p
+    code = P.lib().paqif_solve_lcp(P.paqif.handle(), ctypes.byref(bt.c), vp(band.data_ptr()),
+                                   vp(f.data_ptr()), None, 2, 0, 1e-10, 64, vp(u.data_ptr()),
+                                   None, None, vp(st.data_ptr()), None, vp(ws.data_ptr()), None)
+    assert code == P._binding.PAQIF_EINVAL
+
+
+def test_wrapper_refuses_short_buffers(gpu):
+    """The C ABI takes bare pointers; the binding checks every per-row
+    buffer and the workspace against the batch before calling it."""
+    P = gpu
+    offs, band, f = synth.lcp_batch(3, 2, seed=1, sizes=[10, 20, 30])
+    bt = P.paqif.Batch(offs, 2)
+    dev = torch.device("cuda")
+    band_d = torch.as_tensor(band, device=dev)
+    f_d = torch.as_tensor(f, device=dev)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, band_d[:-1], f_d)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, band_d, f_d[:-1])
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, band_d, f_d, bounded=torch.ones(59, dtype=torch.uint8, device=dev))
+    # an FP32+IR workspace is smaller than an FP64 one: refused for FP64
+    ws32 = bt.workspace(P.PREC_FP32_IR)
+    assert ws32.numel() < bt.workspace_bytes(P.PREC_FP64)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, band_d, f_d, prec=P.PREC_FP64, workspace=ws32)
+    with pytest.raises(ValueError):
+        P.paqif.factor(bt, band_d, factors=ws32)
 
 
 @pytest.mark.parametrize("q", [2, 4, 8])

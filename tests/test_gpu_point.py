@@ -127,6 +127,43 @@ def test_point_newton_kappa_scheme_matches_oracle(gpu):
     assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-9 * abs(o["Hmin"])
 
 
+def test_point_newton_fp32_refined_lcp_matches_oracle(gpu, oracle_33):
+    """lcp_prec = FP32 factors + FP64 refinement for every line LCP: the
+    same fixed point within the mixed-path target 1e-8."""
+    E = gpu.ehl
+    o = oracle_33
+    r = E.solve_point([20.0], [10.0], 33, 33,
+                      opts=E.default_opts(tol=1e-12, max_newton=1500, c_h0=0.02,
+                                          lcp_prec=E.B.PREC_FP32_IR))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    P = r["P"][0].cpu().numpy()
+    assert np.abs(P - o["P"]).max() <= 1e-8 * np.abs(o["P"]).max()
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-8 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-8 * abs(o["Hmin"])
+
+
+def test_point_forced_lcp_cap_status(gpu):
+    """Every line LCP of a colour pass reports its status; with an
+    active-set cap of one solve the first step's passes fail (the empty start
+    set is not the solution's) and, with lcp_fail_steps = 1, every instance
+    stops after that step with SYS_LCP_NOT_CONVERGED."""
+    E = gpu.ehl
+    r = E.solve_point([20.0, 50.0], [10.0, 10.0], 33, 33,
+                      opts=E.default_opts(c_h0=0.02, lcp_max_iter=1, lcp_fail_steps=1,
+                                          steps_per_graph=1))
+    torch.cuda.synchronize()
+    assert r["status"].cpu().tolist() == [3, 3]
+    assert r["iters"].cpu().tolist() == [1, 1]
+    # the default allows 16 consecutive failures: the same cap does not stop
+    # the iteration after one step
+    r = E.solve_point([20.0], [10.0], 33, 33,
+                      opts=E.default_opts(c_h0=0.02, lcp_max_iter=1, max_newton=4,
+                                          steps_per_graph=1))
+    torch.cuda.synchronize()
+    assert int(r["iters"][0]) == 4 and int(r["status"][0]) == 6
+
+
 def test_point_config5_properties(gpu):
     """257 x 257, M = 200, L = 10: properties of the GPU solution checked with
     the oracle's residual."""
