@@ -160,6 +160,34 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch *batch, const double 
 
 
 /*
+ * paqif_solve_lcp_noalloc -- paqif_solve_lcp for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as paqif_solve_lcp, without `workspace`: the level
+ * records, active flags and refinement residual live in a library-owned
+ * device array of PAQIF_NOALLOC_SCRATCH_BYTES per GPU, reserved when the
+ * library is loaded on that GPU and held until the process ends.  The call
+ * allocates nothing.  Its address on the device is taken (hipGetSymbolAddress)
+ * when paqif_create runs there; the handle's device must be the current one
+ * (else PAQIF_EINVAL).
+ * Size limit: with R = total_rows, C = count, K = (R + C)/2 + 1 records and
+ * a(x) = x rounded up to a multiple of 256,
+ *   FP64:     a(K * (4q+6) * 8) + a(R)                    bytes
+ *   FP32_IR:  a(K * (8q+6) * 4) + a(R) + a(8 R)           bytes
+ * must not exceed PAQIF_NOALLOC_SCRATCH_BYTES, else PAQIF_EWORKSPACE (host
+ * check, nothing launched).  Every call on one GPU shares that GPU's array
+ * (its contents are those of the last call; nothing in it needs clearing),
+ * so calls that overlap on one GPU -- on different streams or from
+ * different threads -- race: serialise them.
+ */
+#define PAQIF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const double *band,
+                            const double *b, const uint8_t *bounded, int mode, int prec,
+                            double refine_tol, int max_iter, double *u, double *w,
+                            uint8_t *active_out, int32_t *sys_status, int32_t *sys_iters,
+                            void *stream);
+
+/*
  * Lane layouts of the PAQIF LCP kernel (how many frontier elements a lane
  * owns and how many systems share a wavefront; see the library source).
  * paqif_layout_count(q): number of layouts for half-bandwidth q (0 if q is

@@ -77,6 +77,8 @@ def lib():
         "paqif_solve_factored": ([vp, bp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_solve_lcp": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                              vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "paqif_solve_lcp_noalloc": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d,
+                                     ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_layout_count": ([ctypes.c_int], ctypes.c_int),
         "paqif_set_layout": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "paqif_get_layout": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),

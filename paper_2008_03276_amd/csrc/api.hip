@@ -1,4 +1,5 @@
 // C ABI of the library: argument validation, workspace layout, launches.
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -39,6 +40,76 @@ static LcpLayout lcp_layout(const paqif_batch* b, int prec)
     return L;
 }
 
+// Scratch of paqif_solve_lcp_noalloc: one array per GPU, held until the
+// process ends.  Host code never uses the array's name as a device address:
+// its address on each device comes from hipGetSymbolAddress (taken once per
+// device, with that device current, when a handle is created there).
+static __device__ __align__(256) unsigned char scratch[PAQIF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Address of `scratch` on the current device `dev` (nullptr on failure).
+void* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Tight workspace of one LCP solve: level records at the stride the LCP
+// kernel uses (FP64: Z0 part only; FP32 + refinement: with W0), active
+// flags, refinement residual.
+LcpLayout lcp_layout_tight(const paqif_batch* b, int prec)
+{
+    LcpLayout L;
+    const bool mixed = prec == PREC_FP32_IR;
+    const size_t elt = mixed ? sizeof(float) : sizeof(double);
+    L.rec_bytes = align256(n_records(b) * (size_t)pq::record_stride(b->q, mixed) * elt);
+    L.act_off = L.rec_bytes;
+    L.r_off = L.act_off + align256((size_t)b->total_rows);
+    L.total = L.r_off + (mixed ? align256((size_t)b->total_rows * sizeof(double)) : 0);
+    return L;
+}
+}  // namespace
+
+static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const double* band,
+                      const double* b, const uint8_t* bounded, int mode, int prec,
+                      double refine_tol, int max_iter, double* u, double* w,
+                      uint8_t* active_out, int32_t* sys_status, int32_t* sys_iters, char* ws,
+                      const LcpLayout& L, void* stream)
+{
+    pq::LcpArgs a;
+    a.count = batch->count;
+    a.offsets = batch->offsets;
+    a.order = batch->order;
+    a.band = band;
+    a.b = b;
+    a.bounded = bounded;
+    a.mode = mode;
+    a.max_iter = max_iter;
+    a.refine_tol = refine_tol;
+    a.u = u;
+    a.w = w;
+    a.active_out = active_out;
+    a.status = sys_status;
+    a.iters = sys_iters;
+    a.rec = ws;
+    a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
+    a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
+    a.skip = nullptr;
+    a.warm = 0;
+    return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
+                            (hipStream_t)stream);
+}
+
 extern "C" {
 
 int paqif_create(paqif_handle* handle)
@@ -58,6 +129,11 @@ int paqif_create(paqif_handle* handle)
         h->cu_count = 0;
     for (int qi = 0; qi < 3; qi++)
         for (int p = 0; p < 2; p++) h->layout[qi][p] = 0;
+    h->scratch = scratch_address(h->device);
+    if (!h->scratch) {
+        delete h;
+        return PAQIF_EHIP;
+    }
     *handle = h;
     return PAQIF_OK;
 }
@@ -142,29 +218,34 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double*
     if (mode == LCP_EXACT && max_iter < 1) return PAQIF_EINVAL;
     if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
     const LcpLayout L = lcp_layout(batch, prec);
-    char* ws = static_cast<char*>(workspace);
-    pq::LcpArgs a;
-    a.count = batch->count;
-    a.offsets = batch->offsets;
-    a.order = batch->order;
-    a.band = band;
-    a.b = b;
-    a.bounded = bounded;
-    a.mode = mode;
-    a.max_iter = max_iter;
-    a.refine_tol = refine_tol;
-    a.u = u;
-    a.w = w;
-    a.active_out = active_out;
-    a.status = sys_status;
-    a.iters = sys_iters;
-    a.rec = ws;
-    a.act = reinterpret_cast<uint8_t*>(ws + L.act_off);
-    a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
-    a.skip = nullptr;
-    a.warm = 0;
-    return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
-                            (hipStream_t)stream);
+    return launch_lcp(handle, batch, band, b, bounded, mode, prec, refine_tol, max_iter, u, w,
+                      active_out, sys_status, sys_iters, static_cast<char*>(workspace), L,
+                      stream);
+}
+
+int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch* batch, const double* band,
+                            const double* b, const uint8_t* bounded, int mode, int prec,
+                            double refine_tol, int max_iter, double* u, double* w,
+                            uint8_t* active_out, int32_t* sys_status, int32_t* sys_iters,
+                            void* stream)
+{
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if (batch->count == 0) return PAQIF_OK;
+    if (!band || !b || !u || !sys_status) return PAQIF_EINVAL;
+    if (mode == LCP_EXACT && max_iter < 1) return PAQIF_EINVAL;
+    if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PAQIF_EHIP;
+    if (dev != handle->device || !handle->scratch) return PAQIF_EINVAL;
+    const LcpLayout L = lcp_layout_tight(batch, prec);
+    if (L.total > (size_t)PAQIF_NOALLOC_SCRATCH_BYTES) return PAQIF_EWORKSPACE;
+    // every byte of the scratch that the kernel reads it wrote first in the
+    // same launch (records, flags, residual): nothing needs clearing
+    return launch_lcp(handle, batch, band, b, bounded, mode, prec, refine_tol, max_iter, u, w,
+                      active_out, sys_status, sys_iters, static_cast<char*>(handle->scratch), L,
+                      stream);
 }
 
 int paqif_layout_count(int q) { return pq::layouts_for(q); }

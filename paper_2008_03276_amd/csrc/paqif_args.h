@@ -10,6 +10,9 @@ struct paqif_handle_s {
     int device;
     int cu_count;
     int layout[3][2];
+    // device address of the library-owned scratch array on `device` (the
+    // allocation-free LCP entry point), from hipGetSymbolAddress
+    void* scratch;
 };
 
 

@@ -122,6 +122,35 @@ def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
     return dict(u=u, w=w, active=act, status=st, iters=it)
 
 
+def solve_lcp_noalloc(batch, band, b, u, status, mode=B.LCP_EXACT, prec=B.PREC_FP64,
+                      bounded=None, refine_tol=1e-10, max_iter=64, w=None, active=None,
+                      iters=None):
+    """The allocation-free entry point: same solve as ``solve_lcp``, its
+    scratch in the library's own device array; the caller passes every
+    output (``u``, ``status`` and optionally ``w``, ``active``, ``iters``),
+    so nothing is allocated here either.  Returns the call status code
+    (PAQIF_EWORKSPACE when the batch exceeds the library's scratch)."""
+    _check_system_args(batch, band, b, bounded)
+    rows = batch.total_rows
+    _need(u, torch.float64, "u")
+    _need_len(u, rows, "u")
+    _need(status, torch.int32, "status")
+    _need_len(status, batch.count, "status")
+    if w is not None:
+        _need(w, torch.float64, "w")
+        _need_len(w, rows, "w")
+    if active is not None:
+        _need(active, torch.uint8, "active")
+        _need_len(active, rows, "active")
+    if iters is not None:
+        _need(iters, torch.int32, "iters")
+        _need_len(iters, batch.count, "iters")
+    return B.lib().paqif_solve_lcp_noalloc(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
+                                           _ptr(bounded), mode, prec, refine_tol, max_iter,
+                                           _ptr(u), _ptr(w), _ptr(active), _ptr(status),
+                                           _ptr(iters), _stream())
+
+
 def factor(batch, band, pinned=None, factors=None):
     """A = W0 Z0 for every system; returns (factors, status)."""
     _check_system_args(batch, band, bounded=pinned)
