@@ -204,9 +204,9 @@ def test_newton_stops_when_the_lcp_keeps_hitting_its_cap(monkeypatch):
     real = E.lcp_exact
     calls = {"n": 0}
 
-    def capped(A, b, bnd):
+    def capped(A, b, bnd, max_iter=64):
         calls["n"] += 1
-        u, _ = real(A, b, bnd)
+        u, _ = real(A, b, bnd, max_iter)
         # one converged step in the middle resets the consecutive count
         return u, (0 if calls["n"] == 5 else E.LCP_NOT_CONVERGED)
 
