@@ -191,9 +191,14 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * Lane layouts of the PAQIF LCP kernel (how many frontier elements a lane
  * owns and how many systems share a wavefront; see the library source).
  * paqif_layout_count(q): number of layouts for half-bandwidth q (0 if q is
- * unsupported).  paqif_set_layout / paqif_get_layout: the layout used by
- * paqif_solve_lcp (and the EHL Newton driver) for (q, prec) on this handle;
- * PAQIF_EINVAL for an unknown q, prec or layout.
+ * unsupported).  Layouts 0-2 spread each system's frontier over the lanes of
+ * a wavefront (q = 2 layout 2: one system per lane); layout 3 gives each
+ * system a group of 16 lanes, one frontier row per lane, with pivot rows
+ * broadcast by DPP (FP64 only; with PREC_FP32_IR it runs layout 0).  A new
+ * handle uses layout 3 for PREC_FP64 and layout 0 for PREC_FP32_IR.
+ * paqif_set_layout / paqif_get_layout: the layout used by paqif_solve_lcp
+ * (and the EHL Newton drivers) for (q, prec) on this handle; PAQIF_EINVAL for
+ * an unknown q, prec or layout.
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),
  * stores the fastest in the handle and, if times_ms (host, float[count]) is

@@ -122,13 +122,15 @@ int paqif_create(paqif_handle* handle)
         return PAQIF_EHIP;
     }
     h->cu_count = 0;
-    for (int qi = 0; qi < 3; qi++)
-        for (int p = 0; p < 2; p++) h->layout[qi][p] = 0;
     if (hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) !=
         hipSuccess)
         h->cu_count = 0;
-    for (int qi = 0; qi < 3; qi++)
-        for (int p = 0; p < 2; p++) h->layout[qi][p] = 0;
+    // FP64 solves default to the row layout (one system per lane group of
+    // 16 rows), FP32 solves with refinement to the lane-per-system layout.
+    for (int qi = 0; qi < 3; qi++) {
+        h->layout[qi][PREC_FP64] = 3;
+        h->layout[qi][PREC_FP32_IR] = 0;
+    }
     h->scratch = scratch_address(h->device);
     if (!h->scratch) {
         delete h;

@@ -43,6 +43,9 @@
 // hold the solved outer unknowns of the frontier slots, each level forms two
 // dot products with a DPP butterfly, applies the stored inverse pivot and
 // drops the two new unknowns into slots j and q+j.
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 #include "paqif_args.h"
 
@@ -57,7 +60,9 @@ namespace pq {
 //   q=8: L0 2x2 (64 lanes, 1 per wave)          L1 2x4 (32 lanes, 2 per wave)
 //        L2 1x4 (64 lanes, 1 per wave)
 // q = 2: layout 2 is one system per lane (its own kernel below)
-constexpr int layout_count(int q) { return 3; }
+// layout 3 (FP64): one system per 16-lane row, a frontier row per lane, the
+// pivot rows broadcast by DPP (paqif_lcp_rows_kernel below)
+constexpr int layout_count(int q) { return 4; }
 
 template <int Q, int L>
 struct Geo {
@@ -116,6 +121,14 @@ struct SysView {
 // array length).  Indices stay below 2q+1 <= 17.
 __device__ const double kZeroBand[32] = {};
 __device__ const uint8_t kZeroFlags[32] = {};
+__device__ const uint8_t kOneFlags[32] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                          1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+// Target of the stores of lanes that have nothing to store, so that store
+// instructions need no branch (its contents are never read).
+__device__ double kSink[128];
+
+// Two doubles moved as one 16-byte access.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 PQ_DEV SysView make_view(int64_t off, int64_t n, const double* band, const uint8_t* pin,
                          const double* rhs, int bw, int64_t boff)
@@ -808,13 +821,12 @@ PQ_DEV LDS_PTR(T) as_lds(T* p)
 
 // Residual pass over one system: w = A u - b with the original band.
 // Returns (in *changes) the number of active-set changes for LCP_EXACT.
-template <int Q, int L>
+template <int Q, int LPS>
 PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off, int ls,
                             bool update, bool write_w, int& changes, int& nonfinite)
 {
     ls = launder(ls);
-    using G = Geo<Q, L>;
-    constexpr int BW = G::BW;
+    constexpr int BW = 2 * Q + 1;
     GLB_PTR(const double) u = GLB(const double, A.u + off);
     GLB_PTR(const double) bb = GLB(const double, A.b + off);
     GLB_PTR(const double) band = v.band;
@@ -830,22 +842,22 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
         // finiteness check of u
         constexpr int RU = 8;
         const int nm = v.n - 1;
-        for (int i0 = ls; i0 < v.n; i0 += RU * G::LPS) {
+        for (int i0 = ls; i0 < v.n; i0 += RU * LPS) {
             double uv[RU];
 #pragma unroll
-            for (int r = 0; r < RU; r++) uv[r] = u[min(i0 + r * G::LPS, nm)];
+            for (int r = 0; r < RU; r++) uv[r] = u[min(i0 + r * LPS, nm)];
 #pragma unroll
             for (int r = 0; r < RU; r++)
-                if (i0 + r * G::LPS < v.n && !isfinite(uv[r])) nf = 1;
+                if (i0 + r * LPS < v.n && !isfinite(uv[r])) nf = 1;
         }
     } else if (live) {
         const int nm = v.n - 1;
-        for (int i0 = ls; i0 < v.n; i0 += R * G::LPS) {
+        for (int i0 = ls; i0 < v.n; i0 += R * LPS) {
             double av[R][BW], uv[R][BW], bv[R];
             uint32_t cv[R], kv[R];
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int i = min(i0 + r * G::LPS, nm);
+                const int i = min(i0 + r * LPS, nm);
 #pragma unroll
                 for (int d = 0; d < BW; d++) {
                     av[r][d] = band[(int64_t)i * BW + d];
@@ -857,7 +869,7 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
             }
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int i = i0 + r * G::LPS;
+                const int i = i0 + r * LPS;
                 if (i < v.n) {
                     double s = 0.0;
 #pragma unroll
@@ -880,8 +892,8 @@ PQ_DEV void residual_update(SysView v, bool live, const LcpArgs& A, int64_t off,
             }
         }
     }
-    changes = group_sum_int<G::LPS>(ch);
-    nonfinite = group_max_int<G::LPS>(nf);
+    changes = group_sum_int<LPS>(ch);
+    nonfinite = group_max_int<LPS>(nf);
 }
 
 // Effective residual r = b_eff - A_eff u on one system (for refinement);
@@ -1079,7 +1091,7 @@ __global__ void __launch_bounds__(64)
             }
         }
         __syncthreads();
-        residual_update<Q, L>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
+        residual_update<Q, G::LPS>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
         __syncthreads();
         if (live && !done) {
             if (nonfinite) {
@@ -1489,6 +1501,698 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
 }
 
 // --------------------------------------------------------------------------
+// Row layout (lane layout 3, FP64): one system per 16-lane row of the
+// wavefront, frontier row slot a held whole by lane a (a < 2q; the lanes
+// beyond 2q of a row idle), four systems per wave.  A level needs, in every
+// lane, the two pivot rows; they are taken straight from the pivot lanes'
+// registers by the DPP row broadcast of gfx950 (row_newbcast), fused into
+// the FMAs of the rank-2 update (v_fmac_f64 with a broadcast operand), so a
+// level has no LDS round trip and no cross-lane reduction.
+//
+// Pinned rows (the working active set) are replaced by rows of the identity
+// only, not columns: with u_i = 0 forced by its row, the pinned column
+// multiplies zero, so the solution is the same as with rows and columns
+// replaced, and each entering band row needs only its own flag.
+//
+// Refill.  Lane a (side L = a < q, phase c = a mod q) is the pivot of the
+// levels with j = c; at such a level its row leaves (it is published as the
+// record's Z0 row) and the lane takes the new band row g (g1 or g2).  The
+// new row is written once, pins applied, into a per-lane LDS buffer (double
+// buffered by block parity) and read back in slot order at lane-constant
+// offsets (the rotation by c cannot be a register index).  The columns j,
+// q+j take at level j the entry of the lane's own row in the entering
+// column, index q -+ d of its band row, d = (j - c) mod q, also read from
+// the buffer.  Every band row is loaded once per factorisation.
+//
+// The back solve keeps the 2q outer unknowns in every lane of the row
+// (compile-time slots) and forms the two Z0 dot products by broadcast FMAs
+// from the lanes holding the record entries.
+// --------------------------------------------------------------------------
+namespace rows {
+
+constexpr int LPS = 16;  // lanes per system (one DPP row)
+constexpr int SPW = 4;   // systems per wave
+
+template <int Q>
+struct RG {
+    static constexpr int N2 = 2 * Q;
+    static constexpr int BW = 2 * Q + 1;
+    static constexpr int ZR = 4 * Q + 6;  // record: Z0 rows, inverse pivot, forward values
+    static constexpr int S = Q == 2 ? 4 : (Q == 4 ? 2 : 1);  // blocks of q levels per superblock
+    static constexpr int SB = S * Q;                          // levels per superblock (8)
+    static constexpr int RB = 2 * Q + 2;  // LDS refill buffer: effective band row + a zero
+    static constexpr int BSB = 8;         // back-solve levels per prefetch superblock
+};
+
+// Calls f(std::integral_constant<int, I>) for I = 0 .. N-1 (compile-time
+// indices for the DPP lane selects and register slots).
+template <typename F, int... I>
+PQ_DEV void static_for_impl(F&& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+PQ_DEV void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Value of lane N of this lane's 16-lane row (DPP row_newbcast, one v_mov_b64).
+template <int N>
+PQ_DEV double bcast(double v)
+{
+    return __longlong_as_double(
+        __builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + N, 0xF, 0xF, false));
+}
+
+// acc += (value of src in lane N of the row) * mul, one v_fmac_f64 with a
+// DPP row-broadcast source.  A DPP read needs two wait states after a VALU
+// write of its source, which the compiler does not add in front of inline
+// asm: the first broadcast FMA of a sequence takes an s_nop 1 (NOP), the
+// others read sources that no instruction of the sequence writes.
+template <int N, bool NOP = false>
+PQ_DEV void fmac_bcast(double& acc, double src, double mul)
+{
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(src), "v"(mul), "n"(N));
+    else
+        asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(src), "v"(mul), "n"(N));
+}
+
+// Effective entry with pinned rows only replaced by the identity.
+template <int Q>
+PQ_DEV double arow(const SysView& v, int i, int j)
+{
+    if (i < 0 || j < 0 || i >= v.n || j >= v.n) return 0.0;
+    const int d = j - i;
+    if (d < -Q || d > Q) return 0.0;
+    if (v.pin && v.pin[i]) return i == j ? 1.0 : 0.0;
+    return v.band[(int64_t)i * (2 * Q + 1) + (d + Q)];
+}
+
+// Factorisation with the fused forward solve; writes one record per level
+// (odd n: the centre record first).  lbuf: this lane's 2 refill buffers.
+// Returns true if a pivot of a live level was singular / non-finite.
+template <int Q>
+PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(double) lbuf,
+                   LDS_PTR(double) lrec, LDS_PTR(double) ldum, int a, int kmax)
+{
+    using G = RG<Q>;
+    constexpr int N2 = G::N2, BW = G::BW, ZR = G::ZR, S = G::S, SB = G::SB, RB = G::RB;
+    a = launder(a);
+    const bool slot = a < N2;
+    const bool left = a < Q;
+    const int c = a & (Q - 1);
+    const double lmask = (slot && left) ? 1.0 : 0.0, rmask = (slot && !left) ? 1.0 : 0.0;
+    GLB_PTR(const double) rhs = v.rhs;
+    bool bad = false;
+
+    // ---- initial frontier (after the centre 1x1 level for odd n) ---------
+    double f[N2], y;
+    const int ia = slot ? (left ? v.P1_0 - a : v.P2_0 + (a - Q)) : -1;
+    auto bef = [&](int i) {
+        if (i < 0 || i >= v.n) return 0.0;
+        if (v.pin && v.pin[i]) return 0.0;
+        return rhs[i];
+    };
+    if (v.odd) {
+        const int m = v.npair;
+        const double amm = live ? arow<Q>(v, m, m) : 1.0;
+        if (live && !(amm != 0.0 && isfinite(amm))) bad = true;
+        const double ramm = 1.0 / amm;
+        const double bm = live ? bef(m) : 0.0;
+        const double aim = arow<Q>(v, ia, m) * ramm;
+#pragma unroll
+        for (int cc = 0; cc < N2; cc++) {
+            const int ib = cc < Q ? v.P1_0 - cc : v.P2_0 + (cc - Q);
+            f[cc] = arow<Q>(v, ia, ib) - aim * arow<Q>(v, m, ib);
+        }
+        y = bef(ia) - aim * bm;
+        if (live) {  // centre record: Z0 row m over the slots, 1x1 pivot
+            if (slot) {
+                rec[a] = arow<Q>(v, m, ia);
+                rec[N2 + a] = 0.0;
+            }
+            if (a == 0) {
+                rec[4 * Q + 0] = ramm;
+                rec[4 * Q + 1] = 0.0;
+                rec[4 * Q + 2] = 0.0;
+                rec[4 * Q + 3] = 0.0;
+                rec[4 * Q + 4] = bm;
+                rec[4 * Q + 5] = 0.0;
+            }
+        }
+        rec += ZR;
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < N2; cc++) {
+            const int ib = cc < Q ? v.P1_0 - cc : v.P2_0 + (cc - Q);
+            f[cc] = arow<Q>(v, ia, ib);
+        }
+        y = bef(ia);
+    }
+    // refill buffers: block r's row goes to buffer r mod (S+1), so the rows
+    // of the S blocks of a superblock and the row before them coexist; the
+    // lane's initial row is block -1's (buffer S)
+    double epub;  // the row's coupling to the column entering when it is the pivot
+    {
+        LDS_PTR(double) b0 = lbuf + S * RB;
+#pragma unroll
+        for (int t = 0; t < BW; t++) b0[t] = arow<Q>(v, ia, ia - Q + t);
+        b0[BW] = 0.0;
+        epub = arow<Q>(v, ia, left ? ia - Q : ia + Q);
+    }
+
+    // lane-constant LDS offsets of the refilled row in slot order (the
+    // own-side slots except the lane's own, whose value enters as the
+    // column entry; every other slot reads the zero at index 2q+1)
+    int nro[N2];
+#pragma unroll
+    for (int cc = 0; cc < N2; cc++) {
+        int t = G::BW;  // zero
+        if (slot && left && cc < Q && cc != c) t = 2 * Q - 1 - ((cc - c - 1 + Q) & (Q - 1));
+        if (slot && !left && cc >= Q && cc != Q + c) t = 1 + ((cc - Q - c - 1 + Q) & (Q - 1));
+        nro[cc] = t;
+    }
+
+    // ---- prefetch of the refill rows: block s of a superblock refills this
+    // lane at level kb + s q + c + 1 with row g; raw loads from clamped
+    // addresses, one superblock ahead ------------------------------------------
+    const int nm = v.n > 0 ? v.n - 1 : 0;
+    // flags read unconditionally (a zero array stands in for "no pins"): a
+    // load behind a branch is waited for at once
+    const bool haspin = v.pin != nullptr;
+    GLB_PTR(const uint8_t) pinp = haspin ? v.pin : GLB(const uint8_t, kZeroFlags);
+    double rband[S][BW], rb[S];
+    uint32_t rpin[S];
+    bool rval[S];
+    auto load_super = [&](int kn) {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const int t = kn + s * Q + c;  // refill level - 1
+            const int g = left ? v.P1_0 - t - Q : v.P2_0 + t + Q;
+            rval[s] = slot && live && (t + 1 <= v.npair) && g >= 0 && g < v.n;
+            const int gc = min(max(g, 0), nm);
+#pragma unroll
+            for (int u = 0; u < BW; u++) rband[s][u] = v.band[(int64_t)gc * BW + u];
+            rb[s] = rhs[gc];
+            rpin[s] = (uint32_t)pinp[haspin ? gc : 0];
+        }
+    };
+    load_super(0);
+
+    // records are staged in LDS (lrec: SB x ZR per system) by the pivot
+    // lanes and copied out at the end of the superblock by all lanes of the
+    // row in full 16-byte stores: all LDS reads first, then (after the
+    // refill preparation, whose LDS wait covers them) all stores.  No store
+    // or LDS write sits behind a branch (lanes with nothing to write aim at
+    // ldum / kSink), so every wait count is exact.
+    constexpr int NPAIR = SB * ZR / 2;
+    constexpr int NST = (NPAIR + LPS - 1) / LPS;  // copy pairs per lane per superblock
+    GLB_PTR(double) sink = GLB(double, kSink) + 2 * (threadIdx.x & 63);
+    LDS_PTR(double) dum = ldum + 2 * (threadIdx.x & 63);
+    const int xp = a % 3;  // extras pair written by lanes 0..2: (i11,i12), (i21,i22), (y1,y2)
+    LDS_PTR(double) stg = lrec;
+
+    // ---- refill rows of the superblock at level kn+1 (raw loads in rband):
+    // pins and range applied, into the LDS refill buffers; the rows in slot
+    // order (nr) and the lane's entries in the entering columns (cvl) read
+    // back.  Called before the level loop and at the end of each superblock,
+    // after the record stores, so that its wait for the raw loads does not
+    // also wait for those stores.
+    double nr[S][N2], ybs[S], eps[S], wjs[S], wqs[S], cvl[S][Q];
+    auto prepare = [&](int kn) {
+        const int bbase = (kn / Q) % (S + 1);  // buffer of block 0 of the superblock
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const bool ok = rval[s];
+            const double keep = (ok && rpin[s] == 0u) ? 1.0 : 0.0;
+            const double one = (ok && rpin[s] != 0u) ? 1.0 : 0.0;
+            int bi = bbase + s;
+            bi = bi > S ? bi - (S + 1) : bi;
+            LDS_PTR(double) buf = lbuf + bi * RB;
+            double e[BW];
+#pragma unroll
+            for (int u = 0; u < BW; u++) e[u] = rband[s][u] * keep;
+            e[Q] += one;
+#pragma unroll
+            for (int u = 0; u < BW; u++) buf[u] = e[u];
+            buf[BW] = 0.0;
+            ybs[s] = rb[s] * keep;
+            eps[s] = left ? e[0] : e[2 * Q];
+            wjs[s] = left ? e[2 * Q] : 0.0;
+            wqs[s] = left ? 0.0 : e[0];
+        }
+        wave_sync();
+        // the lane's entries in the columns entering its side, level by level:
+        // level j of block s reads the row it holds then (the previous
+        // block's before its refill at j = c, the block's own from there on),
+        // index q -+ d, d = (j - c) mod q
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            int bi = bbase + s;
+            bi = bi > S ? bi - (S + 1) : bi;
+            const int pbi = bi == 0 ? S : bi - 1;
+            LDS_PTR(double) buf = lbuf + bi * RB;
+#pragma unroll
+            for (int cc = 0; cc < N2; cc++) nr[s][cc] = buf[nro[cc]];
+#pragma unroll
+            for (int j = 0; j < Q; j++) {
+                const int d = (j - c + Q) & (Q - 1);
+                const int bsel = (j < c) ? pbi : bi;
+                cvl[s][j] = lbuf[bsel * RB + (left ? Q - d : Q + d)];
+            }
+        }
+        // every LDS read of the superblock is done here (lgkmcnt 0), so the
+        // level loop, whose only LDS accesses are the record writes, never
+        // waits on LDS
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+    };
+    prepare(0);
+
+    for (int kb = 0; kb < kmax; kb += SB) {
+        load_super(kb + SB);
+
+        static_for<S>([&](auto SS) {
+            constexpr int s = decltype(SS)::value;
+            static_for<Q>([&](auto JJ) {
+                constexpr int j = decltype(JJ)::value;
+                const int k = kb + s * Q + j + 1;
+                const bool act = live && k <= v.npair;
+                const bool isref = slot && c == j;
+                const double cv = cvl[s][j];  // entry of the lane's row in the entering column
+                // pivot data from lanes j and q+j
+                const double P11 = bcast<j>(f[j]), P12 = bcast<j>(f[Q + j]);
+                const double P21 = bcast<Q + j>(f[j]), P22 = bcast<Q + j>(f[Q + j]);
+                const double y1 = bcast<j>(y), y2 = bcast<Q + j>(y);
+                const double E0 = bcast<j>(epub), E2 = bcast<Q + j>(epub);
+                const double det = P11 * P22 - P12 * P21;
+                if (act && !(det != 0.0 && isfinite(det))) bad = true;
+                // 1/det: hardware reciprocal refined by two Newton steps
+                const double r0 = __builtin_amdgcn_rcp(det);
+                const double r1 = __builtin_fma(r0, __builtin_fma(-det, r0, 1.0), r0);
+                const double rd = __builtin_fma(r1, __builtin_fma(-det, r1, 1.0), r1);
+                const double i11 = P22 * rd, i12 = -P12 * rd, i21 = -P21 * rd, i22 = P11 * rd;
+                // multipliers of this lane's row (the refilled lane: of its new row)
+                const double wj = isref ? wjs[s] : f[j];
+                const double wq = isref ? wqs[s] : f[Q + j];
+                const double n1 = -(wj * i11 + wq * i21);
+                const double n2 = -(wj * i12 + wq * i22);
+                // rank-2 update into g (base: own row, or the refilled row); the
+                // next level's pivot columns first, so that its pivot block can be
+                // formed while the other columns are updated
+                double g[N2];
+                constexpr int jn = (j + 1) & (Q - 1);
+                static_for<N2>([&](auto CC) {
+                    constexpr int t = decltype(CC)::value;
+                    constexpr int cc = t == 0 ? jn : (t == 1 ? Q + jn : (t - 2 < jn ? t - 2 : (t - 2 < Q + jn - 1 ? t - 1 : t)));
+                    if constexpr (cc != j && cc != Q + j) {
+                        g[cc] = isref ? nr[s][cc] : f[cc];
+                        fmac_bcast<j, t == 0>(g[cc], f[cc], n1);
+                        fmac_bcast<Q + j>(g[cc], f[cc], n2);
+                    }
+                });
+                g[j] = __builtin_fma(E0, n1, cv * lmask);
+                g[Q + j] = __builtin_fma(E2, n2, cv * rmask);
+                // record (staged): the pivot lanes write their rows (Z0 rows p1,
+                // p2 over the slots after the level), lanes 0..2 of the row one
+                // pair each of the inverse and y
+                {
+                    constexpr int jj = s * Q + j;
+                    LDS_PTR(double) zr = stg + jj * ZR + (left ? 0 : N2);
+#pragma unroll
+                    for (int t = 0; t < Q; t++) {
+                        dbl2 zv;
+                        zv.x = f[2 * t];
+                        zv.y = f[2 * t + 1];
+                        if (2 * t == j) zv.x = epub * lmask;
+                        if (2 * t + 1 == j) zv.y = epub * lmask;
+                        if (2 * t == Q + j) zv.x = epub * rmask;
+                        if (2 * t + 1 == Q + j) zv.y = epub * rmask;
+                        *reinterpret_cast<LDS_PTR(dbl2)>(isref ? zr + 2 * t : dum) = zv;
+                    }
+                    dbl2 xv;
+                    xv.x = xp == 0 ? i11 : (xp == 1 ? i21 : y1);
+                    xv.y = xp == 0 ? i12 : (xp == 1 ? i22 : y2);
+                    *reinterpret_cast<LDS_PTR(dbl2)>(a < 3 ? stg + jj * ZR + 4 * Q + 2 * xp : dum) =
+                        xv;
+                }
+                double gy = isref ? ybs[s] : y;
+                gy = __builtin_fma(y1, n1, gy);
+                gy = __builtin_fma(y2, n2, gy);
+                epub = isref ? eps[s] : epub;
+#pragma unroll
+                for (int cc = 0; cc < N2; cc++) f[cc] = g[cc];
+                y = gy;
+            });
+        });
+        // the superblock's records: pair e of the staging area to rec + 2e
+        // if its level exists, else to the sink
+        dbl2 cp[NST];
+#pragma unroll
+        for (int r = 0; r < NST; r++) {
+            const int e = a + LPS * r;
+            cp[r] = *reinterpret_cast<LDS_PTR(const dbl2)>(stg + 2 * (e < NPAIR ? e : 0));
+        }
+        prepare(kb + SB);
+#pragma unroll
+        for (int r = 0; r < NST; r++) {
+            const int e = a + LPS * r;
+            const bool ok = e < NPAIR && live && kb + (2 * e) / ZR + 1 <= v.npair;
+            GLB_PTR(double) dst = ok ? rec + 2 * e : sink;
+            *reinterpret_cast<GLB_PTR(dbl2)>(dst) = cp[r];
+        }
+        rec += SB * ZR;
+    }
+    return bad;
+}
+
+// Back solve Z0 x = y from both ends inwards; x written to `x` (system
+// base).  Every lane of the row keeps the 2q outer unknowns xs (slots after
+// the level being solved); lane t < 2q holds the record's Z0 entries of
+// slot t, lanes 0..2 the pairs (i11, i12), (i21, i22), (y1, y2).
+template <int Q>
+PQ_DEV void back(const SysView& v, bool live, GLB_PTR(const double) rec0, GLB_PTR(double) x,
+                 int a, int kmax)
+{
+    using G = RG<Q>;
+    constexpr int N2 = G::N2, ZR = G::ZR, BSB = G::BSB;
+    a = launder(a);
+    const bool slot = a < N2;
+    const int zc = slot ? a : 0;
+    const int ep = 4 * Q + 2 * (a % 3);
+    GLB_PTR(const double) recp = rec0 + (v.odd ? ZR : 0);  // first 2x2 level
+    const int64_t lim = live ? (int64_t)v.npair : 0;       // valid records from recp
+    double xs[N2];
+#pragma unroll
+    for (int cc = 0; cc < N2; cc++) xs[cc] = 0.0;
+    double mine = 0.0;
+    double pz1[BSB], pz2[BSB], pe0[BSB], pe1[BSB];
+    const int rmax = lim > 0 ? (int)lim - 1 : 0;
+    GLB_PTR(double) sink = GLB(double, kSink) + 2 * (threadIdx.x & 63);
+    auto load_block = [&](int kb) {  // levels kb+1 .. kb+BSB (clamped records)
+#pragma unroll
+        for (int t = 0; t < BSB; t++) {
+            const int r = min(max(kb + t, 0), rmax);
+            GLB_PTR(const double) p = recp + (int64_t)r * ZR;
+            pz1[t] = p[zc];
+            pz2[t] = p[N2 + zc];
+            const dbl2 ex = *reinterpret_cast<GLB_PTR(const dbl2)>(p + ep);
+            pe0[t] = ex.x;
+            pe1[t] = ex.y;
+        }
+    };
+    const int kb_last = kmax > 0 ? ((kmax - 1) / BSB) * BSB : -BSB;
+    if (kb_last >= 0) load_block(kb_last);
+    // Software pipeline: of a level's two dot products only the terms of the
+    // two slots that the level solved just before changes (the "late" terms);
+    // the others (E: "early" sums, carried in registers) are formed while
+    // that previous level still finishes.  The first level sees xs = 0.
+    double e1a = 0.0, e1b = 0.0, e2a = 0.0, e2b = 0.0;
+    for (int kb = kb_last; kb >= 0; kb -= BSB) {
+        double z1[BSB], z2[BSB], e0[BSB], e1[BSB];
+#pragma unroll
+        for (int t = 0; t < BSB; t++) {
+            z1[t] = pz1[t];
+            z2[t] = pz2[t];
+            e0[t] = pe0[t];
+            e1[t] = pe1[t];
+        }
+        load_block(kb - BSB);  // unconditional (clamped): no branch, exact wait counts
+        static_for<BSB>([&](auto TT) {
+            constexpr int t = BSB - 1 - decltype(TT)::value;
+            constexpr int j = t & (Q - 1);  // kb is a multiple of BSB, a multiple of q
+            const int k = kb + t + 1;
+            const bool act = live && k <= v.npair;
+            constexpr int jp = (j + 1) & (Q - 1);  // slots of the previous level solved
+            // late terms of this level
+            fmac_bcast<jp, true>(e1a, z1[t], xs[jp]);
+            fmac_bcast<Q + jp>(e1b, z1[t], xs[Q + jp]);
+            fmac_bcast<jp>(e2a, z2[t], xs[jp]);
+            fmac_bcast<Q + jp>(e2b, z2[t], xs[Q + jp]);
+            // early sums of the next level in processing order (t - 1, or the
+            // next superblock's last level, still in the prefetch registers):
+            // every slot but the two this level solves
+            double zn1, zn2;
+            if constexpr (t > 0) {
+                zn1 = z1[t - 1];
+                zn2 = z2[t - 1];
+            } else {
+                zn1 = pz1[BSB - 1];
+                zn2 = pz2[BSB - 1];
+            }
+            double n1a = 0.0, n1b = 0.0, n2a = 0.0, n2b = 0.0;
+            static_for<N2>([&](auto CC) {
+                constexpr int cc = decltype(CC)::value;
+                constexpr int first = (j == 0) ? 1 : 0;  // first slot in the sequence
+                if constexpr (cc != j && cc != Q + j) {
+                    if constexpr (cc % 2 == 0) {
+                        fmac_bcast<cc, cc == first>(n1a, zn1, xs[cc]);
+                        fmac_bcast<cc>(n2a, zn2, xs[cc]);
+                    } else {
+                        fmac_bcast<cc, cc == first>(n1b, zn1, xs[cc]);
+                        fmac_bcast<cc>(n2b, zn2, xs[cc]);
+                    }
+                }
+            });
+            const double s1a = e1a, s1b = e1b, s2a = e2a, s2b = e2b;
+            e1a = n1a;
+            e1b = n1b;
+            e2a = n2a;
+            e2b = n2b;
+            const double i11 = bcast<0>(e0[t]), i12 = bcast<0>(e1[t]);
+            const double i21 = bcast<1>(e0[t]), i22 = bcast<1>(e1[t]);
+            const double y1 = bcast<2>(e0[t]), y2 = bcast<2>(e1[t]);
+            const double r1 = y1 - (s1a + s1b), r2 = y2 - (s2a + s2b);
+            const double x1 = i11 * r1 + i12 * r2;
+            const double x2 = i21 * r1 + i22 * r2;
+            xs[j] = act ? x1 : xs[j];
+            xs[Q + j] = act ? x2 : xs[Q + j];
+            if (act && slot && (a & (Q - 1)) == j) mine = a < Q ? x1 : x2;
+            if constexpr (j == 0) {
+                // block of q levels done: lane a (< 2q) holds the unknown of
+                // slot a, level kc = k + (a mod q)
+                const int kc = k + (a & (Q - 1));
+                const int gi = a < Q ? v.P1_0 - (kc - 1) : v.P2_0 + (kc - 1);
+                GLB_PTR(double) dst = (slot && live && kc <= v.npair) ? x + gi : sink;
+                *dst = mine;
+            }
+        });
+    }
+    if (v.odd && live) {
+        // centre: x_m = (y_m - Z0 row m . xs) / a_mm
+        const double zm = rec0[zc];
+        double sa = 0.0, sb = 0.0;
+        static_for<N2>([&](auto CC) {
+            constexpr int cc = decltype(CC)::value;
+            if constexpr (cc % 2 == 0)
+                fmac_bcast<cc, cc == 0>(sa, zm, xs[cc]);
+            else
+                fmac_bcast<cc>(sb, zm, xs[cc]);
+        });
+        if (a == 0) x[v.npair] = rec0[4 * Q] * (rec0[4 * Q + 4] - (sa + sb));
+    }
+}
+
+// Residual pass of the row layout: w = A u - b with the original band and
+// the active-set update, as residual_update, but each lane takes R
+// consecutive rows per pass, so its u window is R + 2q values and its band
+// rows one contiguous run; all loads of a pass (clamped addresses) are issued
+// before any is used.
+template <int Q>
+PQ_DEV void residual(const SysView& v, bool live, const LcpArgs& A, int64_t off, int ls,
+                     bool update, bool write_w, int& changes, int& nonfinite)
+{
+    ls = launder(ls);
+    constexpr int BW = 2 * Q + 1;
+    constexpr int R = Q == 8 ? 4 : (Q == 4 ? 8 : 16);
+    constexpr int UW = R + 2 * Q;
+    GLB_PTR(const double) u = GLB(const double, A.u + off);
+    GLB_PTR(const double) bb = GLB(const double, A.b + off);
+    GLB_PTR(const double) band = v.band;
+    GLB_PTR(double) wout = A.w ? GLB(double, A.w + off) : nullptr;
+    const bool hasb = A.bounded != nullptr;
+    GLB_PTR(const uint8_t) bnds =
+        hasb ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags);
+    GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
+    int ch = 0, nf = 0;
+    if (live) {
+        const int nm = v.n - 1;
+        for (int i0 = ls * R; i0 < v.n; i0 += R * LPS) {
+            double av[R][BW], uv[UW], bv[R];
+            uint32_t cv[R], kv[R];
+#pragma unroll
+            for (int t = 0; t < UW; t++) uv[t] = u[min(max(i0 - Q + t, 0), nm)];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int i = min(i0 + r, nm);
+#pragma unroll
+                for (int d = 0; d < BW; d++) av[r][d] = band[(int64_t)i * BW + d];
+                bv[r] = bb[i];
+                cv[r] = act[i];
+                kv[r] = (uint32_t)bnds[hasb ? i : 0];
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int i = i0 + r;
+                if (i < v.n) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int d = 0; d < BW; d++) {
+                        const int jcol = i + d - Q;
+                        sum = __builtin_fma(av[r][d], (jcol >= 0 && jcol < v.n) ? uv[r + d] : 0.0,
+                                            sum);
+                    }
+                    const double wi = sum - bv[r];
+                    const double ui = uv[r + Q];
+                    if (!isfinite(ui)) nf = 1;
+                    if (write_w && wout) wout[i] = wi;
+                    if (update) {
+                        const int bnd = kv[r] != 0u;
+                        const int cur = cv[r] != 0u;
+                        const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
+                        ch += (nxt != cur);
+                        act[i] = (uint8_t)nxt;
+                    }
+                }
+            }
+        }
+    }
+    changes = group_sum_int<LPS>(ch);
+    nonfinite = group_max_int<LPS>(nf);
+}
+
+}  // namespace rows
+
+template <int Q>
+struct RowLds {
+    // per lane: S+1 refill buffers; an odd lane stride (in doubles) spreads
+    // the 64-bit accesses of 16 lanes over distinct LDS bank pairs
+    double buf[64][(rows::RG<Q>::S + 1) * rows::RG<Q>::RB + 1];
+    alignas(16) double rec[rows::SPW][rows::RG<Q>::SB * rows::RG<Q>::ZR];  // staged records
+    alignas(16) double dum[64][2];  // per lane: discarded writes
+};
+
+// Whole LCP solve in the row layout (FP64), four systems per wave.
+template <int Q>
+__global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
+{
+    using G = rows::RG<Q>;
+    __shared__ RowLds<Q> lds;
+    const int lane = threadIdx.x;
+    const int grp = lane >> 4;
+    const int ls = lane & 15;
+    const int slot = blockIdx.x * rows::SPW + grp;
+    bool live = slot < A.count;
+    int sys = live ? (A.order ? A.order[slot] : slot) : 0;
+    if (live && A.skip && A.skip[sys]) live = false;
+    int64_t off = live ? A.offsets[sys] : 0;
+    int64_t n = live ? A.offsets[sys + 1] - off : 0;
+    int64_t boff = live && A.band_off ? A.band_off[sys] : off;
+    SysView v = make_view(off, n, A.band, A.act, A.b, G::BW, boff);
+    if (!live) {
+        v.n = 0;
+        v.npair = 0;
+    }
+    const int kmax = group_max_int<64>(v.npair);
+    GLB_PTR(double) rec = GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * G::ZR);
+    LDS_PTR(double) lbuf = as_lds(&lds.buf[lane][0]);
+
+    const bool exact = A.mode == LCP_EXACT;
+    const bool warm = exact && A.warm;
+    if (live) {
+        constexpr int R = 8;
+        const int nm = v.n - 1;
+        for (int i0 = ls; i0 < v.n; i0 += R * rows::LPS) {
+            uint32_t bn[R], pa[R];
+            double bv[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int64_t g = off + min(i0 + r * rows::LPS, nm);
+                bn[r] = A.bounded ? (uint32_t)A.bounded[g] : 1u;
+                pa[r] = warm ? (uint32_t)A.act[g] : 0u;
+                bv[r] = A.b[g];
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int i = i0 + r * rows::LPS;
+                const bool start = warm ? pa[r] != 0u : bv[r] <= 0.0;
+                if (i < v.n) A.act[off + i] = (exact && bn[r] != 0u && start) ? 1 : 0;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int max_it = exact ? max(A.max_iter, 1) : 1;
+    int st = SYS_OK;
+    int it = 0;
+    bool done = !live;
+    for (; it < max_it;) {
+        const bool bad = rows::factor<Q>(v, live && !done, rec, lbuf, as_lds(&lds.rec[grp][0]),
+                                         as_lds(&lds.dum[0][0]), ls, kmax);
+        __syncthreads();
+        rows::back<Q>(v, live && !done, rec, GLB(double, A.u + off), ls, kmax);
+        __syncthreads();
+        if (live && !done) it++;
+        const int badg = group_max_int<rows::LPS>(bad ? 1 : 0);
+        if (live && !done && badg) {
+            st = SYS_ZERO_PIVOT;
+            done = true;
+        }
+        int changes = 0, nonfinite = 0;
+        if (A.mode == LCP_CLIP && live && !done) {
+            for (int i = ls; i < v.n; i += rows::LPS) {
+                const int bnd = A.bounded ? (A.bounded[off + i] != 0) : 1;
+                const double ui = A.u[off + i];
+                if (bnd && ui < 0.0) {
+                    A.u[off + i] = 0.0;
+                    A.act[off + i] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        rows::residual<Q>(v, live && !done, A, off, ls, exact, true, changes, nonfinite);
+        __syncthreads();
+        if (live && !done) {
+            if (nonfinite) {
+                st = SYS_NONFINITE;
+                done = true;
+            } else if (!exact || changes == 0) {
+                done = true;
+            } else if (it >= max_it) {
+                st = SYS_LCP_NOT_CONVERGED;
+                done = true;
+            }
+        }
+        const int all_done = group_max_int<64>(done ? 0 : 1) == 0;
+        if (all_done) break;
+    }
+    if (live) {
+        if (A.active_out) {
+            constexpr int R = 8;
+            const int nm = v.n - 1;
+            for (int i0 = ls; i0 < v.n; i0 += R * rows::LPS) {
+                uint8_t fl[R];
+#pragma unroll
+                for (int r = 0; r < R; r++) fl[r] = A.act[off + min(i0 + r * rows::LPS, nm)];
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (i0 + r * rows::LPS < v.n) A.active_out[off + i0 + r * rows::LPS] = fl[r];
+            }
+        }
+        if (ls == 0) {
+            A.status[sys] = st;
+            if (A.iters) A.iters[sys] = it;
+        }
+    }
+}
+
+
+// --------------------------------------------------------------------------
 // Host launchers
 // --------------------------------------------------------------------------
 template <int Q, int L>
@@ -1506,6 +2210,14 @@ static int launch_lcp_l(const LcpArgs& a, int prec, hipStream_t s)
 template <int Q>
 static int launch_lcp(const LcpArgs& a, int prec, int layout, hipStream_t s)
 {
+    if (layout == 3) {
+        // row layout (FP64); the FP32 + refinement path keeps layout 0
+        if (prec == PREC_FP32_IR) return launch_lcp_l<Q, 0>(a, prec, s);
+        const int grid = (a.count + rows::SPW - 1) / rows::SPW;
+        if (grid == 0) return PAQIF_OK;
+        hipLaunchKernelGGL((paqif_lcp_rows_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+        return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+    }
     switch (layout) {
     case 1: return launch_lcp_l<Q, 1>(a, prec, s);
     case 2:

@@ -229,29 +229,31 @@ def test_autotune_picks_a_layout(gpu):
     assert times[chosen] == min(times)
 
 
-@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("q", [2, 4, 8])
+@pytest.mark.parametrize("layout", [0, 1, 2, 3])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_q2_layouts_modes_bounded_and_edges(gpu, layout, mode):
-    """Every q = 2 layout (layout 2: one system per lane) in every mode, with a
-    bounded mask, empty and one-row systems and a singular system."""
+def test_layouts_modes_bounded_and_edges(gpu, q, layout, mode):
+    """Every lane layout (q = 2 layout 2: one system per lane; layout 3: one
+    system per 16-lane row group) in every mode, with a bounded mask, empty and
+    one-row systems and a singular system."""
     P = gpu
     dev = torch.device("cuda")
-    sizes = [0, 1, 7, 0, 64, 301, 3, 1000, 2]
-    offs, band, f = synth.lcp_batch(len(sizes), 2, seed=33, sizes=sizes)
+    sizes = [0, 1, 7, 0, 64, 301, 3, 1000, 2, 17, 33]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=33 + q, sizes=sizes)
     rng = np.random.default_rng(5)
     bounded = (rng.random(len(f)) < 0.8).astype(np.uint8)
     sing = int(offs[6])  # the 3-row system: zero its centre row
     band[sing + 1, :] = 0.0
-    o = oracle.lcp_batch(2, offs, band, f, mode=mode, bounded=bounded)
-    bt = P.paqif.Batch(offs, 2, order="lpt")
-    keep = P.paqif.get_layout(2, 0)
+    o = oracle.lcp_batch(q, offs, band, f, mode=mode, bounded=bounded)
+    bt = P.paqif.Batch(offs, q, order="lpt")
+    keep = P.paqif.get_layout(q, 0)
     try:
-        P.paqif.set_layout(2, 0, layout)
+        P.paqif.set_layout(q, 0, layout)
         r = P.paqif.solve_lcp(bt, torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev),
                               mode=mode, bounded=torch.as_tensor(bounded, device=dev))
         torch.cuda.synchronize()
     finally:
-        P.paqif.set_layout(2, 0, keep)
+        P.paqif.set_layout(q, 0, keep)
     st = r["status"].cpu().numpy()
     assert (st == o["status"]).all(), (st, o["status"])
     u, act, w = r["u"].cpu().numpy(), r["active"].cpu().numpy(), r["w"].cpu().numpy()
