@@ -7,10 +7,11 @@
   * the same with the kappa-scheme convection (kappa = 0, 1/3, -1; exact and
     first-order Newton matrix);
   * converged alternating-sweep solution on 33 x 33 nodes (van Leer, and
-    the kappa-scheme with kappa = 1/3): P, H0, Hmin
-    within 1e-9 relative (both sides stop at max |dP| <= 1e-12 per step;
-    with a contraction of about 0.97 per step each is within ~3e-11 of the
-    fixed point);
+    the kappa-scheme with kappa = 1/3): P, H0, Hmin within 1e-10 relative
+    (both sides stop at max |dP| <= 1e-12 per step; with a contraction of
+    about 0.97 per step each is within ~3e-11 of the fixed point: the
+    oracle's solution at this stop differs from its solution at 1e-13 by
+    6e-12 relative);
   * the 257 x 257 contact (M = 200, L = 10): converged, load balance, y-mirror
     symmetry and complementarity of the oracle's residual on the GPU
     solution.
@@ -106,9 +107,9 @@ def test_point_newton_matches_oracle(gpu, oracle_33):
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 0
     P = r["P"][0].cpu().numpy()
-    assert np.abs(P - o["P"]).max() <= 1e-9 * np.abs(o["P"]).max()
-    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-9 * abs(o["H0"])
-    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-9 * abs(o["Hmin"])
+    assert np.abs(P - o["P"]).max() <= 1e-10 * np.abs(o["P"]).max()
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
 
 
 def test_point_newton_kappa_scheme_matches_oracle(gpu):
@@ -122,9 +123,9 @@ def test_point_newton_kappa_scheme_matches_oracle(gpu):
     torch.cuda.synchronize()
     assert int(r["status"][0]) == 0
     P = r["P"][0].cpu().numpy()
-    assert np.abs(P - o["P"]).max() <= 1e-9 * np.abs(o["P"]).max()
-    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-9 * abs(o["H0"])
-    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-9 * abs(o["Hmin"])
+    assert np.abs(P - o["P"]).max() <= 1e-10 * np.abs(o["P"]).max()
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
 
 
 def test_point_newton_fp32_refined_lcp_matches_oracle(gpu, oracle_33):
