@@ -278,7 +278,7 @@ typedef struct {
     double M, L;
 } ehl_params;
 
-/* Options of the hybrid Newton line iteration (Lhs1, eqs. 60-75). */
+/* Options of the hybrid line iteration (eqs. 60-75). */
 typedef struct {
     double omega;        /* relaxation of the pressure change, (0, 1]          */
     double c_h0;         /* load-balance relaxation c of eq. 75                */
@@ -314,6 +314,18 @@ typedef struct {
                              instance at once (SYS_ZERO_PIVOT / SYS_NONFINITE).
                              Point contact: a step fails if any line of any of
                              its four colour passes failed.                    */
+    int32_t splitting;   /* matrix of each step's linearised problem (the
+                            residual and the fixed point do not change):
+                            0 the Newton band (limiter_jacobian applies);
+                            1 / 2 the implicit operator of the hybrid
+                            splitting Lhs1 / Lhs2 (Sec. 3.3.2, eqs. 60 / 61:
+                            Ls1 or Ls0 for a direct change, eqs. 48-49; Ls4
+                            or Ls5 for a weighted change, eqs. 56-59) --
+                            eps and rho held at the current iterate, the
+                            convective flux first-order upwind with weight
+                            (2-k)/2 (Lhs1) or (2-k)/2 + (1-k)/4 (Lhs2), k =
+                            kappa with convection 1, 0 with the limited
+                            slope.  Line and point contact.                   */
 } ehl_opts;
 
 /*

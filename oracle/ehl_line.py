@@ -146,6 +146,22 @@ def limiter_jacobian(dm, dp, mode, kappa=None):
     return np.zeros_like(pa), np.zeros_like(pb)
 
 
+def splitting_coefficient(split, kappa=None):
+    """Weight of the upwind film-response difference (rho H)_i - (rho H)_{i-1}
+    in the implicit operator of the paper's hybrid splittings (Sec. 3.3.2):
+    Lhs1 (eq. 60: Ls1 for a direct change, eq. 49; Ls4 for a weighted change,
+    eqs. 56-57) keeps (2 - kappa)/2 of it implicit; Lhs2 (eq. 61: Ls0, eq. 48;
+    Ls5, eqs. 58-59) also moves the (1 - kappa)/4 part of the upstream
+    difference, (H_{i-1} - H_i) + (H_i - H_{i-2}), to the implicit side:
+    (2 - kappa)/2 + (1 - kappa)/4.  kappa = 0 with the limited slope."""
+    k = 0.0 if kappa is None else kappa
+    if split == 1:
+        return 0.5 * (2.0 - k)
+    if split == 2:
+        return 0.5 * (2.0 - k) + 0.25 * (1.0 - k)
+    raise ValueError("split must be 1 (Lhs1) or 2 (Lhs2)")
+
+
 def state(P, H, ph, lam):
     rho, drho, lneta, dlneta = lubricant(P, ph)
     eta = np.exp(lneta)
@@ -168,7 +184,8 @@ def residual(P, H, ph, lam, h, kappa=None):
     return R, s
 
 
-def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa=None):
+def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa=None,
+                  split=0):
     """Band of dR_i/dsigma_j (interior rows and columns) for the change
     delta = D sigma (column j of D: e_j for a direct node, e_j - (e_{j-1} +
     e_{j+1})/2 for a distributive one; boundary nodes stay fixed).
@@ -176,6 +193,11 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa
     The film reacts to sigma_j through the distributed kernel (K D); as in
     eqs. 66-67 and 74 it is kept for the nodes |m - j| <= kterms only.
     With every node direct this is dR/dP with the kernel cut to |k-j| <= 1.
+    split = 1 or 2: the implicit operator of the splitting Lhs1 or Lhs2
+    instead -- eps and rho held at the current iterate (eqs. 62, 64-65,
+    70, 72-73: only P + D sigma and the film H + K D sigma move), the
+    convective flux first-order upwind with the weight
+    splitting_coefficient(split, kappa).
     Returns J with J[r, s+4] = dR_{r+1}/dsigma_{r+1+s}, s = -4..4 (nonzero
     offsets -3..2)."""
     N = len(P)
@@ -216,8 +238,13 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa
         dHn[o] = np.where(kin, np.where(dk, kd - corr, kd), 0.0)
     eP = drho * H ** 3 / lam_eta - eps * dlneta
     eH = 3.0 * rho * H ** 2 / lam_eta
+    drhoH = drho * H
+    cw = 1.0
+    if split:
+        eP, eH, drhoH = 0.0 * eP, 0.0 * eH, 0.0 * drhoH
+        limjac, cw = 2, splitting_coefficient(split, kappa)
     deps = {o: eP * dPn[o] + eH * dHn[o] for o in OFFS}
-    drH = {o: drho * H * dPn[o] + rho * dHn[o] for o in OFFS}
+    drH = {o: drhoH * dPn[o] + rho * dHn[o] for o in OFFS}
 
     def node_d(darr, mm, j):
         o = j - mm
@@ -252,7 +279,7 @@ def jacobian_band(P, H, ph, lam, h, kvec, direct=None, kterms=1, limjac=0, kappa
             out[t] += 0.5 * dpsi
             return out
 
-        dR = (dA - dB) / h ** 2 - (dflux(i) - dflux(i - 1)) / h
+        dR = (dA - dB) / h ** 2 - cw * (dflux(i) - dflux(i - 1)) / h
         J[:, s + 4] = np.where(valid, dR, 0.0)
     return J
 
@@ -315,16 +342,18 @@ def hybrid_direct(P, eps, h):
 
 
 def newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp_solve, kterms=2, limjac=LIMJAC,
-                kappa=None):
-    """One Lhs1 step (kappa given: the kappa-scheme convection of Sec. 3.3
-    instead of the limited slope); returns (P_new, H0_new, info)."""
+                kappa=None, split=0):
+    """One step of the hybrid line iteration (kappa given: the kappa-scheme
+    convection of Sec. 3.3 instead of the limited slope; split 1 / 2: the
+    implicit operator of the splitting Lhs1 / Lhs2 instead of the Newton
+    band); returns (P_new, H0_new, info)."""
     abar, lam, ph = moes_line(M, L)
     H = film(P, H0, x, kvec, rough)
     R, st = residual(P, H, ph, lam, h, kappa)
     direct_all = hybrid_direct(P, st["eps"], h)
     direct = direct_all[1:-1]
     D = distributive_matrix_band(direct)
-    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac, kappa)
+    A = -jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac, kappa, split)
     Pi = P[1:-1]
     b = band_matvec(A, Pi) + R
     nb = np.concatenate([[True], direct, [True]])
@@ -367,7 +396,7 @@ def lcp_exact(A, b, bounded, max_iter=64):
 
 def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-13,
                rough=None, P=None, H0=None, limjac=None, stall_steps=0, kappa=None,
-               rigid=False, lcp_max_iter=64, lcp_fail_steps=LCP_FAIL_STEPS):
+               rigid=False, lcp_max_iter=64, lcp_fail_steps=LCP_FAIL_STEPS, splitting=0):
     """Run the hybrid Newton line iteration to convergence.
 
     Stops when max |P_new - P| <= t * max(1, |P|_inf) and |pi/2 - h sum P|
@@ -380,7 +409,9 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     number of steps and the status.  ``rigid`` drops the elastic
     deformation (K = 0); with L = 0 (p_h = 0) the lubricant is
     incompressible and isoviscous (rho = eta = 1), the rigid-isoviscous
-    problem the paper names for incompressible flow."""
+    problem the paper names for incompressible flow.  ``splitting`` 1 or 2
+    iterates with the implicit operator of Lhs1 or Lhs2 (eqs. 60-61) instead
+    of the Newton band: same fixed point, another iteration."""
     x, h = grid(N)
     kvec = np.zeros(N) if rigid else deform.line_kernel(N, h)
     if P is None:
@@ -404,7 +435,7 @@ def solve_line(M, L, N, omega=0.5, c_h0=0.1, kterms=2, max_newton=2000, tol=1e-1
     best, best_it = np.inf, 0
     for it in range(1, max_newton + 1):
         Pn, H0, info = newton_step(P, H0, x, h, kvec, M, L, rough, omega, c_h0, lcp, kterms,
-                                   LIMJAC if limjac is None else limjac, kappa)
+                                   LIMJAC if limjac is None else limjac, kappa, splitting)
         dP = np.abs(Pn - P).max()
         P = Pn
         fails = fails + 1 if last[0] == LCP_NOT_CONVERGED else 0

@@ -129,10 +129,14 @@ def classify(P, eps, hx, hy):
 
 
 def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=EL.LIMJAC,
-                  kappa=None):
+                  kappa=None, split=0):
     """Band systems of every interior line of one sweep direction.
 
     axis = 0: x-lines (one per interior j, positions i); axis = 1: y-lines.
+    split = 1 or 2: the implicit operator of the splitting Lhs1 or Lhs2
+    (eps and rho held at the current iterate, first-order upwind convective
+    derivative weighted by ehl_line.splitting_coefficient) instead of the
+    Newton band.
     Returns (A, b, bounded) with A of shape (lines, n, 9), A[l, r, s+4] =
     -dR/dsigma between rows r and r+s of line l (n = interior positions)."""
     # generic layout G[line, pos]: along-line = axis 1, across-line = axis 0
@@ -144,6 +148,10 @@ def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=
     eP = drho * Hg ** 3 / lam_eta - eps * T(st["dlneta"])
     eH = 3.0 * rho * Hg ** 2 / lam_eta
     drhoH = drho * Hg
+    cw = 1.0
+    if split:
+        eP, eH, drhoH = 0.0 * eP, 0.0 * eH, 0.0 * drhoH
+        limjac, cw = 2, EL.splitting_coefficient(split, kappa)
     dist = ~T(direct)
     nl, nn = Pg.shape                       # lines incl. boundary lines, nodes per line
     n = nn - 2
@@ -282,7 +290,7 @@ def sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms=1, limjac=
                            + (1.0 + 0.5 * (pb_m[:, sl] - pa_m[:, sl])) * d[-1]
                            + 0.5 * pa_m[:, sl] * d[0])
             conv = (f_i - f_m) / h_p
-        dR = along + across - conv
+        dR = along + across - cw * conv
         J[:, :, s + 4] = np.where(valid[None, :], dR, 0.0)
     A = -J
     R2, _ = residual(P, H, ph, lam, hx, hy, kappa)
@@ -330,7 +338,7 @@ def sweep_update(P, sigma_g, direct, omega):
 
 
 def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color,
-                kappa=None):
+                kappa=None, split=0):
     """Solve the lines of one sweep direction (color None: all lines, else
     the lines whose index has that parity) and apply their changes."""
     _, lam, ph = moes_point(M, L)
@@ -338,7 +346,7 @@ def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, 
     st = EL.state(P, H, ph, lam)
     direct = classify(P, st["eps"], hx, hy)
     A, b, bounded = sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms,
-                                  kappa=kappa)
+                                  kappa=kappa, split=split)
     T = (lambda a: a.T) if axis == 0 else (lambda a: a)
     Pl = T(P)[1:-1, 1:-1]
     frozen = ~T(direct)[1:-1, 1:-1] if axis == 1 else np.zeros(Pl.shape, dtype=bool)
@@ -354,7 +362,7 @@ def _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, 
 
 
 def half_sweep(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, c_h0, kterms, lcp, rough=None,
-               kappa=None):
+               kappa=None, split=0):
     """One sweep direction then the H0 update.  The lines are solved in two
     colours (odd lines, then even ones with the film re-evaluated): with all
     lines at once the weighted changes of neighbouring lines can cancel
@@ -362,7 +370,7 @@ def half_sweep(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, c_h0, kterms, lcp, ro
     the x-flux couples each column to its upstream neighbours."""
     for color in (1, 0):
         P = _sweep_part(P, H0, X, Y, hx, hy, k2, M, L, axis, omega, kterms, lcp, rough, color,
-                        kappa)
+                        kappa, split)
     H0n = H0 - c_h0 * (LOAD - hx * hy * P.sum())
     return P, H0n
 
@@ -379,8 +387,9 @@ def start_h0(X, Y, hx, hy, M):
 
 
 def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.02, kterms=2, max_steps=400, tol=1e-12,
-                rough=None, P=None, H0=None, lcp=None, kappa=None):
-    """Alternating x/y line sweeps to convergence.  Stops when max |P change|
+                rough=None, P=None, H0=None, lcp=None, kappa=None, splitting=0):
+    """Alternating x/y line sweeps to convergence (splitting 1 / 2: the
+    lines' matrices are the implicit operators of Lhs1 / Lhs2).  Stops when max |P change|
     over one x+y step <= t max(1, |P|_inf) and |2pi/3 - hx hy sum P| <= t,
     t = max(tol, 4 max(Nx, Ny) eps) (status 0), else status 6.  Returns dict(P, H0, H, Hmin, iters, status,
     X, Y, hx, hy)."""
@@ -397,9 +406,9 @@ def solve_point(M, L, Nx, Ny, omega=0.5, c_h0=0.02, kterms=2, max_steps=400, tol
     it = 0
     for it in range(1, max_steps + 1):
         P1, H0 = half_sweep(P, H0, X, Y, hx, hy, k2, M, L, 0, omega, c_h0, kterms, lcp, rough,
-                            kappa)
+                            kappa, splitting)
         P2, H0 = half_sweep(P1, H0, X, Y, hx, hy, k2, M, L, 1, omega, c_h0, kterms, lcp, rough,
-                            kappa)
+                            kappa, splitting)
         dP = np.abs(P2 - P).max()
         P = P2
         if not np.isfinite(dP):

@@ -71,6 +71,29 @@ bool valid_convection(const ehl_opts* o)
     return o->convection == 0 || (o->convection == 1 && o->kappa >= -1.0 && o->kappa <= 1.0);
 }
 
+// Weight of the upwind convective derivative in the splitting matrices
+// (Sec. 3.3.2): Lhs1 (2-k)/2, Lhs2 (2-k)/2 + (1-k)/4, k = kappa for the
+// kappa-scheme, 0 for the limited slope.
+double splitting_weight(const ehl_opts* o)
+{
+    const double k = o->convection == 1 ? o->kappa : 0.0;
+    if (o->splitting == 1) return 0.5 * (2.0 - k);
+    if (o->splitting == 2) return 0.5 * (2.0 - k) + 0.25 * (1.0 - k);
+    return 1.0;
+}
+
+// Assembly arguments shared by the line and point kernels: slope, limiter
+// matrix and splitting.
+template <typename Args>
+void set_scheme(Args& a, const ehl_opts* o)
+{
+    a.conv = o->convection;
+    a.kappa = o->kappa;
+    a.split = o->splitting;
+    a.csplit = splitting_weight(o);
+    a.limjac = o->splitting != 0 ? 2 : o->limiter_jacobian;
+}
+
 bool valid_opts(const ehl_opts* o)
 {
     return o && o->omega > 0 && o->omega <= 1.0 && o->c_h0 > 0 && o->tol > 0 &&
@@ -81,7 +104,7 @@ bool valid_opts(const ehl_opts* o)
            (o->lcp_prec == PREC_FP64 || o->lcp_prec == PREC_FP32_IR) &&
            o->steps_per_graph >= 1 && o->steps_per_graph <= 64 && o->limiter_jacobian >= 0 &&
            o->limiter_jacobian <= 2 && o->stall_steps >= 0 && o->lcp_fail_steps >= 0 &&
-           valid_convection(o);
+           o->splitting >= 0 && o->splitting <= 2 && valid_convection(o);
 }
 
 // Newton workspace layout (line contact)
@@ -321,9 +344,7 @@ int point_newton(paqif_handle handle, const ehl_grid* grid, const ehl_params* pa
     pa.Ny = Ny;
     pa.B = B;
     pa.kterms = opts->kernel_terms;
-    pa.limjac = opts->limiter_jacobian;
-    pa.conv = opts->convection;
-    pa.kappa = opts->kappa;
+    set_scheme(pa, opts);
     pa.hx = hx;
     pa.hy = hy;
     pa.k2 = dws;
@@ -537,9 +558,7 @@ int ehl_jacobian_assemble(paqif_handle handle, const ehl_grid* grid, const ehl_p
     a.N = N;
     a.B = B;
     a.kterms = opts->kernel_terms;
-    a.limjac = opts->limiter_jacobian;
-    a.conv = opts->convection;
-    a.kappa = opts->kappa;
+    set_scheme(a, opts);
     a.h = hx_of(grid);
     a.x0 = grid->x0;
     a.switch_ratio = opts->switch_ratio;
@@ -619,9 +638,7 @@ int ehl_newton_tvd(paqif_handle handle, const ehl_grid* grid, const ehl_params* 
     aa.N = N;
     aa.B = B;
     aa.kterms = opts->kernel_terms;
-    aa.limjac = opts->limiter_jacobian;
-    aa.conv = opts->convection;
-    aa.kappa = opts->kappa;
+    set_scheme(aa, opts);
     aa.h = h;
     aa.x0 = grid->x0;
     aa.switch_ratio = opts->switch_ratio;
@@ -835,9 +852,7 @@ int ehl_point_sweep_assemble(paqif_handle handle, const ehl_grid* grid, const eh
     pa.axis = axis;
     pa.color = color;
     pa.kterms = opts->kernel_terms;
-    pa.limjac = opts->limiter_jacobian;
-    pa.conv = opts->convection;
-    pa.kappa = opts->kappa;
+    set_scheme(pa, opts);
     pa.hx = na.hx;
     pa.hy = na.hy;
     pa.k2 = k2;

@@ -21,6 +21,10 @@ struct LineAssembleArgs {
     int N, B, kterms, limjac;
     int conv;       // 0 van Leer slope, 1 kappa-scheme
     double kappa;
+    // splitting matrix (Lhs1 / Lhs2): eps and rho frozen, upwind convective
+    // derivative weighted by csplit (limjac must be 2); 0: Newton band
+    int split = 0;
+    double csplit = 1.0;
     double h, x0, switch_ratio;
     const ehl_params* params;  // device, B
     const double* kvec;        // N (device) or null: use kap
@@ -107,6 +111,8 @@ struct PointAssembleArgs {
     int Nx, Ny, B, axis, color, kterms, limjac;
     int conv;      // 0 van Leer slope, 1 kappa-scheme slope (Sec. 3.3, eqs. 56-59)
     double kappa;
+    int split = 0;  // as LineAssembleArgs
+    double csplit = 1.0;
     double hx, hy;
     const double* k2;  // Nx x Ny kernel table
     const double *P, *eps, *rH, *rho, *drhoH, *eP, *eH;

@@ -126,15 +126,18 @@ __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
     auto rHn = [&](int m) { return sRH[m - mbase]; };
     // derivatives of node quantities wrt sigma_k
     auto dP = [&](int m, int k) { return (m < 0 || m >= N) ? 0.0 : Dc(k, m); };
+    // (splitting matrices: eps and rho held at the current iterate, so only
+    // the pressure and the film move)
+    const bool frozen = a.split != 0;
     auto dEps = [&](int m, int k) {
-        if (m < 0 || m >= N) return 0.0;
+        if (frozen || m < 0 || m >= N) return 0.0;
         const int w = m - mbase;
         return sEP[w] * Dc(k, m) + sEH[w] * KDc(k, m);
     };
     auto dRH = [&](int m, int k) {
         if (m < 0 || m >= N) return 0.0;
         const int w = m - mbase;
-        return sDrhoH[w] * Dc(k, m) + sRho[w] * KDc(k, m);
+        return (frozen ? 0.0 : sDrhoH[w] * Dc(k, m)) + sRho[w] * KDc(k, m);
     };
     // limiter at node tt (1 <= tt <= N-2)
     auto limiter = [&](int tt, double& psi, double& pa, double& pb) {
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(TILE) line_assemble_kernel(LineAssembleArgs a)
                                               pb_m * (dRH(i - 1, k) - dRH(i - 2, k)));
             else
                 df_m = dRH(0, k);
-            const double J = (dA - dB) / (h * h) - (df_i - df_m) / h;
+            const double J = (dA - dB) / (h * h) - a.csplit * (df_i - df_m) / h;
             Aval = -J;
             rhs += Aval * Pn(k);
         }

@@ -162,15 +162,17 @@ __global__ void __launch_bounds__(256) point_assemble_kernel(PointAssembleArgs a
         }
         return v;
     };
+    // (splitting matrices: eps and rho held at the current iterate)
+    const bool frozen = a.split != 0;
     auto dEps = [&](int m, int k) -> double {
-        if (m < 0 || m >= nn) return 0.0;
+        if (frozen || m < 0 || m >= nn) return 0.0;
         const int64_t q = id(l, m);
         return a.eP[q] * dPd(0, m, k) + a.eH[q] * dHd(0, m, k);
     };
     auto dRH = [&](int aa, int m, int k) -> double {
         if (m < 0 || m >= nn || l + aa < 0 || l + aa >= nl) return 0.0;
         const int64_t q = id(l + aa, m);
-        return a.drhoH[q] * dPd(aa, m, k) + a.rho[q] * dHd(aa, m, k);
+        return (frozen ? 0.0 : a.drhoH[q] * dPd(aa, m, k)) + a.rho[q] * dHd(aa, m, k);
     };
     auto eps = [&](int ll, int m) { return a.eps[id(ll, m)]; };
     auto rH = [&](int ll, int m) { return a.rH[id(ll, m)]; };
@@ -274,7 +276,7 @@ __global__ void __launch_bounds__(256) point_assemble_kernel(PointAssembleArgs a
                     fm = dm1;
                 conv = (fi - fm) / h_p;
             }
-            Av = -(along + across - conv);
+            Av = -(along + across - a.csplit * conv);
             contrib = Av * Pn(l, k);
         }
         if (active) brow[s + 4] = Av;

@@ -26,7 +26,7 @@ def default_opts(**kw):
     o = dict(omega=0.5, c_h0=0.1, switch_ratio=0.6, tol=1e-13, max_newton=4000, kernel_terms=2,
              lcp_max_iter=64, deform_prec=B.PREC_FP64, lcp_prec=B.PREC_FP64, steps_per_graph=16,
              start_rule=1, limiter_jacobian=2, stall_steps=0, convection=0, kappa=0.0,
-             lcp_fail_steps=16)
+             lcp_fail_steps=16, splitting=0)
     o.update(kw)
     return B.EhlOpts(**o)
 

@@ -11,6 +11,8 @@ Tolerances:
     1e-11 of the row scale plus 1e-14 of the instance scale (rows near the
     cavitation boundary are differences of terms as large as the instance
     scale, so their rounding error is absolute); masks exact;
+  * the same for the Lhs1 / Lhs2 splitting matrices (eqs. 60-61) and the
+    fixed point those iterations reach;
   * converged Newton solution: P, H, H0, Hmin within 1e-10 relative (the
     stated FP64 target); both sides iterate to max|dP| <= 1e-13.
 """
@@ -109,6 +111,56 @@ def test_line_assembly(gpu, N, kterms, limjac):
         assert (np.abs(g["band"][b] - A) <= 1e-11 * scale + 1e-14 * np.abs(A).max()).all()
         assert _rel(g["R"][b], R) < 1e-11
         assert np.abs(g["rhs"][b] - rhs).max() <= 1e-11 * max(1, np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("N", [65, 700])
+@pytest.mark.parametrize("split,kappa", [(1, None), (2, None), (1, 1.0 / 3.0), (2, -1.0)])
+def test_line_assembly_splitting(gpu, N, split, kappa):
+    """The Lhs1 / Lhs2 matrices (eps and rho frozen, upwind convective
+    derivative weighted by (2-k)/2 or (2-k)/2 + (1-k)/4) and the right-hand
+    side built on them, against the oracle."""
+    P = gpu.ehl
+    Ms, Ls, H0s = [20.0, 100.0, 500.0], [10.0, 5.0, 20.0], [-0.3, -0.55, -0.58]
+    x, h, kvec, _ = _state(N, 0)
+    Ps = np.stack([_state(N, s)[3] for s in range(3)])
+    Hel = np.stack([odef.line_deformation(Ps[b], h) for b in range(3)])
+    opts = P.default_opts(kernel_terms=2, convection=0 if kappa is None else 1,
+                          kappa=0.0 if kappa is None else kappa, splitting=split)
+    r = P.assemble(P.line_grid(N), P.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
+                   torch.as_tensor(Hel, device=DEV),
+                   torch.as_tensor(H0s, dtype=torch.float64, device=DEV), opts)
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    for b in range(3):
+        _, lam, ph = OE.moes_line(Ms[b], Ls[b])
+        H = H0s[b] + 0.5 * x * x + Hel[b]
+        R, st = OE.residual(Ps[b], H, ph, lam, h, kappa)
+        direct = OE.hybrid_direct(Ps[b], st["eps"], h)[1:-1]
+        A = -OE.jacobian_band(Ps[b], H, ph, lam, h, kvec, direct, 2, kappa=kappa, split=split)
+        rhs = OE.band_matvec(A, Ps[b][1:-1]) + R
+        scale = np.abs(A).max(axis=1, keepdims=True)
+        assert (np.abs(g["band"][b] - A) <= 1e-11 * scale + 1e-14 * np.abs(A).max()).all()
+        assert _rel(g["R"][b], R) < 1e-11
+        assert np.abs(g["rhs"][b] - rhs).max() <= 1e-11 * max(1, np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("split,kappa", [(1, None), (2, None), (2, 1.0 / 3.0)])
+def test_newton_splitting_matches_oracle(gpu, split, kappa):
+    """Config 1 iterated with the Lhs1 / Lhs2 matrices (eqs. 60-61) instead
+    of the Newton band: the GPU and the oracle, run the same way, agree on the
+    fixed point within 1e-10."""
+    o = OE.solve_line(20.0, 10.0, 257, kappa=kappa, splitting=split)
+    assert o["status"] == 0
+    P = gpu.ehl
+    r = P.solve_line([20.0], [10.0], 257,
+                     opts=P.default_opts(convection=0 if kappa is None else 1,
+                                         kappa=0.0 if kappa is None else kappa,
+                                         splitting=split))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    assert _rel(r["P"][0].cpu().numpy(), o["P"]) < 1e-10
+    assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
+    assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
+    assert abs(int(r["iters"][0]) - o["iters"]) <= 5
 
 
 @pytest.fixture(scope="module")

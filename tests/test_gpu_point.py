@@ -5,13 +5,13 @@
     in another evaluation order: 1e-11 of the row scale plus 1e-14 of the
     instance scale (the line-contact assembly bound), masks exact;
   * the same with the kappa-scheme convection (kappa = 0, 1/3, -1; exact and
-    first-order Newton matrix);
+    first-order Newton matrix), and with the Lhs1 / Lhs2 splitting matrices;
   * converged alternating-sweep solution on 33 x 33 nodes (van Leer, and
     the kappa-scheme with kappa = 1/3): P, H0, Hmin within 1e-10 relative
     (both sides stop at max |dP| <= 1e-12 per step; with a contraction of
     about 0.97 per step each is within ~3e-11 of the fixed point: the
     oracle's solution at this stop differs from its solution at 1e-13 by
-    6e-12 relative);
+    6e-12 relative); the Lhs2 splitting reaches the same fixed point;
   * the 257 x 257 contact (M = 200, L = 10): converged, load balance, y-mirror
     symmetry and complementarity of the oracle's residual on the GPU
     solution.
@@ -53,7 +53,15 @@ def test_point_sweep_assembly_kappa_scheme(gpu, axis, limjac, kappa):
     _check_assembly(gpu, 17, 13, axis, 2, limjac, kappa)
 
 
-def _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, kappa):
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("split,kappa", [(1, None), (2, None), (2, 1.0 / 3.0), (1, -1.0)])
+def test_point_sweep_assembly_splitting(gpu, axis, split, kappa):
+    """Lhs1 / Lhs2 line matrices (eps and rho frozen, weighted upwind
+    convective derivative) and their right-hand sides."""
+    _check_assembly(gpu, 17, 13, axis, 2, 2, kappa, split)
+
+
+def _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, kappa, split=0):
     E = gpu.ehl
     Ms, Ls, H0s = [20.0, 200.0], [10.0, 8.0], [-0.5, -0.9]
     X, Y, hx, hy, _ = _state(Nx, Ny, 0)
@@ -62,7 +70,7 @@ def _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, kappa):
     k2 = odef.point_kernel(Nx, Ny, hx, hy)
     opts = E.default_opts(kernel_terms=kterms, limiter_jacobian=limjac,
                           convection=0 if kappa is None else 1,
-                          kappa=0.0 if kappa is None else kappa)
+                          kappa=0.0 if kappa is None else kappa, splitting=split)
     grid = E.point_grid(Nx, Ny)
     for color in (1, 0):
         g = E.point_sweep_assemble(grid, E.params_tensor(Ms, Ls, DEV), torch.as_tensor(Ps, device=DEV),
@@ -78,7 +86,7 @@ def _check_assembly(gpu, Nx, Ny, axis, kterms, limjac, kappa):
             st = OL.state(Ps[b], H, ph, lam)
             direct = OP.classify(Ps[b], st["eps"], hx, hy)
             A, rhs, bounded = OP.sweep_systems(Ps[b], H, st, ph, lam, hx, hy, k2, direct, axis,
-                                               kterms, limjac, kappa)
+                                               kterms, limjac, kappa, split)
             assert (g["direct"][b] == direct.astype(np.uint8)).all()
             inst = np.abs(A).max()
             for slot, l in enumerate(lines):
@@ -126,6 +134,24 @@ def test_point_newton_kappa_scheme_matches_oracle(gpu):
     assert np.abs(P - o["P"]).max() <= 1e-10 * np.abs(o["P"]).max()
     assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
     assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
+
+
+def test_point_lhs2_splitting_matches_oracle(gpu, oracle_33):
+    """The Lhs2 splitting (eq. 61) as the sweeps' line matrices: the oracle's
+    Lhs2 iteration and the GPU's reach the Newton fixed point within 1e-10."""
+    o2 = OP.solve_point(20.0, 10.0, 33, 33, tol=1e-12, max_steps=1500, splitting=2)
+    assert o2["status"] == 0
+    E = gpu.ehl
+    r = E.solve_point([20.0], [10.0], 33, 33,
+                      opts=E.default_opts(tol=1e-12, max_newton=1500, c_h0=0.02, splitting=2))
+    torch.cuda.synchronize()
+    assert int(r["status"][0]) == 0
+    P = r["P"][0].cpu().numpy()
+    for o in (o2, oracle_33):
+        assert np.abs(P - o["P"]).max() <= 1e-10 * np.abs(o["P"]).max()
+        assert abs(float(r["H0"][0]) - o["H0"]) <= 1e-10 * abs(o["H0"])
+        assert abs(float(r["Hmin"][0]) - o["Hmin"]) <= 1e-10 * abs(o["Hmin"])
+    assert abs(int(r["iters"][0]) - o2["iters"]) <= 10
 
 
 def test_point_newton_fp32_refined_lcp_matches_oracle(gpu, oracle_33):

@@ -9,7 +9,10 @@
   * the band Jacobian against central finite differences of the residual
     (with the film map the Jacobian claims to linearise);
   * the converged line contact (M=20, L=10, N=257): complementarity, load
-    balance, the flux invariant of the Reynolds equation, positivity of H.
+    balance, the flux invariant of the Reynolds equation, positivity of H;
+  * the Lhs1 / Lhs2 splitting matrices against finite differences of their
+    implicit operator (eps, rho frozen; weighted upwind convection), and the
+    fixed point of those iterations equal to the Newton iteration's.
 """
 import numpy as np
 import pytest
@@ -279,3 +282,91 @@ def test_converged_config1_with_kappa_scheme(kappa):
     pos = np.where(P > 0)[0]
     qq = q[pos[0] - 1:pos[-1] + 1]
     assert (qq.max() - qq.min()) < 1e-9 * np.abs(qq).max()
+
+
+def _implicit_operator_line(sigma, P, H, eps, rho, h, D, T, c):
+    """Implicit part of the splittings Lhs1 / Lhs2 as a function of the
+    change sigma (interior nodes), written from eqs. 62 and 70 (1D): eps and
+    rho stay at the current iterate, the pressure moves by D sigma, the film
+    by T sigma (the distributed kernel cut as in eqs. 67 and 74), and the
+    convective flux is the upwind value rho H of the node behind the face,
+    weighted by c."""
+    s = np.concatenate([[0.0], sigma, [0.0]])
+    Pb = P.copy()
+    Pb[1:-1] += D @ sigma
+    Hb = H + T @ s
+    ef = 0.5 * (eps[:-1] + eps[1:])
+    dP = Pb[1:] - Pb[:-1]
+    diff = (ef[1:] * dP[1:] - ef[:-1] * dP[:-1]) / h ** 2
+    f = rho * Hb                                  # upwind face value of face i+1/2: node i
+    return diff - c * (f[1:-1] - f[:-2]) / h
+
+
+@pytest.mark.parametrize("split,kappa", [(1, None), (2, None), (1, 1.0 / 3.0), (2, 1.0 / 3.0),
+                                         (2, -1.0)])
+def test_splitting_band_matches_finite_differences(split, kappa):
+    """The Lhs1 / Lhs2 matrix is the derivative of its implicit operator
+    (finite differences of the function above, with distributive columns and
+    the elastic film cut to |m - k| <= 2); the weights are (2 - k)/2 and
+    (2 - k)/2 + (1 - k)/4 (k = 0 for the limited slope)."""
+    N, kterms = 65, 2
+    x, h = E.grid(N)
+    kvec = deform.line_kernel(N, h)
+    _, lam, ph = E.moes_line(50.0, 8.0)
+    rng = np.random.default_rng(11)
+    P = E.hertz_start(x) * (1 + 0.1 * rng.random(N))
+    P[0] = P[-1] = 0.0
+    P[40:44] = 0.0
+    H = E.film(P, -0.2, x, kvec)
+    st = E.state(P, H, ph, lam)
+    n = N - 2
+    direct = rng.random(n) < 0.5
+    D = np.eye(n)
+    for k in range(n):
+        if not direct[k]:
+            if k > 0:
+                D[k - 1, k] = -0.5
+            if k < n - 1:
+                D[k + 1, k] = -0.5
+    Dfull = np.zeros((N, N))
+    Dfull[1:-1, 1:-1] = D
+    KD = deform.line_matrix(N, h) @ Dfull
+    T = np.zeros((N, N))
+    for m in range(N):
+        for k in range(1, N - 1):
+            if abs(m - k) <= kterms:
+                T[m, k] = KD[m, k]
+    kk = 0.0 if kappa is None else kappa
+    c = (2 - kk) / 2 if split == 1 else (2 - kk) / 2 + (1 - kk) / 4
+    e = 1e-6
+    Jfd = np.zeros((n, n))
+    for k in range(n):
+        s = np.zeros(n)
+        s[k] = e
+        Jfd[:, k] = (_implicit_operator_line(s, P, H, st["eps"], st["rho"], h, D, T, c) -
+                     _implicit_operator_line(-s, P, H, st["eps"], st["rho"], h, D, T, c)) / (2 * e)
+    J = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, kappa=kappa, split=split)
+    Jd = np.zeros((n, n))
+    for r in range(n):
+        for s in range(-4, 5):
+            if 0 <= r + s < n:
+                Jd[r, r + s] = J[r, s + 4]
+    err = np.abs(Jd - Jfd).max()
+    assert err <= 1e-12 * np.abs(Jfd).max()
+    # the test tells the matrices apart: the Newton band (eps, rho and the
+    # slope move there) and the other splitting's weight differ by far more
+    Jn = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, limjac=0, kappa=kappa)
+    Jo = E.jacobian_band(P, H, ph, lam, h, kvec, direct, kterms, kappa=kappa, split=3 - split)
+    assert np.abs(Jn - J).max() > 1e6 * err and np.abs(Jo - J).max() > 1e6 * err
+
+
+@pytest.mark.parametrize("split", [1, 2])
+def test_splitting_reaches_the_newton_fixed_point(split, converged_cfg1):
+    """Lhs1 and Lhs2 change the iteration, not the discrete equations: on
+    config 1 they converge to the Newton iteration's fixed point."""
+    r = E.solve_line(20.0, 10.0, 257, splitting=split, max_newton=2000)
+    assert r["status"] == 0
+    ref = converged_cfg1
+    assert np.abs(r["P"] - ref["P"]).max() <= 1e-10 * np.abs(ref["P"]).max()
+    assert abs(r["H0"] - ref["H0"]) <= 1e-10 * abs(ref["H0"])
+    assert abs(r["Hmin"] - ref["Hmin"]) <= 1e-10 * abs(ref["Hmin"])

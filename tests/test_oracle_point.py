@@ -13,7 +13,10 @@
     distributive node (sigma - 4 sigma/4 = 0);
   * the converged 33 x 33 contact (van Leer, and the kappa-scheme with
     kappa = 1/3): complementarity, load balance 2 pi/3, y-mirror symmetry,
-    positive film.
+    positive film;
+  * the Lhs1 / Lhs2 line matrices of both sweep directions against finite
+    differences of their implicit operator (elastic film, weighted changes),
+    and the Lhs2 iteration's fixed point equal to the Newton iteration's.
 """
 import numpy as np
 import pytest
@@ -162,3 +165,102 @@ def test_converged_point_contact_kappa_scheme():
     assert abs(hx * hy * P.sum() - OP.LOAD) <= 1e-10
     assert np.abs(P - P[:, ::-1]).max() <= 1e-12
     assert H.min() > 0
+
+
+def _point_implicit(sig, l, axis, P, H, eps, rho, hx, hy, k2, direct, kterms, c):
+    """Implicit operator of the splitting Lhs1 / Lhs2 on line l as a function
+    of that line's changes sig (interior positions), from eqs. 62 and 69-74:
+    eps and rho at the current iterate; the change field delta = D sigma
+    (sigma at the node, -sigma/4 to the four neighbours of a weighted-change
+    node); the film moves by the 2D kernel sum of each column's change field,
+    kept where the along-line offset to the column is at most kterms; the
+    x-convection is the upwind rho H weighted by c.  Returns the rows of the
+    line's interior nodes."""
+    Nx, Ny = P.shape
+    node = (lambda ll, m: (m, ll)) if axis == 0 else (lambda ll, m: (ll, m))
+    nn = Nx if axis == 0 else Ny
+    Pb, Hb = P.copy(), H.copy()
+    ii, jj = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="ij")
+    along = ii if axis == 0 else jj
+    for k in range(1, nn - 1):
+        if sig[k - 1] == 0.0:
+            continue
+        d = np.zeros_like(P)
+        i0, j0 = node(l, k)
+        d[i0, j0] = 1.0
+        if not direct[i0, j0]:
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                a, b = i0 + di, j0 + dj
+                if 1 <= a <= Nx - 2 and 1 <= b <= Ny - 2:
+                    d[a, b] -= 0.25
+        resp = np.zeros_like(P)
+        for a, b in zip(*np.nonzero(d)):
+            resp += d[a, b] * k2[np.abs(ii - a), np.abs(jj - b)]
+        Pb += sig[k - 1] * d
+        Hb += sig[k - 1] * np.where(np.abs(along - k) <= kterms, resp, 0.0)
+    ex = 0.5 * (eps[1:, :] + eps[:-1, :])
+    ey = 0.5 * (eps[:, 1:] + eps[:, :-1])
+    f = rho * Hb
+    out = []
+    for m in range(1, nn - 1):
+        i, j = node(l, m)
+        r = (ex[i, j] * (Pb[i + 1, j] - Pb[i, j]) - ex[i - 1, j] * (Pb[i, j] - Pb[i - 1, j])) / hx ** 2
+        r += (ey[i, j] * (Pb[i, j + 1] - Pb[i, j]) - ey[i, j - 1] * (Pb[i, j] - Pb[i, j - 1])) / hy ** 2
+        r -= c * (f[i, j] - f[i - 1, j]) / hx
+        out.append(r)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("split,kappa", [(1, None), (2, None), (2, 1.0 / 3.0)])
+def test_splitting_line_matrix_matches_finite_differences(axis, split, kappa):
+    """The point contact's Lhs1 / Lhs2 line matrices are the derivatives of
+    the implicit operator above (elastic film, weighted-change nodes; y-lines:
+    the rows of direct nodes, the others stay identity rows)."""
+    Nx, Ny, kterms, l = 13, 11, 2, 5
+    X, Y, hx, hy, P, H, lam, ph = _rigid_state(Nx, Ny, seed=4)
+    st = OL.state(P, H, ph, lam)
+    rng = np.random.default_rng(8)
+    direct = rng.random((Nx, Ny)) < 0.5
+    direct[0, :] = direct[-1, :] = direct[:, 0] = direct[:, -1] = True
+    k2 = deform.point_kernel(Nx, Ny, hx, hy)
+    A, _, _ = OP.sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms,
+                               kappa=kappa, split=split)
+    kk = 0.0 if kappa is None else kappa
+    c = (2 - kk) / 2 if split == 1 else (2 - kk) / 2 + (1 - kk) / 4
+    nn = Nx if axis == 0 else Ny
+    n = nn - 2
+    e = 1e-6
+    Jfd = np.zeros((n, n))
+    for k in range(n):
+        s = np.zeros(n)
+        s[k] = e
+        Jfd[:, k] = (_point_implicit(s, l, axis, P, H, st["eps"], st["rho"], hx, hy, k2, direct,
+                                     kterms, c) -
+                     _point_implicit(-s, l, axis, P, H, st["eps"], st["rho"], hx, hy, k2, direct,
+                                     kterms, c)) / (2 * e)
+    Ad = np.zeros((n, n))
+    for r in range(n):
+        for s in range(-4, 5):
+            if 0 <= r + s < n:
+                Ad[r, r + s] = A[l - 1, r, s + 4]
+    rows = np.arange(n)
+    if axis == 1:
+        rows = rows[direct[l, 1:-1]]
+        frozen = ~direct[l, 1:-1]
+        assert (Ad[frozen] == np.eye(n)[frozen]).all()
+    err = np.abs(-Ad[rows] - Jfd[rows]).max()
+    assert err <= 1e-9 * np.abs(Jfd[rows]).max(), err
+    An, _, _ = OP.sweep_systems(P, H, st, ph, lam, hx, hy, k2, direct, axis, kterms, limjac=0,
+                                kappa=kappa)
+    assert np.abs(An[l - 1] - A[l - 1]).max() > 1e3 * err
+
+
+def test_splitting_reaches_the_newton_fixed_point_point_contact():
+    """Lhs2 on the 17 x 17 contact converges to the Newton iteration's fixed
+    point (the splitting changes the iteration, not the equations)."""
+    ref = OP.solve_point(20.0, 10.0, 17, 17, tol=1e-13, max_steps=1500)
+    r = OP.solve_point(20.0, 10.0, 17, 17, tol=1e-13, max_steps=1500, splitting=2)
+    assert ref["status"] == 0 and r["status"] == 0
+    assert np.abs(r["P"] - ref["P"]).max() <= 1e-10 * np.abs(ref["P"]).max()
+    assert abs(r["H0"] - ref["H0"]) <= 1e-10 * abs(ref["H0"])
