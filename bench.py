@@ -32,6 +32,28 @@ def algorithmic_bytes_per_row(q):
     return 8 * (2 * q + 1) + 8 + 8 + 2 * 8 * (2 * q + 1)
 
 
+def mixed_bytes_per_row(q):
+    # FP32 + refinement, per active-set iteration: FP64 band 8(2q+1), b and u,
+    # FP32 level records Z (4q+6 values per level, ~ (2q+3) per row) and W
+    # multipliers (4q per level, 2q per row) written and read back once;
+    # the refinement sweeps' extra residual and re-solve traffic is not
+    # counted (the kernel does not report their number)
+    return 8 * (2 * q + 1) + 8 + 8 + 2 * 4 * ((2 * q + 3) + 2 * q)
+
+
+def lcp_kernel_name(P, q, prec):
+    """Name of the kernel paqif_solve_lcp launches for (q, prec) under the
+    handle's current lane layout."""
+    lay = P.paqif.get_layout(q, prec)
+    if prec == P.PREC_FP64 and lay == 3:
+        return f"paqif_lcp_rows_kernel<{q}>"
+    if prec == P.PREC_FP64 and lay == 2 and q == 2:
+        return "paqif_lcp_lane_kernel<2>"
+    if prec != P.PREC_FP64 and (lay == 3 or (lay == 2 and q == 2)):
+        lay = 0
+    return f"paqif_lcp_kernel<{q},{lay},{'double' if prec == P.PREC_FP64 else 'float'}>"
+
+
 def minimum_bytes_per_row(q):
     # band, b and u read once per active-set iteration (no factor traffic)
     return 8 * (2 * q + 1) + 8 + 8
@@ -151,9 +173,10 @@ def cpu_baseline(batches, sample, nthreads):
     return solves / t_total
 
 
-def measured_traffic(kernel_q):
+def measured_traffic(kernel_q, kernel):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel sources (else None)."""
+    summary, if it was taken on this kernel and the current kernel sources
+    (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "paqif_lcp_q8_hbm_counters.md")
@@ -162,7 +185,8 @@ def measured_traffic(kernel_q):
     txt = open(path).read()
     m_val = re.search(r"traffic_bytes_per_launch_q8_fp64:\s*([0-9.eE+]+)", txt)
     m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
-    if not (m_val and m_sha):
+    m_ker = re.search(r"traffic_kernel:\s*(\S+)", txt)
+    if not (m_val and m_sha and m_ker) or m_ker.group(1) != kernel:
         return None
     h = hashlib.sha256()
     for f in ("paqif.hip", "common.h", "paqif_args.h"):
@@ -244,9 +268,26 @@ def ehl_legs(P, torch, synth, dev, args):
         conv_all += int(ok.sum())
         if N == 1025:
             P1025, ok1025, idx1025 = r["P"], ok, idx
+        if N == 4097:
+            st4097, idx4097 = st, idx
         log(f"ehl sweep N={N}: {dt:.2f} s, converged {int(ok.sum())}/{len(idx)}")
-    res.update(seconds=round(t_all, 3), converged=conv_all,
-               solves_per_s=round(nb / t_all, 3), converged_per_s=round(conv_all / t_all, 3))
+    res.update(seconds=round(t_all, 3), converged=conv_all, failed=nb - conv_all,
+               converged_per_s=round(conv_all / t_all, 3),
+               all_instances_per_s=round(nb / t_all, 3))
+    # the N = 4097 instances that stopped on the active-set cap of 8, re-run
+    # once with the library default cap of 64: do they converge, or cycle?
+    capped = idx4097[st4097 == 3] if args.sweep_cap64 else idx4097[:0]
+    if len(capped):
+        opts64 = P.ehl.default_opts(max_newton=3000, lcp_max_iter=64, stall_steps=600)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        r = P.ehl.solve_line(M[capped], L[capped], 4097, opts=opts64)
+        torch.cuda.synchronize()
+        st64 = r["status"].cpu().numpy()
+        res["N4097_cap8_failures_at_cap64"] = dict(
+            instances=int(len(capped)), seconds=round(_t.perf_counter() - t0, 3),
+            statuses={str(int(k)): int(v) for k, v in zip(*np.unique(st64, return_counts=True))})
+        log(f"ehl sweep N=4097 cap-8 failures at cap 64: {res['N4097_cap8_failures_at_cap64']}")
     if not args.no_cpu:
         # the oracle on a seeded subset: the first instance of the N = 1025
         # group (the full sweep would take the oracle hours)
@@ -557,6 +598,9 @@ def main():
                     help="roughness amplitude of the adjoint leg")
     ap.add_argument("--point-n", type=int, default=257,
                     help="nodes per side of the point-contact leg")
+    ap.add_argument("--sweep-cap64", action="store_true",
+                    help="re-run the N=4097 sweep instances that stop on the active-set cap of 8 "
+                         "with the default cap of 64 (about 80 s more)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (scale of the HBM byte counters)")
     ap.add_argument("--partitioned-only", action="store_true",
@@ -663,28 +707,58 @@ def main():
         bytes_alg = units * algorithmic_bytes_per_row(q)
         per_q[q] = dict(avg_ms=avg_ms, iters_mean=float(iters.mean()),
                         status_ok=bool((status == 0).all()),
+                        kernel=lcp_kernel_name(P, q, P.PREC_FP64),
                         active_frac=float(r["active"].float().mean().item()),
                         gbs=bytes_alg / (avg_ms / 1e3) / 1e9, bytes=bytes_alg)
 
     log(f"LCP fp64: {ms_per_step:.2f} ms/step")
-    # mixed precision (FP32 factors + FP64 refinement): same workload
+    # mixed precision (FP32 factors + FP64 refinement to 1e-10): same
+    # workload, HIP events per solve as above
     for _ in range(max(1, args.warmup // 2)):
         step(P.PREC_FP32_IR)
     torch.cuda.synchronize()
+    evm = {q: [] for q in QS}
     tm0 = time.perf_counter()
     for _ in range(max(1, args.steps // 2)):
-        rm = step(P.PREC_FP32_IR)
+        for q in QS:
+            g = gpu[q]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT,
+                                  prec=P.PREC_FP32_IR, workspace=g["ws32"], refine_tol=1e-10)
+            e1.record()
+            evm[q].append((e0, e1, r))
     torch.cuda.synchronize()
     ms_mixed = (time.perf_counter() - tm0) * 1e3 / max(1, args.steps // 2)
+    rm = {q: evm[q][-1][2] for q in QS}
     r64 = step(P.PREC_FP64)
     torch.cuda.synchronize()
     mixed_err = 0.0
     mixed_active_match = True
+    per_q_mixed = {}
     for q in QS:
         u64 = r64[q]["u"]
         mixed_err = max(mixed_err, float((rm[q]["u"] - u64).abs().max() /
                                          max(1.0, float(u64.abs().max()))))
         mixed_active_match &= bool(torch.equal(rm[q]["active"], r64[q]["active"]))
+        durs = [a.elapsed_time(b) for a, b, _ in evm[q]]
+        st = rm[q]["status"].cpu().numpy()
+        its = rm[q]["iters"].cpu().numpy().astype(np.int64)
+        sizes = batches[q][0][1:] - batches[q][0][:-1]
+        bytes_alg = int((sizes * its).sum()) * mixed_bytes_per_row(q)
+        avg = float(np.mean(durs))
+        per_q_mixed[q] = dict(avg_ms=round(avg, 4), iters_mean=round(float(its.mean()), 4),
+                              statuses={str(int(k)): int(v)
+                                        for k, v in zip(*np.unique(st, return_counts=True))},
+                              gbs=round(bytes_alg / (avg / 1e3) / 1e9, 2),
+                              kernel=lcp_kernel_name(P, q, P.PREC_FP32_IR), bytes=bytes_alg)
+    domm = max(QS, key=lambda q: per_q_mixed[q]["avg_ms"])
+    mixed_roof = dict(bound="hbm", achieved=per_q_mixed[domm]["gbs"], peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=round(per_q_mixed[domm]["gbs"] / HBM_PEAK_GBS, 4),
+                      traffic=None, kernel=per_q_mixed[domm]["kernel"],
+                      algorithmic_bytes_per_launch_gb=round(per_q_mixed[domm]["bytes"] / 1e9, 3),
+                      bytes_per_row_iteration=mixed_bytes_per_row(domm))
 
     active30 = active30_leg(P, torch, synth, args) if not args.no_active30 else None
     ehl = ehl_legs(P, torch, synth, dev, args) if not args.no_ehl else None
@@ -693,11 +767,12 @@ def main():
     copy_gbs = copy_bandwidth(torch)
 
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
-    tr = measured_traffic(dom)
+    dom_kernel = lcp_kernel_name(P, dom, P.PREC_FP64)
+    tr = measured_traffic(dom, dom_kernel)
     roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
                 traffic=None if tr is None else round(tr / 1e9, 3),
-                kernel=f"paqif_lcp_kernel<{dom},double>",
+                kernel=dom_kernel,
                 algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
     rows_it = per_q[dom]["bytes"] / algorithmic_bytes_per_row(dom)
     min_gbs = rows_it * minimum_bytes_per_row(dom) / (per_q[dom]["avg_ms"] / 1e3) / 1e9
@@ -718,7 +793,10 @@ def main():
                    cpu_model=cpu_model(),
                    sample=(f"all {COUNT} systems of each q batch" if args.cpu_sample >= COUNT
                            else f"first {args.cpu_sample} systems of each q batch")
-                          + ", exact LCP, OpenMP over systems")
+                          + ", exact LCP, OpenMP over systems",
+                   build="C oracle, gcc -O3 -march=x86-64-v3 -ffp-contract=off -fopenmp",
+                   ehl_oracle_note="the EHL oracle times in the ehl leg are numpy in one "
+                                   "process (not threaded)")
 
     line = {
         "metric": "PAQIF banded-LCP solves/s (exact LCP, FP64)",
@@ -742,7 +820,10 @@ def main():
                           "solves_per_s": round(len(QS) * COUNT / (ms_mixed / 1e3), 2),
                           "speedup_vs_fp64": round(ms_per_step / ms_mixed, 4),
                           "max_rel_err_vs_fp64": mixed_err,
-                          "active_set_match": mixed_active_match},
+                          "active_set_match": mixed_active_match,
+                          "per_q": {str(q): {k: v for k, v in per_q_mixed[q].items()
+                                             if k != "bytes"} for q in QS},
+                          "roofline": mixed_roof},
         "autotune": tune,
         "ehl": ehl,
         "partitioned": part,
