@@ -376,6 +376,27 @@ def convdiff_leg(P, torch, args):
     out["ls3_n65"] = ls3
     log("convdiff Ls3 n=65: " + ", ".join(f"{k} {v['iterations']} it rel. defect {v['rel_defect']:.1e}"
                                           for k, v in ls3.items()))
+    # the paper's x-line splittings Ls0 / Ls1 (two colours per sweep, omega
+    # 0.7) on 65 x 65 and 257 x 257 nodes, at most 2000 sweeps
+    for n in (65, 257):
+        ws = torch.empty(P.lib().cd_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        spl = {}
+        for which in (0, 1):
+            for kappa in (0.0, 1.0 / 3.0, -1.0):
+                f, u = P.convdiff.example(n)
+                torch.cuda.synchronize()
+                t0 = _t.perf_counter()
+                it, res = P.convdiff.split_relax(f, u, which, kappa, omega=0.7, tol=1e-10,
+                                                 max_iter=2000, workspace=ws)
+                torch.cuda.synchronize()
+                dt = _t.perf_counter() - t0
+                fmax = float(f[1:-1, 1:-1].abs().max())
+                spl[f"Ls{which}_kappa_{kappa:.3f}"] = dict(
+                    iterations=it, ms=round(dt * 1e3, 3), ms_per_iteration=round(dt * 1e3 / it, 4),
+                    rel_defect=res / fmax, converged=bool(res <= 1e-10 * fmax))
+        out[f"ls01_n{n}"] = spl
+        log(f"convdiff Ls0/Ls1 n={n}: " + ", ".join(
+            f"{k} {v['iterations']} it {v['rel_defect']:.1e}" for k, v in spl.items()))
     if not args.no_cpu:
         from oracle import convdiff as OC
         cpu = {}

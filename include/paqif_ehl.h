@@ -494,6 +494,25 @@ int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a
                   int32_t *iters, double *defect, void *workspace, void *stream);
 
 /*
+ * cd_split_relax -- the paper's x-line splittings Ls0 (which = 0, Sec. 3.1
+ * eq. 48) and Ls1 (which = 1, eq. 49) of the same problem, as a defect
+ * correction: x-line j solves L0 sigma = f - L_h u with the tridiagonal
+ * implicit operator u_{i-1}: -eps/h^2 - w a/h, u_i: w a/h + 4 eps/h^2 +
+ * b/h (3 - 3 kappa)/4 (the line's own y-convection coefficient; (1 -
+ * kappa)/2 on the first line), u_{i+1}: -eps/h^2, w = (2 - kappa)/2 (Ls1)
+ * or (2 - kappa)/2 + (1 - kappa)/4 (Ls0), then u += omega sigma on the line
+ * (omega < 1: the paper's under-relaxation).  The paper sweeps the x-lines
+ * in lexicographic order; here one iteration solves the odd lines, then the
+ * even ones, each colour in one batched PAQIF launch (linear mode,
+ * half-bandwidth 2), each on the defect after the other colour's update.
+ * Arguments as for cd_line_relax (workspace: cd_workspace_bytes(n) bytes);
+ * PAQIF_EINVAL for which not 0 or 1.
+ */
+int cd_split_relax(paqif_handle handle, int n, int which, double kappa, double eps, double a,
+                   double b, double omega, double tol, int max_iter, const double *f, double *u,
+                   int32_t *iters, double *defect, void *workspace, void *stream);
+
+/*
  * cd_distributive_relax -- the distributive line relaxation (Ls3 of Sec. 3.1,
  * eqs. 51-54) of the same problem: a node's change is distributed,
  * u_ij += s_ij - (s_{i+-1,j} + s_{i,j+-1}) / 4, and every line solves for

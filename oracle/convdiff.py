@@ -255,3 +255,92 @@ def solve_ls3(n, kappa, eps=1e-6, omega=1.0, tol=1e-10, max_iter=500, a=1.0, b=1
         if res <= tol * fmax:
             break
     return dict(u=u, iters=it, defect=res, fmax=fmax)
+
+
+# ---------------------------------------------------------------------------
+# The paper's x-line splittings Ls0 and Ls1 (Sec. 3.1, eqs. 48-49): the
+# forward x-line splitting L = L+ + L0 + L- with L0 the implicit operator of
+# line j, L+ the upstream line(s) at their new values, L- the rest at the old
+# ones.  Written as a defect correction: L0 sigma = f - L_h u (u with the
+# lines already swept at their new values), u += omega sigma.
+# ---------------------------------------------------------------------------
+
+def split_weight(which, kappa):
+    """Implicit weight of the x-upwind difference (u_i - u_{i-1}) a/h in L0:
+    Ls1 (eq. 49) keeps the first-order upwind part (2 - kappa)/2, Ls0 (eq. 48)
+    also the "positive" part of the upstream kappa term: (2 - kappa)/2 +
+    (1 - kappa)/4."""
+    if which == 1:
+        return 0.5 * (2.0 - kappa)
+    if which == 0:
+        return 0.5 * (2.0 - kappa) + 0.25 * (1.0 - kappa)
+    raise ValueError("which must be 0 (Ls0) or 1 (Ls1)")
+
+
+def split_line_band(n, l, which, kappa, eps, a=1.0, b=1.0):
+    """L0 of x-line l (n-2 interior unknowns) as a half-bandwidth-2 band
+    (rows x 5, column s -> offset s-2): u_{i-1} -eps/h^2 - w a/h, u_i
+    w a/h + 4 eps/h^2 + (the line's own y-convection coefficient), u_{i+1}
+    -eps/h^2, w = split_weight(which, kappa).  The printed L0 has no b terms;
+    the y-convection's coefficient of u_{i,j} itself (b/h (3-3kappa)/4, next
+    to the inflow boundary (1-kappa)/2) is kept implicit like the diffusion
+    diagonal; its upstream terms act through L+ (new values)."""
+    _, h = grid(n)
+    m = n - 2
+    w = split_weight(which, kappa)
+    own_y = b / h * ((3 - 3 * kappa) / 4 if l >= 2 else (1 - kappa) / 2)
+    band = np.zeros((m, 5))
+    for r in range(m):
+        if r >= 1:
+            band[r, 1] = -eps / h ** 2 - w * a / h
+        band[r, 2] = w * a / h + 4 * eps / h ** 2 + own_y
+        if r <= m - 2:
+            band[r, 3] = -eps / h ** 2
+    return band
+
+
+def split_half_step(u, f, which, color, kappa, eps, omega, a=1.0, b=1.0):
+    """The x-lines of one colour (line index parity) at once: L0 sigma = the
+    defect on each, then u += omega sigma on those lines."""
+    n = u.shape[0]
+    r = defect(u, f, kappa, eps, a, b)
+    un = u.copy()
+    for l in range(1, n - 1):
+        if l % 2 != color:
+            continue
+        ab = _band_to_ab(split_line_band(n, l, which, kappa, eps, a, b))
+        un[1:-1, l] += omega * sla.solve_banded((2, 2), ab, r[1:-1, l])
+    return un
+
+
+def split_iteration(u, f, which, kappa, eps, omega, a=1.0, b=1.0, lexicographic=False):
+    """One sweep over the x-lines: odd lines, then even ones (both colours see
+    the other's latest values); lexicographic=True sweeps j = 1, 2, ... one
+    line at a time as the paper's forward ordering does."""
+    n = u.shape[0]
+    if not lexicographic:
+        for color in (1, 0):
+            u = split_half_step(u, f, which, color, kappa, eps, omega, a, b)
+        return u
+    for l in range(1, n - 1):
+        r = defect(u, f, kappa, eps, a, b)
+        ab = _band_to_ab(split_line_band(n, l, which, kappa, eps, a, b))
+        u = u.copy()
+        u[1:-1, l] += omega * sla.solve_banded((2, 2), ab, r[1:-1, l])
+    return u
+
+
+def solve_split(n, which, kappa, eps=1e-6, omega=1.0, tol=1e-10, max_iter=500, a=1.0, b=1.0,
+                lexicographic=False):
+    """Ls0 (which = 0) or Ls1 (which = 1) sweeps until max |f - L_h u| <= tol
+    max|f|."""
+    f = rhs(n, eps, a, b)
+    u = start(n)
+    fmax = np.abs(f[1:-1, 1:-1]).max()
+    it, res = 0, np.inf
+    for it in range(1, max_iter + 1):
+        u = split_iteration(u, f, which, kappa, eps, omega, a, b, lexicographic)
+        res = np.abs(defect(u, f, kappa, eps, a, b)).max()
+        if res <= tol * fmax or not np.isfinite(res):
+            break
+    return dict(u=u, iters=it, defect=res, fmax=fmax)

@@ -116,6 +116,8 @@ def lib():
         "cd_example": ([ctypes.c_int, d, d, d, vp, vp, vp], ctypes.c_int),
         "cd_line_relax": ([vp, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp, vp,
                            ctypes.POINTER(i32), ctypes.POINTER(d), vp, vp], ctypes.c_int),
+        "cd_split_relax": ([vp, ctypes.c_int, ctypes.c_int, d, d, d, d, d, d, ctypes.c_int, vp,
+                            vp, ctypes.POINTER(i32), ctypes.POINTER(d), vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -13,6 +13,7 @@
 // Half-step along `axis`: on every line l of that direction at once solve
 // M sigma = f - L_h u, M = the whole along-line operator (kappa convection +
 // diffusion) plus the diagonal of the across-line part, then u += omega sigma.
+// Also the paper's x-line splittings Ls0 / Ls1 and the distributive Ls3.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -169,6 +170,48 @@ __global__ void cd_ls3_update_kernel(int n, int axis, int first, double omega,
     };
     const double du = g(p, q) - 0.25 * (g(p + 1, q) + g(p - 1, q) + g(p, q + 1) + g(p, q - 1));
     u[(int64_t)p * n + q] += omega * du;
+}
+
+// ---------------------------------------------------------------------------
+// x-line splittings Ls0 / Ls1 (Sec. 3.1, eqs. 48-49): the implicit operator
+// of x-line j is tridiagonal, u_{i-1}: -eps/h^2 - w a/h, u_i: w a/h +
+// 4 eps/h^2 + the line's own y-convection coefficient, u_{i+1}: -eps/h^2,
+// w = (2-k)/2 (Ls1) or (2-k)/2 + (1-k)/4 (Ls0); the rest of L_h acts through
+// the defect.  The x-lines run in two colours (odd, then even j), each
+// colour's defect taken after the other's update.
+// ---------------------------------------------------------------------------
+
+// thread per row of the colour's x-lines (slot k: line j = first + 2k);
+// the band has half-bandwidth 2 with its outer diagonals zero
+__global__ void cd_split_assemble_kernel(CdArgs A, double w, int first, int cnt, double* band,
+                                         double* rhs)
+{
+    const int n = A.n, m = n - 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)cnt * m) return;
+    const int k = (int)(t / m), r = (int)(t % m);
+    const int j = first + 2 * k, i = r + 1;
+    rhs[t] = defect_at(A, i, j);
+    const double h = A.h, e2 = A.eps / (h * h), kp = A.kappa;
+    const double own_y = A.b / h * (j >= 2 ? 0.25 * (3.0 - 3.0 * kp) : 0.5 * (1.0 - kp));
+    double* b = band + t * 5;
+    b[0] = 0.0;
+    b[1] = r >= 1 ? -e2 - w * A.a / h : 0.0;
+    b[2] = w * A.a / h + 4.0 * e2 + own_y;
+    b[3] = r <= m - 2 ? -e2 : 0.0;
+    b[4] = 0.0;
+}
+
+// u += omega sigma on the colour's x-lines
+__global__ void cd_split_update_kernel(int n, int first, int cnt, double omega,
+                                       const double* sigma, double* u)
+{
+    const int m = n - 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)cnt * m) return;
+    const int k = (int)(t / m), r = (int)(t % m);
+    const int j = first + 2 * k, i = r + 1;
+    u[(int64_t)i * n + j] += omega * sigma[t];
 }
 
 // max over the interior of |f - L_h u| (mode 0) or |f| (mode 1), as the bit
@@ -362,6 +405,99 @@ int cd_line_relax(paqif_handle handle, int n, double kappa, double eps, double a
             if (e) return e;
             hipLaunchKernelGGL(pq::cd_update_kernel, dim3(nb), dim3(256), 0, s, n, axis, omega,
                                sigma, u);
+            if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+        }
+        hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm);
+        hipLaunchKernelGGL(pq::cd_norm_kernel, dim3(nb), dim3(256), 0, s, A, 0, nrm);
+        if (!pq::hip_ok(hipGetLastError()) ||
+            hipMemcpyAsync(host, nrm, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PAQIF_EHIP;
+        double v;
+        memcpy(&v, &host[0], sizeof v);
+        res = v;
+        memcpy(&fmax, &host[1], sizeof fmax);
+        if (res <= tol * fmax || !std::isfinite(res)) break;
+    }
+    *iters = std::min(it, max_iter);
+    *defect = res;
+    return PAQIF_OK;
+}
+
+int cd_split_relax(paqif_handle handle, int n, int which, double kappa, double eps, double a,
+                   double b, double omega, double tol, int max_iter, const double* f, double* u,
+                   int32_t* iters, double* defect, void* workspace, void* stream)
+{
+    if (!handle || !pq::cd_valid(n, kappa, eps, a, b) || !(which == 0 || which == 1) ||
+        !(omega > 0.0 && omega < 2.0) || !(tol >= 0.0) || max_iter < 1 || !f || !u || !iters ||
+        !defect || !workspace)
+        return PAQIF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pq::CdLayout L = pq::cd_layout(n);
+    char* ws = static_cast<char*>(workspace);
+    const int m = n - 2;
+    const int64_t rows = (int64_t)m * m;
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offs);
+    double* band = reinterpret_cast<double*>(ws + L.band);
+    double* rhs = reinterpret_cast<double*>(ws + L.rhs);
+    double* sigma = reinterpret_cast<double*>(ws + L.sigma);
+    unsigned long long* nrm = reinterpret_cast<unsigned long long*>(ws + L.norm);
+    // implicit weight of the x-upwind difference (eq. 49: Ls1; eq. 48: Ls0)
+    const double w = which == 1 ? 0.5 * (2.0 - kappa) : 0.5 * (2.0 - kappa) + 0.25 * (1.0 - kappa);
+
+    pq::CdArgs A;
+    A.n = n;
+    A.kappa = kappa;
+    A.eps = eps;
+    A.a = a;
+    A.b = b;
+    A.h = 2.0 / (n - 1);
+    A.f = f;
+    A.u = u;
+
+    pq::LcpArgs la;
+    la.offsets = offs;
+    la.order = nullptr;
+    la.band = band;
+    la.b = rhs;
+    la.bounded = nullptr;
+    la.mode = LCP_LINEAR;
+    la.max_iter = 1;
+    la.refine_tol = 0.0;
+    la.u = sigma;
+    la.w = nullptr;
+    la.active_out = nullptr;
+    la.status = reinterpret_cast<int32_t*>(ws + L.lst);
+    la.iters = reinterpret_cast<int32_t*>(ws + L.lit);
+    la.rec = ws + L.rec;
+    la.act = reinterpret_cast<uint8_t*>(ws + L.act);
+    la.r = nullptr;
+    la.skip = nullptr;
+    la.warm = 0;
+
+    const unsigned nb = (unsigned)((rows + 255) / 256);
+    hipLaunchKernelGGL(pq::cd_offsets_kernel, dim3((m + 256) / 256), dim3(256), 0, s, m, offs);
+    hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm + 1);
+    hipLaunchKernelGGL(pq::cd_norm_kernel, dim3(nb), dim3(256), 0, s, A, 1, nrm + 1);
+    if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+    unsigned long long host[2];
+    const int layout = handle->layout[0][0];
+    int it = 0;
+    double res = INFINITY, fmax = 0.0;
+    for (it = 1; it <= max_iter; it++) {
+        for (int color = 1; color >= 0; color--) {
+            const int first = color == 1 ? 1 : 2;  // x-lines j = first, first + 2, ...
+            if (first > m) continue;
+            const int cnt = (m - first) / 2 + 1;
+            la.count = cnt;
+            const unsigned nbl = (unsigned)(((int64_t)cnt * m + 255) / 256);
+            hipLaunchKernelGGL(pq::cd_split_assemble_kernel, dim3(nbl), dim3(256), 0, s, A, w,
+                               first, cnt, band, rhs);
+            if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
+            int e = pq::dispatch_lcp(2, la, PREC_FP64, layout, s);
+            if (e) return e;
+            hipLaunchKernelGGL(pq::cd_split_update_kernel, dim3(nbl), dim3(256), 0, s, n, first,
+                               cnt, omega, sigma, u);
             if (!pq::hip_ok(hipGetLastError())) return PAQIF_EHIP;
         }
         hipLaunchKernelGGL(pq::cd_zero_kernel, dim3(1), dim3(1), 0, s, nrm);

@@ -13,6 +13,10 @@
     of iterations within 1e-10 of the oracle's (n = 13, 34), and on 9 x 9
     nodes the converged solution within 1e-10 with the iteration count
     within one;
+  * the x-line splittings Ls0 / Ls1 (two colours per sweep): the iterate
+    after a fixed number of sweeps within 1e-10 of the oracle's (n = 13, 34,
+    65), and on 33 x 33 nodes the converged solution within 1e-10 with the
+    sweep count within one;
   * argument checks.
 """
 import numpy as np
@@ -100,3 +104,41 @@ def test_ls3_converged_matches_oracle(gpu, kappa):
     assert res <= 1e-11 * o["fmax"]
     assert abs(it - o["iters"]) <= 1
     assert np.abs(u.cpu().numpy() - o["u"]).max() <= 1e-10 * np.abs(o["u"]).max()
+
+
+@pytest.mark.parametrize("n", [13, 34, 65])
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_split_fixed_iterations_match_oracle(gpu, n, which, kappa):
+    eps, omega, k = 1e-6, 0.7, 5
+    f, u = gpu.convdiff.example(n, eps)
+    it, _ = gpu.convdiff.split_relax(f, u, which, kappa, eps, omega=omega, tol=0.0, max_iter=k)
+    torch.cuda.synchronize()
+    assert it == k
+    ref = C.start(n)
+    fr = C.rhs(n, eps)
+    for _ in range(k):
+        ref = C.split_iteration(ref, fr, which, kappa, eps, omega)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_split_converged_matches_oracle(gpu, which, kappa):
+    n = 33
+    o = C.solve_split(n, which, kappa, omega=0.7, tol=1e-12, max_iter=2000)
+    assert o["defect"] <= 1e-12 * o["fmax"]
+    f, u = gpu.convdiff.example(n, 1e-6)
+    it, res = gpu.convdiff.split_relax(f, u, which, kappa, omega=0.7, tol=1e-12, max_iter=2000)
+    torch.cuda.synchronize()
+    assert res <= 1e-12 * o["fmax"]
+    assert abs(it - o["iters"]) <= 1
+    assert np.abs(u.cpu().numpy() - o["u"]).max() <= 1e-10 * np.abs(o["u"]).max()
+
+
+def test_split_invalid_arguments(gpu):
+    f, u = gpu.convdiff.example(17)
+    with pytest.raises(RuntimeError):
+        gpu.convdiff.split_relax(f, u, 2, 0.0)
+    with pytest.raises(RuntimeError):
+        gpu.convdiff.split_relax(f, u, 0, 1.0)

@@ -14,6 +14,10 @@
     and its entries equal the kappa stencil composed with the pattern by
     hand on a row far from the boundary; the iteration converges (slowly,
     as the paper warns) to the direct solution on 9 x 9 nodes.
+  * x-line splittings Ls0 / Ls1: the implicit line operator L0 equals the
+    coefficients printed in eqs. 48 / 49 (with b = 0, the terms the paper
+    prints); the two-colour and the lexicographic sweeps converge, under-
+    relaxed, to the direct solution.
 The absolute errors of the paper's printed table are not reproduced (the
 paper does not give a(x, y), b(x, y) nor its boundary closure): parity
 unpinned there.
@@ -107,3 +111,39 @@ def test_ls3_converges_to_the_direct_solution(kappa):
     assert r["defect"] <= 1e-11 * r["fmax"]
     d = C.solve(n, kappa, tol=1e-13, max_iter=500)
     assert np.abs(r["u"] - d["u"]).max() <= 1e-9 * np.abs(d["u"]).max()
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_split_line_operator_is_the_printed_one(which, kappa):
+    """Interior and first rows of L0 against eq. 48 (Ls0) / eq. 49 (Ls1):
+    u_{i-1}: -eps/h^2 - a/h w, u_i: a/h w + 4 eps/h^2, u_{i+1}: -eps/h^2 with
+    w = (2-k)/2 + (1-k)/4 = (5-3k)/4 for Ls0 (printed as a/(4h)(5-3k) and
+    a/h((2-k)/2 + (1-k)/4)) and w = (2-k)/2 for Ls1."""
+    n, eps, a = 11, 0.05, 1.3
+    _, h = C.grid(n)
+    band = C.split_line_band(n, 4, which, kappa, eps, a, 0.0)
+    k = kappa
+    if which == 0:
+        lo, di = -(eps / h ** 2 + a / (4 * h) * (5 - 3 * k)), a / h * ((2 - k) / 2 + (1 - k) / 4)
+    else:
+        lo, di = -a / h * (2 - k) / 2 - eps / h ** 2, a / h * (2 - k) / 2
+    di += 4 * eps / h ** 2
+    up = -eps / h ** 2
+    for r in (3, 0, n - 3):
+        ref = [0.0, lo if r > 0 else 0.0, di, up if r < n - 3 else 0.0, 0.0]
+        assert np.abs(band[r] - np.array(ref)).max() <= 1e-12 * abs(di), (r, band[r], ref)
+    # the y-convection's own coefficient joins the diagonal (b > 0)
+    band_b = C.split_line_band(n, 4, which, kappa, eps, a, 0.7)
+    assert abs(band_b[3, 2] - band[3, 2] - 0.7 / h * (3 - 3 * k) / 4) <= 1e-12 * abs(di)
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_split_sweeps_converge_to_the_direct_solution(which, kappa):
+    n = 13
+    d = C.solve(n, kappa, tol=1e-13, max_iter=500)
+    for lex in (False, True):
+        r = C.solve_split(n, which, kappa, omega=0.7, tol=1e-12, max_iter=2000, lexicographic=lex)
+        assert r["defect"] <= 1e-12 * r["fmax"], (lex, r["iters"])
+        assert np.abs(r["u"] - d["u"]).max() <= 1e-10 * np.abs(d["u"]).max()
