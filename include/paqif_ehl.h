@@ -138,8 +138,10 @@ int paqif_solve_factored(paqif_handle handle, const paqif_batch *batch, const vo
  *  mode LCP_LINEAR: u = A^{-1} b.
  *  mode LCP_CLIP  : u = max(0, A^{-1} b) on bounded rows (the paper's
  *                   projection of the AQIF solution onto u >= 0).
- *  mode LCP_EXACT : active sets A_0 = {}, solve with rows/columns of A_k
- *                   replaced by the identity and b = 0 there, w = A u - b,
+ *  mode LCP_EXACT : active sets A_0 (the handle's start rule, see
+ *                   paqif_set_start_sweeps), solve with the rows of A_k
+ *                   replaced by identity rows and b = 0 there (so u = 0 on
+ *                   A_k), w = A u - b,
  *                   A_{k+1} = {i in A_k : w_i > 0} u {i not in A_k : u_i < 0}
  *                   (bounded rows), until A_{k+1} = A_k or max_iter solves.
  *  prec       : PREC_FP64, or PREC_FP32_IR (FP32 factors; every solve is
@@ -199,15 +201,31 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * paqif_set_layout / paqif_get_layout: the layout used by paqif_solve_lcp
  * (and the EHL Newton drivers) for (q, prec) on this handle; PAQIF_EINVAL for
  * an unknown q, prec or layout.
+ * paqif_set_start_sweeps / paqif_get_start_sweeps: the starting active set
+ * of mode LCP_EXACT for (q, prec) on this handle: A_0 = {bounded i : u_i <=
+ * 0} for u after `sweeps` projected Jacobi sweeps from u = 0,
+ * u_i <- (b_i - sum_{j != i} a_ij u_j) / a_ii, clipped at 0 on bounded rows
+ * (0 or 1 sweep: A_0 = {bounded i : b_i <= 0}).  The solution does not
+ * depend on the start (the active-set iteration ends at the LCP's solution);
+ * the number of active-set solves does.  The sweeps run for the systems
+ * of the workgroups (four systems each in the row layout) whose largest
+ * system has at least 0.7 max_n / 2 elimination levels, the ones that set
+ * the launch's length; the others take the sign start.  0 <= sweeps <=
+ * PAQIF_MAX_START_SWEEPS; a new handle uses 4.  The sweeps read and write u
+ * and the workspace's record area.
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),
  * stores the fastest in the handle and, if times_ms (host, float[count]) is
- * not NULL, the measured times.  Arguments as for paqif_solve_lcp; u,
- * sys_status and workspace are used as scratch.
+ * not NULL, the measured times; in mode LCP_EXACT it then times the start
+ * sweeps 0, 2, 3, 4, 5, 6, 8 with that layout and keeps the fastest.  Arguments
+ * as for paqif_solve_lcp; u, sys_status and workspace are used as scratch.
  */
+#define PAQIF_MAX_START_SWEEPS 32
 int paqif_layout_count(int q);
 int paqif_set_layout(paqif_handle handle, int q, int prec, int layout);
 int paqif_get_layout(paqif_handle handle, int q, int prec);
+int paqif_set_start_sweeps(paqif_handle handle, int q, int prec, int sweeps);
+int paqif_get_start_sweeps(paqif_handle handle, int q, int prec);
 int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *band,
                    const double *b, const uint8_t *bounded, int mode, int prec, int max_iter,
                    double *u, int32_t *sys_status, void *workspace, void *stream,

@@ -83,6 +83,8 @@ def lib():
         "paqif_layout_count": ([ctypes.c_int], ctypes.c_int),
         "paqif_set_layout": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "paqif_get_layout": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "paqif_set_start_sweeps": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "paqif_get_start_sweeps": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "paqif_autotune": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
                             vp, vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "ehl_deformation_workspace_bytes": ([ctypes.POINTER(EhlGrid), ctypes.c_int],

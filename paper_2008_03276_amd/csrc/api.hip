@@ -106,6 +106,11 @@ static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const doubl
     a.r = prec == PREC_FP32_IR ? reinterpret_cast<double*>(ws + L.r_off) : nullptr;
     a.skip = nullptr;
     a.warm = 0;
+    a.sweeps = mode == LCP_EXACT ? handle->sweeps[pq::q_index(batch->q)][prec != 0] : 0;
+    // the workgroups with the batch's largest systems set the launch's
+    // length; the others start from the sign of b and leave them the memory
+    // bandwidth the sweeps need
+    a.sweep_min = (int)(0.7 * (double)(batch->max_n / 2));
     return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
                             (hipStream_t)stream);
 }
@@ -130,6 +135,7 @@ int paqif_create(paqif_handle* handle)
     for (int qi = 0; qi < 3; qi++) {
         h->layout[qi][PREC_FP64] = 3;
         h->layout[qi][PREC_FP32_IR] = 0;
+        h->sweeps[qi][PREC_FP64] = h->sweeps[qi][PREC_FP32_IR] = 4;
     }
     h->scratch = scratch_address(h->device);
     if (!h->scratch) {
@@ -268,6 +274,22 @@ int paqif_get_layout(paqif_handle handle, int q, int prec)
     return handle->layout[pq::q_index(q)][prec != 0];
 }
 
+int paqif_set_start_sweeps(paqif_handle handle, int q, int prec, int sweeps)
+{
+    if (!handle || pq::layouts_for(q) == 0) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if (sweeps < 0 || sweeps > PAQIF_MAX_START_SWEEPS) return PAQIF_EINVAL;
+    handle->sweeps[pq::q_index(q)][prec != 0] = sweeps;
+    return PAQIF_OK;
+}
+
+int paqif_get_start_sweeps(paqif_handle handle, int q, int prec)
+{
+    if (!handle || pq::layouts_for(q) == 0) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    return handle->sweeps[pq::q_index(q)][prec != 0];
+}
+
 int paqif_autotune(paqif_handle handle, const paqif_batch* batch, const double* band,
                    const double* b, const uint8_t* bounded, int mode, int prec, int max_iter,
                    double* u, int32_t* sys_status, void* workspace, void* stream,
@@ -305,6 +327,34 @@ int paqif_autotune(paqif_handle handle, const paqif_batch* batch, const double* 
         }
     }
     handle->layout[pq::q_index(batch->q)][prec != 0] = best;
+    // exact mode: then the start sweeps with that layout
+    if (st == PAQIF_OK && mode == LCP_EXACT) {
+        static const int cand[] = {0, 2, 3, 4, 5, 6, 8};
+        int& sw = handle->sweeps[pq::q_index(batch->q)][prec != 0];
+        int best_sw = sw;
+        float best_sw_ms = -1.0f;
+        for (int c : cand) {
+            if (st != PAQIF_OK) break;
+            sw = c;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && st == PAQIF_OK; rep++) {
+                if (hipEventRecord(e0, s) != hipSuccess) st = PAQIF_EHIP;
+                if (st == PAQIF_OK)
+                    st = paqif_solve_lcp(handle, batch, band, b, bounded, mode, prec, 1e-10,
+                                         max_iter, u, nullptr, nullptr, sys_status, nullptr,
+                                         workspace, stream);
+                if (st == PAQIF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                       hipEventSynchronize(e1) != hipSuccess ||
+                                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    st = PAQIF_EHIP;
+            }
+            if (st == PAQIF_OK && (best_sw_ms < 0.0f || ms < best_sw_ms)) {
+                best_sw = c;
+                best_sw_ms = ms;
+            }
+        }
+        sw = best_sw;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;

@@ -958,6 +958,66 @@ PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
     bmax = bm;
 }
 
+// Starting active set of the exact LCP: `sweeps` projected Jacobi sweeps
+// from u = 0, u_i <- (b_i - sum_{j != i} a_ij u_j) / a_ii, clipped at zero on
+// bounded rows, then A_0 = {bounded i : u_i <= 0} (one sweep gives the sign
+// of b).  Pure Jacobi: the sweeps alternate between the buffers x0 and x1
+// (every sweep reads the whole previous iterate); the return value is the
+// buffer with the last one.  Each lane takes R consecutive rows per pass,
+// all loads of a pass (clamped rows) issued before any is used; a workgroup
+// barrier separates the sweeps.  Called by every thread of the block.
+template <int Q, int LPS>
+PQ_DEV GLB_PTR(const double) start_sweeps(const SysView& v, bool live, GLB_PTR(const uint8_t) bnds,
+                                          bool hasb, GLB_PTR(double) x0, GLB_PTR(double) x1,
+                                          int ls, int sweeps)
+{
+    constexpr int BW = 2 * Q + 1;
+    constexpr int R = Q == 8 ? 4 : (Q == 4 ? 8 : 16);
+    constexpr int UW = R + 2 * Q;
+    GLB_PTR(double) src = x1;
+    GLB_PTR(double) dst = x0;
+    for (int s = 0; s < sweeps; s++) {
+        if (live) {
+            const int nm = v.n - 1;
+            for (int i0 = ls * R; i0 < v.n; i0 += R * LPS) {
+                double av[R][BW], uv[UW], bv[R];
+                uint32_t kv[R];
+#pragma unroll
+                for (int t = 0; t < UW; t++)
+                    uv[t] = s == 0 ? 0.0 : src[min(max(i0 - Q + t, 0), nm)];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int i = min(i0 + r, nm);
+#pragma unroll
+                    for (int d = 0; d < BW; d++) av[r][d] = v.band[(int64_t)i * BW + d];
+                    bv[r] = v.rhs[i];
+                    kv[r] = (uint32_t)bnds[hasb ? i : 0];
+                }
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int i = i0 + r;
+                    if (i < v.n) {
+                        double sum = bv[r];
+#pragma unroll
+                        for (int d = 0; d < BW; d++) {
+                            const int jcol = i + d - Q;
+                            if (d != Q && jcol >= 0 && jcol < v.n)
+                                sum = __builtin_fma(-av[r][d], uv[r + d], sum);
+                        }
+                        const double x = sum / av[r][Q];
+                        dst[i] = kv[r] != 0u ? fmax(x, 0.0) : x;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        GLB_PTR(double) t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
 // Whole LCP solve, one wave per SPW systems.
 template <int Q, int L, typename FT>
 __global__ void __launch_bounds__(64)
@@ -993,11 +1053,21 @@ __global__ void __launch_bounds__(64)
     GLB_PTR(FT) rec = GLB(FT, reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride);
 
     const bool exact = A.mode == LCP_EXACT;
-    // working active set: exact mode starts from A_0 = {bounded i : b_i <= 0}
-    // (the sign of b predicts the binding constraints of a diagonally
+    // working active set: exact mode starts from A_0 = {bounded i : u_i <= 0}
+    // for u after A.sweeps projected Jacobi sweeps (one sweep or none: the
+    // sign of b, which predicts the binding constraints of a diagonally
     // dominant system), or, warm, from the flags the caller left in act
     // restricted to bounded rows; the other modes start empty
     const bool warm = exact && A.warm;
+    const bool swept = exact && !warm && A.sweeps > 0 && kmax >= A.sweep_min;
+    GLB_PTR(const double) us = GLB(const double, A.b + off);
+    if (swept)
+        us = start_sweeps<Q, G::LPS>(
+            v, live, A.bounded ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags),
+            A.bounded != nullptr, GLB(double, A.u + off),
+            GLB(double, reinterpret_cast<double*>(reinterpret_cast<char*>(A.rec) +
+                                                  level_base(off, sys) * stride * sizeof(FT))),
+            ls, A.sweeps);
     if (live) {
         // 8 rows per lane per pass, loads (clamped rows) issued before use
         constexpr int R = 8;
@@ -1010,7 +1080,7 @@ __global__ void __launch_bounds__(64)
                 const int64_t g = off + min(i0 + r * G::LPS, nm);
                 bn[r] = A.bounded ? (uint32_t)A.bounded[g] : 1u;
                 pa[r] = warm ? (uint32_t)A.act[g] : 0u;
-                bv[r] = A.b[g];
+                bv[r] = us[g - off];
             }
 #pragma unroll
             for (int r = 0; r < R; r++) {
@@ -1439,10 +1509,15 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
     GLB_PTR(const uint8_t) bnds = A.bounded ? GLB(const uint8_t, A.bounded + off) : nullptr;
     const bool exact = A.mode == LCP_EXACT;
-    // working active set: exact mode starts from {bounded i : b_i <= 0}, or
-    // warm from the flags in act (bounded rows only)
+    // working active set: exact mode starts from {bounded i : u_i <= 0} for
+    // u after A.sweeps projected Jacobi sweeps (none: the sign of b), or warm
+    // from the flags in act (bounded rows only)
+    GLB_PTR(const double) us = bb;
+    if (exact && !A.warm && A.sweeps > 0 && group_max_int<64>(v.npair) >= A.sweep_min)
+        us = start_sweeps<Q, 1>(v, live, bnds ? bnds : GLB(const uint8_t, kOneFlags), bnds != nullptr,
+                                u, rec, 0, A.sweeps);
     for (int i = 0; i < v.n; i++)
-        act[i] = (exact && (bnds ? bnds[i] != 0 : true) && (A.warm ? act[i] != 0 : bb[i] <= 0.0));
+        act[i] = (exact && (bnds ? bnds[i] != 0 : true) && (A.warm ? act[i] != 0 : us[i] <= 0.0));
     const int max_it = exact ? max(A.max_iter, 1) : 1;
     int st = SYS_OK, it = 0;
     bool done = !live;
@@ -2104,6 +2179,14 @@ __global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
 
     const bool exact = A.mode == LCP_EXACT;
     const bool warm = exact && A.warm;
+    // starting active set as in paqif_lcp_kernel (projected Jacobi sweeps,
+    // their second buffer the system's record area)
+    const bool swept = exact && !warm && A.sweeps > 0 && kmax >= A.sweep_min;
+    GLB_PTR(const double) us = GLB(const double, A.b + off);
+    if (swept)
+        us = start_sweeps<Q, rows::LPS>(
+            v, live, A.bounded ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags),
+            A.bounded != nullptr, GLB(double, A.u + off), rec, ls, A.sweeps);
     if (live) {
         constexpr int R = 8;
         const int nm = v.n - 1;
@@ -2115,7 +2198,7 @@ __global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
                 const int64_t g = off + min(i0 + r * rows::LPS, nm);
                 bn[r] = A.bounded ? (uint32_t)A.bounded[g] : 1u;
                 pa[r] = warm ? (uint32_t)A.act[g] : 0u;
-                bv[r] = A.b[g];
+                bv[r] = us[g - off];
             }
 #pragma unroll
             for (int r = 0; r < R; r++) {

@@ -10,6 +10,7 @@ struct paqif_handle_s {
     int device;
     int cu_count;
     int layout[3][2];
+    int sweeps[3][2];  // start sweeps of the exact LCP per (q, precision)
     // device address of the library-owned scratch array on `device` (the
     // allocation-free LCP entry point), from hipGetSymbolAddress
     void* scratch;
@@ -44,6 +45,11 @@ struct LcpArgs {
     // per system: first row of its band rows in `band` (null = offsets[sys]);
     // lets several systems (e.g. one matrix with several right-hand sides) share rows
     const int64_t* band_off = nullptr;
+    // exact mode without a warm start: projected Jacobi sweeps that choose
+    // the starting active set (0: the sign of b), run by the workgroups
+    // whose largest system has at least sweep_min elimination levels
+    int sweeps = 0;
+    int sweep_min = 0;
 };
 
 struct FactorArgs {

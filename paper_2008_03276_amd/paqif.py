@@ -190,10 +190,23 @@ def get_layout(q, prec=B.PREC_FP64):
     return B.lib().paqif_get_layout(handle(), int(q), int(prec))
 
 
+def set_start_sweeps(q, prec, sweeps):
+    """Projected Jacobi sweeps that choose the exact LCP's starting active
+    set for (q, prec) on this process's handle (0: the sign of b)."""
+    B.check(B.lib().paqif_set_start_sweeps(handle(), int(q), int(prec), int(sweeps)),
+            "paqif_set_start_sweeps")
+
+
+def get_start_sweeps(q, prec=B.PREC_FP64):
+    return B.lib().paqif_get_start_sweeps(handle(), int(q), int(prec))
+
+
 def autotune(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None, max_iter=64,
              workspace=None):
     """Time every lane layout of the LCP kernel on this batch; the fastest is
-    kept in the handle for (q, prec).  Returns (chosen, times_ms)."""
+    kept in the handle for (q, prec); in exact mode the start sweeps are then
+    tuned with that layout (get_start_sweeps).  Returns (chosen layout,
+    times_ms per layout)."""
     _check_system_args(batch, band, b, bounded)
     nl = layout_count(batch.q)
     times = (ctypes.c_float * nl)()

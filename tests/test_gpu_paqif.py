@@ -1,5 +1,9 @@
 """PAQIF on the GPU vs the FP64 oracle (same seeded inputs, element by element).
 
+The exact mode's starting active set (projected Jacobi sweeps, a handle
+setting the autotuner tunes) changes only the number of active-set solves:
+the tests compare solutions and active sets exactly, solve counts loosely.
+
 Tolerances: the AQIF solution differs from the oracle only by rounding order
 (same elimination order, FP64); on these diagonally dominant systems
 (condition number below ~50) the relative difference stays below 1e-12.  The
@@ -266,3 +270,58 @@ def test_layouts_modes_bounded_and_edges(gpu, q, layout, mode):
         assert 1 <= it[s] <= o["iters"][s] + 2, s
         assert _relerr(u[a:b], o["u"][a:b]) < 1e-12, s
         assert np.abs(w[a:b] - o["w"][a:b]).max() <= 1e-12 * max(1.0, np.abs(o["w"][a:b]).max())
+
+
+@pytest.mark.parametrize("q", [2, 4, 8])
+@pytest.mark.parametrize("layout", [0, 3])
+@pytest.mark.parametrize("sweeps", [0, 1, 3, 8])
+def test_start_sweeps_keep_the_solution(gpu, q, layout, sweeps):
+    """The exact LCP's starting active set (projected Jacobi sweeps) changes
+    the number of active-set solves, not the solution: active set and u
+    against the oracle on ragged sizes with a bounded mask; with sweeps the
+    largest systems need fewer solves than from the sign of b."""
+    P = gpu
+    dev = torch.device("cuda")
+    sizes = [1, 2, 7, 64, 301, 1000, 2049, 2050, 1999]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=44 + q, sizes=sizes)
+    rng = np.random.default_rng(q)
+    bounded = (rng.random(len(f)) < 0.9).astype(np.uint8)
+    o = oracle.lcp_batch(q, offs, band, f, mode=2, bounded=bounded)
+    bt = P.paqif.Batch(offs, q, order="lpt")
+    keep_l, keep_s = P.paqif.get_layout(q, 0), P.paqif.get_start_sweeps(q, 0)
+    try:
+        P.paqif.set_layout(q, 0, layout)
+        P.paqif.set_start_sweeps(q, 0, sweeps)
+        r = P.paqif.solve_lcp(bt, torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev),
+                              mode=2, bounded=torch.as_tensor(bounded, device=dev))
+        torch.cuda.synchronize()
+    finally:
+        P.paqif.set_layout(q, 0, keep_l)
+        P.paqif.set_start_sweeps(q, 0, keep_s)
+    assert (r["status"].cpu().numpy() == 0).all()
+    assert (r["active"].cpu().numpy() == o["active"]).all()
+    assert _relerr(r["u"].cpu().numpy(), o["u"]) < 1e-12
+    it = r["iters"].cpu().numpy()
+    if sweeps >= 8:
+        big = np.array(sizes) >= 1999
+        assert it[big].max() <= 2, it
+
+
+def test_start_sweeps_argument_checks(gpu):
+    P = gpu
+    with pytest.raises(RuntimeError):
+        P.paqif.set_start_sweeps(4, 0, 33)
+    with pytest.raises(RuntimeError):
+        P.paqif.set_start_sweeps(3, 0, 2)
+    keep = P.paqif.get_start_sweeps(4, 1)
+    P.paqif.set_start_sweeps(4, 1, 6)
+    assert P.paqif.get_start_sweeps(4, 1) == 6
+    P.paqif.set_start_sweeps(4, 1, keep)
+
+
+@pytest.mark.parametrize("q", [2, 8])
+def test_start_sweeps_fp32_refined(gpu, q):
+    offs, g, o = _run(gpu, q, SIZES_RAGGED + [2049], 2, prec=1, seed=9)
+    assert (g["status"] == 0).all(), g["status"]
+    assert (g["active"] == o["active"]).all()
+    assert _relerr(g["u"], o["u"]) < 1e-9
