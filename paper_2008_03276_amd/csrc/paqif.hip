@@ -963,51 +963,72 @@ PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
 // bounded rows, then A_0 = {bounded i : u_i <= 0} (one sweep gives the sign
 // of b).  Pure Jacobi: the sweeps alternate between the buffers x0 and x1
 // (every sweep reads the whole previous iterate); the return value is the
-// buffer with the last one.  Each lane takes R consecutive rows per pass,
-// all loads of a pass (clamped rows) issued before any is used; a workgroup
-// barrier separates the sweeps.  Called by every thread of the block.
+// buffer with the last one.  Each lane takes R consecutive rows per stage,
+// all loads of a stage (clamped rows) issued together; a workgroup
+// barrier separates the sweeps; within a sweep the loads of the next stage
+// of rows are issued before the current stage is used.  Called by every
+// thread of the block.
 template <int Q, int LPS>
 PQ_DEV GLB_PTR(const double) start_sweeps(const SysView& v, bool live, GLB_PTR(const uint8_t) bnds,
                                           bool hasb, GLB_PTR(double) x0, GLB_PTR(double) x1,
                                           int ls, int sweeps)
 {
     constexpr int BW = 2 * Q + 1;
-    constexpr int R = Q == 8 ? 4 : (Q == 4 ? 8 : 16);
+    constexpr int R = Q == 8 ? 2 : (Q == 4 ? 4 : 8);  // rows per lane per stage
     constexpr int UW = R + 2 * Q;
+    struct Stage {
+        double a[R][BW], u[UW], b[R];
+        uint32_t k[R];
+    };
     GLB_PTR(double) src = x1;
     GLB_PTR(double) dst = x0;
+    GLB_PTR(double) sink = GLB(double, kSink) + (threadIdx.x & 63);
     for (int s = 0; s < sweeps; s++) {
-        if (live) {
+        if (live && v.n > 0) {
             const int nm = v.n - 1;
-            for (int i0 = ls * R; i0 < v.n; i0 += R * LPS) {
-                double av[R][BW], uv[UW], bv[R];
-                uint32_t kv[R];
+            const int step = R * LPS;
+            // raw loads of the rows i0 .. i0+R-1 (clamped: always valid)
+            auto load = [&](int i0, Stage& g) {
 #pragma unroll
                 for (int t = 0; t < UW; t++)
-                    uv[t] = s == 0 ? 0.0 : src[min(max(i0 - Q + t, 0), nm)];
+                    g.u[t] = s == 0 ? 0.0 : src[min(max(i0 - Q + t, 0), nm)];
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int i = min(i0 + r, nm);
 #pragma unroll
-                    for (int d = 0; d < BW; d++) av[r][d] = v.band[(int64_t)i * BW + d];
-                    bv[r] = v.rhs[i];
-                    kv[r] = (uint32_t)bnds[hasb ? i : 0];
+                    for (int d = 0; d < BW; d++) g.a[r][d] = v.band[(int64_t)i * BW + d];
+                    g.b[r] = v.rhs[i];
+                    g.k[r] = (uint32_t)bnds[hasb ? i : 0];
                 }
+            };
+            // new values of the rows; rows past the end go to the sink
+            auto update = [&](int i0, const Stage& g) {
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int i = i0 + r;
-                    if (i < v.n) {
-                        double sum = bv[r];
+                    double sum = g.b[r];
 #pragma unroll
-                        for (int d = 0; d < BW; d++) {
-                            const int jcol = i + d - Q;
-                            if (d != Q && jcol >= 0 && jcol < v.n)
-                                sum = __builtin_fma(-av[r][d], uv[r + d], sum);
-                        }
-                        const double x = sum / av[r][Q];
-                        dst[i] = kv[r] != 0u ? fmax(x, 0.0) : x;
+                    for (int d = 0; d < BW; d++) {
+                        const int jcol = i + d - Q;
+                        if (d != Q && jcol >= 0 && jcol < v.n)
+                            sum = __builtin_fma(-g.a[r][d], g.u[r + d], sum);
                     }
+                    const double x = sum / g.a[r][Q];
+                    GLB_PTR(double) p = i < v.n ? dst + i : sink;
+                    *p = g.k[r] != 0u ? fmax(x, 0.0) : x;
                 }
+            };
+            Stage A, B;
+            int i0 = ls * R;
+            load(i0, A);
+            while (i0 < v.n) {
+                load(i0 + step, B);  // the next stage's loads fly while A is used
+                update(i0, A);
+                i0 += step;
+                if (i0 >= v.n) break;
+                load(i0 + step, A);
+                update(i0, B);
+                i0 += step;
             }
         }
         __syncthreads();
@@ -2075,66 +2096,89 @@ PQ_DEV void back(const SysView& v, bool live, GLB_PTR(const double) rec0, GLB_PT
 
 // Residual pass of the row layout: w = A u - b with the original band and
 // the active-set update, as residual_update, but each lane takes R
-// consecutive rows per pass, so its u window is R + 2q values and its band
-// rows one contiguous run; all loads of a pass (clamped addresses) are issued
-// before any is used.
+// consecutive rows per stage, so its u window is R + 2q values and its band
+// rows one contiguous run; the loads of a stage (clamped addresses) are
+// issued together, the next stage's before the current one is used.
 template <int Q>
 PQ_DEV void residual(const SysView& v, bool live, const LcpArgs& A, int64_t off, int ls,
                      bool update, bool write_w, int& changes, int& nonfinite)
 {
     ls = launder(ls);
     constexpr int BW = 2 * Q + 1;
-    constexpr int R = Q == 8 ? 4 : (Q == 4 ? 8 : 16);
+    constexpr int R = Q == 8 ? 2 : (Q == 4 ? 4 : 8);  // rows per lane per stage
     constexpr int UW = R + 2 * Q;
     GLB_PTR(const double) u = GLB(const double, A.u + off);
     GLB_PTR(const double) bb = GLB(const double, A.b + off);
     GLB_PTR(const double) band = v.band;
     GLB_PTR(double) wout = A.w ? GLB(double, A.w + off) : nullptr;
+    const bool ww = write_w && wout != nullptr;
     const bool hasb = A.bounded != nullptr;
     GLB_PTR(const uint8_t) bnds =
         hasb ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags);
     GLB_PTR(uint8_t) act = GLB(uint8_t, A.act + off);
+    // stores of rows past the end (and w when it is not wanted) go to the
+    // sink: no store sits behind a branch
+    GLB_PTR(double) sinkd = GLB(double, kSink) + (threadIdx.x & 63);
+    GLB_PTR(uint8_t) sinkb = GLB(uint8_t, reinterpret_cast<uint8_t*>(kSink)) + (threadIdx.x & 63);
+    struct Stage {
+        double a[R][BW], u[UW], b[R];
+        uint32_t c[R], k[R];
+    };
     int ch = 0, nf = 0;
-    if (live) {
+    if (live && v.n > 0) {
         const int nm = v.n - 1;
-        for (int i0 = ls * R; i0 < v.n; i0 += R * LPS) {
-            double av[R][BW], uv[UW], bv[R];
-            uint32_t cv[R], kv[R];
+        const int step = R * LPS;
+        auto load = [&](int i0, Stage& g) {  // clamped rows: always valid addresses
 #pragma unroll
-            for (int t = 0; t < UW; t++) uv[t] = u[min(max(i0 - Q + t, 0), nm)];
+            for (int t = 0; t < UW; t++) g.u[t] = u[min(max(i0 - Q + t, 0), nm)];
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int i = min(i0 + r, nm);
 #pragma unroll
-                for (int d = 0; d < BW; d++) av[r][d] = band[(int64_t)i * BW + d];
-                bv[r] = bb[i];
-                cv[r] = act[i];
-                kv[r] = (uint32_t)bnds[hasb ? i : 0];
+                for (int d = 0; d < BW; d++) g.a[r][d] = band[(int64_t)i * BW + d];
+                g.b[r] = bb[i];
+                g.c[r] = act[i];
+                g.k[r] = (uint32_t)bnds[hasb ? i : 0];
             }
+        };
+        auto apply = [&](int i0, const Stage& g) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int i = i0 + r;
-                if (i < v.n) {
-                    double sum = 0.0;
+                const bool in = i < v.n;
+                double sum = 0.0;
 #pragma unroll
-                    for (int d = 0; d < BW; d++) {
-                        const int jcol = i + d - Q;
-                        sum = __builtin_fma(av[r][d], (jcol >= 0 && jcol < v.n) ? uv[r + d] : 0.0,
-                                            sum);
-                    }
-                    const double wi = sum - bv[r];
-                    const double ui = uv[r + Q];
-                    if (!isfinite(ui)) nf = 1;
-                    if (write_w && wout) wout[i] = wi;
-                    if (update) {
-                        const int bnd = kv[r] != 0u;
-                        const int cur = cv[r] != 0u;
-                        const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
-                        ch += (nxt != cur);
-                        act[i] = (uint8_t)nxt;
-                    }
+                for (int d = 0; d < BW; d++) {
+                    const int jcol = i + d - Q;
+                    sum = __builtin_fma(g.a[r][d], (jcol >= 0 && jcol < v.n) ? g.u[r + d] : 0.0,
+                                        sum);
+                }
+                const double wi = sum - g.b[r];
+                const double ui = g.u[r + Q];
+                if (in && !isfinite(ui)) nf = 1;
+                *((ww && in) ? wout + i : sinkd) = wi;
+                if (update) {
+                    const int bnd = g.k[r] != 0u;
+                    const int cur = g.c[r] != 0u;
+                    const int nxt = bnd ? (cur ? (wi > 0.0) : (ui < 0.0)) : 0;
+                    ch += (in && nxt != cur) ? 1 : 0;
+                    *(in ? act + i : sinkb) = (uint8_t)nxt;
                 }
             }
+        };
+        // two stages in flight: the next stage's loads are issued before the
+        // current one is used
+        Stage S0, S1;
+        int i0 = ls * R;
+        load(i0, S0);
+        while (i0 < v.n) {
+            load(i0 + step, S1);
+            apply(i0, S0);
+            i0 += step;
+            if (i0 >= v.n) break;
+            load(i0 + step, S0);
+            apply(i0, S1);
+            i0 += step;
         }
     }
     changes = group_sum_int<LPS>(ch);
