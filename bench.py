@@ -41,9 +41,18 @@ def mixed_bytes_per_row(q):
     return 8 * (2 * q + 1) + 8 + 8 + 2 * 4 * ((2 * q + 3) + 2 * q)
 
 
+def lcp_call_kernels(P, q, prec):
+    """Kernels of one exact paqif_solve_lcp call: the start sweeps (if the
+    handle runs any) and the solve."""
+    k = lcp_kernel_name(P, q, prec)
+    if P.paqif.get_start_sweeps(q, prec) > 0:
+        k = f"paqif_sweep_kernel<{q}> + " + k
+    return k
+
+
 def lcp_kernel_name(P, q, prec):
-    """Name of the kernel paqif_solve_lcp launches for (q, prec) under the
-    handle's current lane layout."""
+    """Name of the solve kernel paqif_solve_lcp launches for (q, prec) under
+    the handle's current lane layout."""
     lay = P.paqif.get_layout(q, prec)
     if prec == P.PREC_FP64 and lay == 3:
         return f"paqif_lcp_rows_kernel<{q}>"
@@ -55,17 +64,18 @@ def lcp_kernel_name(P, q, prec):
 
 
 def sweep_bytes(q, sizes, sweeps):
-    """Bytes of the exact LCP's start sweeps (projected Jacobi from u = 0):
-    per row and sweep the band 8(2q+1), b, the previous iterate (not in the
-    first sweep) and the new one.  Counted for the systems with at least
-    0.7 max_n / 2 levels (the sweeps run in the workgroups whose largest
-    system reaches that; smaller systems sharing such a workgroup are left
-    out, so the count is a lower bound)."""
+    """Algorithmic bytes of the exact LCP's start sweeps (projected Jacobi
+    from u = 0, paqif_sweep_kernel): its launches run up to 1 + 64/q sweeps
+    each with the band rows held on chip, so per row and launch the band
+    8(2q+1), b and the iterate written, plus the previous iterate read by
+    every launch after the first.  Counted for the systems with at least
+    0.7 (max_n // 2) elimination levels, the ones the sweeps run on."""
     if sweeps <= 0:
         return 0
+    launches = -(-sweeps // (1 + 64 // q))
     npair = sizes // 2
     rows = int(sizes[npair >= int(0.7 * (int(sizes.max()) // 2))].sum())
-    return rows * (sweeps * (8 * (2 * q + 1) + 24) - 8)
+    return rows * (launches * (8 * (2 * q + 1) + 16) + (launches - 1) * 8)
 
 
 def minimum_bytes_per_row(q):
@@ -188,9 +198,9 @@ def cpu_baseline(batches, sample, nthreads):
 
 
 def measured_traffic(kernel_q, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on this kernel and the current kernel sources
-    (else None)."""
+    """HBM bytes per solve call (summed over its kernels) from the committed
+    counter summary, if it was taken on these kernels and the current kernel
+    sources (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "paqif_lcp_q8_hbm_counters.md")
@@ -747,7 +757,7 @@ def main():
                         iters_max=int(iters.max()), start_sweeps=sw,
                         sweep_bytes_gb=round(bytes_sweeps / 1e9, 4),
                         status_ok=bool((status == 0).all()),
-                        kernel=lcp_kernel_name(P, q, P.PREC_FP64),
+                        kernel=lcp_call_kernels(P, q, P.PREC_FP64),
                         active_frac=float(r["active"].float().mean().item()),
                         gbs=bytes_alg / (avg_ms / 1e3) / 1e9, bytes=bytes_alg)
 
@@ -793,7 +803,7 @@ def main():
                               statuses={str(int(k)): int(v)
                                         for k, v in zip(*np.unique(st, return_counts=True))},
                               gbs=round(bytes_alg / (avg / 1e3) / 1e9, 2),
-                              kernel=lcp_kernel_name(P, q, P.PREC_FP32_IR), bytes=bytes_alg)
+                              kernel=lcp_call_kernels(P, q, P.PREC_FP32_IR), bytes=bytes_alg)
     domm = max(QS, key=lambda q: per_q_mixed[q]["avg_ms"])
     mixed_roof = dict(bound="hbm", achieved=per_q_mixed[domm]["gbs"], peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=round(per_q_mixed[domm]["gbs"] / HBM_PEAK_GBS, 4),
@@ -808,12 +818,13 @@ def main():
     copy_gbs = copy_bandwidth(torch)
 
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
-    dom_kernel = lcp_kernel_name(P, dom, P.PREC_FP64)
-    tr = measured_traffic(dom, dom_kernel)
+    # the committed counter summary names the call's kernels joined by "+"
+    tr = measured_traffic(dom, per_q[dom]["kernel"].replace(" ", ""))
     roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
                 traffic=None if tr is None else round(tr / 1e9, 3),
-                kernel=dom_kernel,
+                kernel=per_q[dom]["kernel"],
+                timing="HIP events around each solve call (its launches on the stream)",
                 algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
     rows_it = (per_q[dom]["bytes"] - per_q[dom]["sweep_bytes_gb"] * 1e9) / \
         algorithmic_bytes_per_row(dom)

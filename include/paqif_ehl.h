@@ -208,16 +208,19 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * (0 or 1 sweep: A_0 = {bounded i : b_i <= 0}).  The solution does not
  * depend on the start (the active-set iteration ends at the LCP's solution);
  * the number of active-set solves does.  The sweeps run for the systems
- * of the workgroups (four systems each in the row layout) whose largest
- * system has at least 0.7 max_n / 2 elimination levels, the ones that set
- * the launch's length; the others take the sign start.  0 <= sweeps <=
- * PAQIF_MAX_START_SWEEPS; a new handle uses 4.  The sweeps read and write u
- * and the workspace's record area.
+ * with at least 0.7 max_n / 2 elimination levels, the ones that set the
+ * solve's length (the others take the sign start), as a kernel of their
+ * own before the solve: each workgroup holds 256 rows of a system and the
+ * band rows within (sweeps - 1) q of them in LDS and runs the sweeps there
+ * (one band read for up to 1 + 64 / q sweeps).  0 <= sweeps <=
+ * PAQIF_MAX_START_SWEEPS; a new handle uses 12 for q = 2 and 8 for q = 4
+ * and 8.  The sweeps write u (and,
+ * above 1 + 64 / q sweeps, the workspace's record area).
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),
  * stores the fastest in the handle and, if times_ms (host, float[count]) is
  * not NULL, the measured times; in mode LCP_EXACT it then times the start
- * sweeps 0, 2, 3, 4, 5, 6, 8 with that layout and keeps the fastest.  Arguments
+ * sweeps 0, 2, 4, 6, 8, 12, 16 with that layout and keeps the fastest.  Arguments
  * as for paqif_solve_lcp; u, sys_status and workspace are used as scratch.
  */
 #define PAQIF_MAX_START_SWEEPS 32

@@ -44,11 +44,12 @@ def lib():
                                          ctypes.POINTER(ctypes.c_int)]
         L.or_lcp_pgs.argtypes = [i64, i32, d, d, u8, ctypes.c_double, i32, ctypes.c_double, d,
                                  ctypes.POINTER(ctypes.c_int)]
+        L.or_start_sweeps.argtypes = [i64, i32, d, d, u8, i32, d]
         L.or_lcp_batch.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int64), d, d, u8, i32, i32,
                                    d, d, u8, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), i32]
         for f in (L.or_aqif_solve, L.or_aqif_factor_dense, L.or_lcp_solve, L.or_lcp_solve_start,
-                  L.or_lcp_pgs, L.or_lcp_batch):
+                  L.or_lcp_pgs, L.or_lcp_batch, L.or_start_sweeps):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -135,6 +136,41 @@ def lcp_solve_start(band, f, bounded=None, start=None, max_iter=64):
     st = lib().or_lcp_solve_start(n, q, _dp(band), _dp(f), _u8(bounded), _u8(start), max_iter,
                                   _dp(u), _dp(w), _u8(act), ctypes.byref(it))
     return dict(u=u, w=w, active=act, iters=it.value, status=st)
+
+
+def start_sweeps(band, f, bounded=None, k=1):
+    """Iterate after k projected Jacobi sweeps from u = 0 (the exact LCP's
+    start rule: A_0 = {bounded i : u_i <= 0}); not part of the paper's
+    method."""
+    band = _f64(band)
+    n, wd = band.shape
+    q = (wd - 1) // 2
+    f = _f64(f)
+    bounded = _mask(bounded)
+    u = np.zeros(n)
+    lib().or_start_sweeps(n, q, _dp(band), _dp(f), _u8(bounded), int(k), _dp(u))
+    return u
+
+
+def lcp_start_sets(q, offsets, band, f, bounded=None, k=0, frac=0.7):
+    """Per-system starting active sets of a batch: the systems with at
+    least int(frac * (max_n // 2)) elimination levels (n // 2) from k start
+    sweeps, the others (and all for k == 0) from the sign of f."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    band = _f64(band).reshape(-1, 2 * q + 1)
+    f = _f64(f)
+    bnd = np.ones(len(f), dtype=bool) if bounded is None else np.asarray(bounded) != 0
+    sizes = np.diff(offsets)
+    lmin = int(frac * float(int(sizes.max()) // 2)) if len(sizes) else 0
+    start = np.zeros(len(f), dtype=np.uint8)
+    for s in range(len(sizes)):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        if k > 0 and (b - a) // 2 >= lmin:
+            u = start_sweeps(band[a:b], f[a:b], None if bounded is None else bounded[a:b], k)
+            start[a:b] = bnd[a:b] & (u <= 0.0)
+        else:
+            start[a:b] = bnd[a:b] & (f[a:b] <= 0.0)
+    return start
 
 
 def lcp_pgs(band, f, bounded=None, omega=1.0, max_sweeps=100000, tol=1e-14):

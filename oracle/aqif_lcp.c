@@ -447,6 +447,39 @@ int or_lcp_solve_start(int64_t n, int q, const double *band, const double *f,
 }
 
 /*
+ * Start sweeps of the exact LCP (a starting active set, not part of the
+ * paper's method): k projected Jacobi sweeps from u = 0,
+ *   u_i <- (f_i - sum_{j != i} a_ij u_j) / a_ii, clipped at 0 on bounded rows,
+ * every sweep reading only the previous iterate.  The sum runs over the
+ * row's band columns in increasing order, each term one fused
+ * multiply-add.  The active-set iteration may start from
+ * A_0 = {bounded i : u_i <= 0}.
+ */
+int or_start_sweeps(int64_t n, int q, const double *band, const double *f,
+                    const uint8_t *bounded, int k, double *u)
+{
+    const int bw = 2 * q + 1;
+    double *prev = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    for (int64_t i = 0; i < n; i++) u[i] = 0.0;
+    for (int s = 0; s < k; s++) {
+        memcpy(prev, u, (size_t)n * sizeof(double));
+        for (int64_t i = 0; i < n; i++) {
+            double sum = f[i];
+            for (int d = 0; d < bw; d++) {
+                const int64_t j = i + d - q;
+                if (d == q || j < 0 || j >= n) continue;
+                sum = fma(-band[i * bw + d], prev[j], sum);
+            }
+            const double x = sum / band[i * bw + q];
+            const int b = bounded ? bounded[i] != 0 : 1;
+            u[i] = b ? fmax(x, 0.0) : x;
+        }
+    }
+    free(prev);
+    return OR_OK;
+}
+
+/*
  * Projected SOR for the banded LCP (Cryer's projected splitting
  * iteration): sweep i = 0..n-1,
  *   u_i <- max(0, u_i + omega * (f_i - (A u)_i) / a_ii)   (bounded rows)

@@ -958,85 +958,159 @@ PQ_DEV void eff_residual(SysView v, bool live, GLB_PTR(const double) bsys,
     bmax = bm;
 }
 
-// Starting active set of the exact LCP: `sweeps` projected Jacobi sweeps
-// from u = 0, u_i <- (b_i - sum_{j != i} a_ij u_j) / a_ii, clipped at zero on
-// bounded rows, then A_0 = {bounded i : u_i <= 0} (one sweep gives the sign
-// of b).  Pure Jacobi: the sweeps alternate between the buffers x0 and x1
-// (every sweep reads the whole previous iterate); the return value is the
-// buffer with the last one.  Each lane takes R consecutive rows per stage,
-// all loads of a stage (clamped rows) issued together; a workgroup
-// barrier separates the sweeps; within a sweep the loads of the next stage
-// of rows are issued before the current stage is used.  Called by every
-// thread of the block.
-template <int Q, int LPS>
-PQ_DEV GLB_PTR(const double) start_sweeps(const SysView& v, bool live, GLB_PTR(const uint8_t) bnds,
-                                          bool hasb, GLB_PTR(double) x0, GLB_PTR(double) x1,
-                                          int ls, int sweeps)
+// Sweeps per launch of paqif_sweep_kernel: a halo of at most 64 rows per
+// side of the 512 rows a workgroup holds.
+template <int Q>
+constexpr int sweep_pass_max()
+{
+    return 1 + 64 / Q;
+}
+
+// Starting iterate of the exact LCP's active-set loop: kp projected Jacobi
+// sweeps, u_i <- (b_i - sum_{j != i} a_ij u_j) / a_ii, clipped at zero on
+// bounded rows, from the iterate in src (null: u = 0, so that the first
+// sweep gives b_i / a_ii); the solve kernels then start from
+// A_0 = {bounded i : u_i <= 0}.  The sweeps are pure Jacobi, every row
+// independent, so a workgroup takes SWR = 2 SWC consecutive rows of one
+// system, two per thread, whose band rows stay in the thread's registers
+// for all kp sweeps, and runs them with the iterates in LDS.  Sweep s is
+// exact on the rows at least s q from the held range's ends (the others
+// read stale values at the ends), so the workgroup writes the rows at least
+// (kp - 1) q inside, its core of SWR - 2 (kp - 1) q rows (temporal
+// blocking: one read of the band for kp sweeps).  Rows outside the system
+// hold zero.  Systems with fewer than sweep_min elimination levels are
+// left alone (grid: cores x systems).
+template <int Q>
+__global__ void __launch_bounds__(SWC) paqif_sweep_kernel(SweepArgs S)
 {
     constexpr int BW = 2 * Q + 1;
-    constexpr int R = Q == 8 ? 2 : (Q == 4 ? 4 : 8);  // rows per lane per stage
-    constexpr int UW = R + 2 * Q;
-    struct Stage {
-        double a[R][BW], u[UW], b[R];
-        uint32_t k[R];
-    };
-    GLB_PTR(double) src = x1;
-    GLB_PTR(double) dst = x0;
-    GLB_PTR(double) sink = GLB(double, kSink) + (threadIdx.x & 63);
-    for (int s = 0; s < sweeps; s++) {
-        if (live && v.n > 0) {
-            const int nm = v.n - 1;
-            const int step = R * LPS;
-            // raw loads of the rows i0 .. i0+R-1 (clamped: always valid)
-            auto load = [&](int i0, Stage& g) {
+    constexpr int R = 2;                // rows per thread
+    constexpr int SWR = R * SWC;        // rows held by the workgroup
+    constexpr int UB = SWR + 2 * Q;     // iterate buffer: held rows and q beyond each end
+    __shared__ __attribute__((aligned(16))) double ubuf[2][UB];
+    const int sys = blockIdx.y;
+    const int64_t off = S.offsets[sys];
+    const int n = (int)(S.offsets[sys + 1] - off);
+    const int kp = S.kp;
+    const int H = (kp - 1) * Q;         // rows of the held range outside the core
+    const int C = SWR - 2 * H;          // core rows
+    const int c0 = blockIdx.x * C;
+    if (n / 2 < S.sweep_min || c0 >= n) return;  // the whole workgroup
+    const int blo = c0 - H;                      // first held row (may be < 0)
+    const int i0 = blo + R * (int)threadIdx.x;   // this thread's first row
+    const int64_t boff = S.band_off ? S.band_off[sys] : off;
+    const bool hasu = S.src != nullptr;
+
+    // this thread's rows (clamped loads; rows outside the system are
+    // computed from a real row and then replaced by zero), and the source
+    // iterate on the buffer's rows blo - q .. blo + SWR + q - 1
+    double a[R][BW], bv[R];
+    uint32_t kb[R];
+    constexpr int PU = (UB + SWC - 1) / SWC;
+    double ru[PU];
+    {
+        GLB_PTR(const double) gb = GLB(const double, S.band + boff * BW);
+        GLB_PTR(const double) gr = GLB(const double, S.b + off);
+        GLB_PTR(const uint8_t) gk =
+            S.bounded ? GLB(const uint8_t, S.bounded + off) : GLB(const uint8_t, kOneFlags);
+        GLB_PTR(const double) gs = GLB(const double, (hasu ? S.src : S.b) + off);
 #pragma unroll
-                for (int t = 0; t < UW; t++)
-                    g.u[t] = s == 0 ? 0.0 : src[min(max(i0 - Q + t, 0), nm)];
+        for (int r = 0; r < R; r++) {
+            const int ic = min(max(i0 + r, 0), n - 1);
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const int i = min(i0 + r, nm);
+            for (int d = 0; d < BW; d++) a[r][d] = gb[(int64_t)ic * BW + d];
+            // band entries of columns outside the system (padding) are not
+            // part of A
 #pragma unroll
-                    for (int d = 0; d < BW; d++) g.a[r][d] = v.band[(int64_t)i * BW + d];
-                    g.b[r] = v.rhs[i];
-                    g.k[r] = (uint32_t)bnds[hasb ? i : 0];
-                }
-            };
-            // new values of the rows; rows past the end go to the sink
-            auto update = [&](int i0, const Stage& g) {
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const int i = i0 + r;
-                    double sum = g.b[r];
-#pragma unroll
-                    for (int d = 0; d < BW; d++) {
-                        const int jcol = i + d - Q;
-                        if (d != Q && jcol >= 0 && jcol < v.n)
-                            sum = __builtin_fma(-g.a[r][d], g.u[r + d], sum);
-                    }
-                    const double x = sum / g.a[r][Q];
-                    GLB_PTR(double) p = i < v.n ? dst + i : sink;
-                    *p = g.k[r] != 0u ? fmax(x, 0.0) : x;
-                }
-            };
-            Stage A, B;
-            int i0 = ls * R;
-            load(i0, A);
-            while (i0 < v.n) {
-                load(i0 + step, B);  // the next stage's loads fly while A is used
-                update(i0, A);
-                i0 += step;
-                if (i0 >= v.n) break;
-                load(i0 + step, A);
-                update(i0, B);
-                i0 += step;
+            for (int d = 0; d < BW; d++) {
+                const int j = ic + d - Q;
+                if (d != Q && (j < 0 || j >= n)) a[r][d] = 0.0;
             }
+            bv[r] = gr[ic];
+            kb[r] = (uint32_t)gk[S.bounded ? ic : 0];
         }
-        __syncthreads();
-        GLB_PTR(double) t = src;
-        src = dst;
-        dst = t;
+#pragma unroll
+        for (int t = 0; t < PU; t++)
+            ru[t] = gs[min(max(blo - Q + (int)threadIdx.x + t * SWC, 0), n - 1)];
     }
-    return src;
+#pragma unroll
+    for (int t = 0; t < PU; t++) {
+        const int e = (int)threadIdx.x + t * SWC;
+        const int i = blo - Q + e;
+        if (e < UB) ubuf[0][e] = (hasu && i >= 0 && i < n) ? ru[t] : 0.0;
+    }
+    // rows outside the system hold zero
+    bool in[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) in[r] = i0 + r >= 0 && i0 + r < n;
+    __syncthreads();
+    int cur = 0;
+    for (int sw = 0; sw < kp; sw++) {
+        const double* up = ubuf[cur];
+        double* un = ubuf[cur ^ 1];
+        // window: rows i0 - q .. i0 + R - 1 + q (buffer index R t ..)
+        double w[R + 2 * Q];
+#pragma unroll
+        for (int k = 0; k < R + 2 * Q; k += 2) {
+            const double2 p = *reinterpret_cast<const double2*>(up + R * threadIdx.x + k);
+            w[k] = p.x;
+            w[k + 1] = p.y;
+        }
+        double x[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            double sum = bv[r];
+#pragma unroll
+            for (int d = 0; d < BW; d++)
+                if (d != Q) sum = __builtin_fma(-a[r][d], w[r + d], sum);
+            const double v = sum / a[r][Q];
+            x[r] = in[r] ? (kb[r] != 0u ? fmax(v, 0.0) : v) : 0.0;
+        }
+        *reinterpret_cast<double2*>(un + Q + R * threadIdx.x) = make_double2(x[0], x[1]);
+        __syncthreads();
+        cur ^= 1;
+    }
+    // the core rows c0 .. c0 + C - 1 (within the system)
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = i0 + r;
+        if (i >= c0 && i < c0 + C && i < n) S.dst[off + i] = ubuf[cur][Q + R * threadIdx.x + r];
+    }
+}
+
+// All k sweeps: ceil(k / sweep_pass_max) launches alternating between tmp
+// and u so that the last one writes u.
+template <int Q>
+static int launch_sweeps(const LcpArgs& a, int max_n, double* tmp, hipStream_t s)
+{
+    const int k = a.sweeps;
+    if (k <= 0 || a.count <= 0 || max_n <= 0) return PAQIF_OK;
+    constexpr int KP = sweep_pass_max<Q>();
+    const int passes = (k + KP - 1) / KP;
+    SweepArgs S;
+    S.count = a.count;
+    S.offsets = a.offsets;
+    S.band_off = a.band_off;
+    S.band = a.band;
+    S.b = a.b;
+    S.bounded = a.bounded;
+    S.sweep_min = a.sweep_min;
+    const double* src = nullptr;
+    int left = k;
+    for (int p = 0; p < passes; p++) {
+        const int kp = left - (passes - 1 - p) * KP > KP ? KP : left - (passes - 1 - p) * KP;
+        double* dst = ((passes - 1 - p) % 2 == 0) ? a.u : tmp;
+        S.src = src;
+        S.dst = dst;
+        S.kp = kp;
+        const int core = 2 * SWC - 2 * (kp - 1) * Q;  // rows written per workgroup
+        const dim3 grid((max_n + core - 1) / core, a.count);
+        hipLaunchKernelGGL((paqif_sweep_kernel<Q>), grid, dim3(SWC), 0, s, S);
+        if (!hip_ok(hipGetLastError())) return PAQIF_EHIP;
+        src = dst;
+        left -= kp;
+    }
+    return PAQIF_OK;
 }
 
 // Whole LCP solve, one wave per SPW systems.
@@ -1080,15 +1154,8 @@ __global__ void __launch_bounds__(64)
     // dominant system), or, warm, from the flags the caller left in act
     // restricted to bounded rows; the other modes start empty
     const bool warm = exact && A.warm;
-    const bool swept = exact && !warm && A.sweeps > 0 && kmax >= A.sweep_min;
-    GLB_PTR(const double) us = GLB(const double, A.b + off);
-    if (swept)
-        us = start_sweeps<Q, G::LPS>(
-            v, live, A.bounded ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags),
-            A.bounded != nullptr, GLB(double, A.u + off),
-            GLB(double, reinterpret_cast<double*>(reinterpret_cast<char*>(A.rec) +
-                                                  level_base(off, sys) * stride * sizeof(FT))),
-            ls, A.sweeps);
+    const bool swept = exact && !warm && A.sweeps > 0 && live && v.npair >= A.sweep_min;
+    GLB_PTR(const double) us = GLB(const double, (swept ? A.u : A.b) + off);
     if (live) {
         // 8 rows per lane per pass, loads (clamped rows) issued before use
         constexpr int R = 8;
@@ -1533,10 +1600,8 @@ __global__ void __launch_bounds__(64) paqif_lcp_lane_kernel(LcpArgs A)
     // working active set: exact mode starts from {bounded i : u_i <= 0} for
     // u after A.sweeps projected Jacobi sweeps (none: the sign of b), or warm
     // from the flags in act (bounded rows only)
-    GLB_PTR(const double) us = bb;
-    if (exact && !A.warm && A.sweeps > 0 && group_max_int<64>(v.npair) >= A.sweep_min)
-        us = start_sweeps<Q, 1>(v, live, bnds ? bnds : GLB(const uint8_t, kOneFlags), bnds != nullptr,
-                                u, rec, 0, A.sweeps);
+    const bool swept = exact && !A.warm && A.sweeps > 0 && live && v.npair >= A.sweep_min;
+    GLB_PTR(const double) us = swept ? GLB(const double, u) : bb;
     for (int i = 0; i < v.n; i++)
         act[i] = (exact && (bnds ? bnds[i] != 0 : true) && (A.warm ? act[i] != 0 : us[i] <= 0.0));
     const int max_it = exact ? max(A.max_iter, 1) : 1;
@@ -1638,6 +1703,12 @@ struct RG {
     static constexpr int SB = S * Q;                          // levels per superblock (8)
     static constexpr int RB = 2 * Q + 2;  // LDS refill buffer: effective band row + a zero
     static constexpr int BSB = 8;         // back-solve levels per prefetch superblock
+    // discard area of the staging writes: lane l's base is 2l doubles in,
+    // and its writes reach up to DUM doubles past it (a pivot row's 2q
+    // values, or the three extras pairs) into the next lanes' areas, which
+    // is harmless since nothing reads it; one instruction's 64 stores stay
+    // distinct and 16 bytes apart (no bank conflicts)
+    static constexpr int DUM = N2 > 6 ? N2 : 6;
 };
 
 // Calls f(std::integral_constant<int, I>) for I = 0 .. N-1 (compile-time
@@ -1675,6 +1746,21 @@ PQ_DEV void fmac_bcast(double& acc, double src, double mul)
                      : "v"(src), "v"(mul), "n"(N));
     else
         asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(src), "v"(mul), "n"(N));
+}
+
+// acc -= (value of src in lane N of the row) * mul: the same instruction
+// with the negation modifier on its DPP source (exactly fma(-src, mul, acc)).
+template <int N, bool NOP = false>
+PQ_DEV void fmsc_bcast(double& acc, double src, double mul)
+{
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(src), "v"(mul), "n"(N));
+    else
+        asm volatile("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                      : "+v"(acc)
                      : "v"(src), "v"(mul), "n"(N));
 }
@@ -1751,6 +1837,13 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
         }
         y = bef(ia);
     }
+    // a frontier row outside the system is an identity row (1 in its own
+    // slot): the levels past the system's last one then pivot on identity
+    // blocks, so a singular pivot can only be a real one
+    if (slot && !(ia >= 0 && ia < v.n)) {
+#pragma unroll
+        for (int cc = 0; cc < N2; cc++) f[cc] = cc == a ? 1.0 : 0.0;
+    }
     // refill buffers: block r's row goes to buffer r mod (S+1), so the rows
     // of the S blocks of a superblock and the row before them coexist; the
     // lane's initial row is block -1's (buffer S)
@@ -1811,7 +1904,6 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
     constexpr int NST = (NPAIR + LPS - 1) / LPS;  // copy pairs per lane per superblock
     GLB_PTR(double) sink = GLB(double, kSink) + 2 * (threadIdx.x & 63);
     LDS_PTR(double) dum = ldum + 2 * (threadIdx.x & 63);
-    const int xp = a % 3;  // extras pair written by lanes 0..2: (i11,i12), (i21,i22), (y1,y2)
     LDS_PTR(double) stg = lrec;
 
     // ---- refill rows of the superblock at level kn+1 (raw loads in rband):
@@ -1827,7 +1919,8 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
         for (int s = 0; s < S; s++) {
             const bool ok = rval[s];
             const double keep = (ok && rpin[s] == 0u) ? 1.0 : 0.0;
-            const double one = (ok && rpin[s] != 0u) ? 1.0 : 0.0;
+            // pinned rows and rows outside the system: identity rows
+            const double one = (!ok || rpin[s] != 0u) ? 1.0 : 0.0;
             int bi = bbase + s;
             bi = bi > S ? bi - (S + 1) : bi;
             LDS_PTR(double) buf = lbuf + bi * RB;
@@ -1877,8 +1970,6 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
             constexpr int s = decltype(SS)::value;
             static_for<Q>([&](auto JJ) {
                 constexpr int j = decltype(JJ)::value;
-                const int k = kb + s * Q + j + 1;
-                const bool act = live && k <= v.npair;
                 const bool isref = slot && c == j;
                 const double cv = cvl[s][j];  // entry of the lane's row in the entering column
                 // pivot data from lanes j and q+j
@@ -1887,7 +1978,7 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
                 const double y1 = bcast<j>(y), y2 = bcast<Q + j>(y);
                 const double E0 = bcast<j>(epub), E2 = bcast<Q + j>(epub);
                 const double det = P11 * P22 - P12 * P21;
-                if (act && !(det != 0.0 && isfinite(det))) bad = true;
+                if (!(det != 0.0 && isfinite(det))) bad = true;
                 // 1/det: hardware reciprocal refined by two Newton steps
                 const double r0 = __builtin_amdgcn_rcp(det);
                 const double r1 = __builtin_fma(r0, __builtin_fma(-det, r0, 1.0), r0);
@@ -1896,8 +1987,9 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
                 // multipliers of this lane's row (the refilled lane: of its new row)
                 const double wj = isref ? wjs[s] : f[j];
                 const double wq = isref ? wqs[s] : f[Q + j];
-                const double n1 = -(wj * i11 + wq * i21);
-                const double n2 = -(wj * i12 + wq * i22);
+                // (negated multipliers: the update subtracts)
+                const double n1 = wj * i11 + wq * i21;
+                const double n2 = wj * i12 + wq * i22;
                 // rank-2 update into g (base: own row, or the refilled row); the
                 // next level's pivot columns first, so that its pivot block can be
                 // formed while the other columns are updated
@@ -1908,18 +2000,20 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
                     constexpr int cc = t == 0 ? jn : (t == 1 ? Q + jn : (t - 2 < jn ? t - 2 : (t - 2 < Q + jn - 1 ? t - 1 : t)));
                     if constexpr (cc != j && cc != Q + j) {
                         g[cc] = isref ? nr[s][cc] : f[cc];
-                        fmac_bcast<j, t == 0>(g[cc], f[cc], n1);
-                        fmac_bcast<Q + j>(g[cc], f[cc], n2);
+                        fmsc_bcast<j, t == 0>(g[cc], f[cc], n1);
+                        fmsc_bcast<Q + j>(g[cc], f[cc], n2);
                     }
                 });
-                g[j] = __builtin_fma(E0, n1, cv * lmask);
-                g[Q + j] = __builtin_fma(E2, n2, cv * rmask);
+                g[j] = __builtin_fma(-E0, n1, cv * lmask);
+                g[Q + j] = __builtin_fma(-E2, n2, cv * rmask);
                 // record (staged): the pivot lanes write their rows (Z0 rows p1,
-                // p2 over the slots after the level), lanes 0..2 of the row one
-                // pair each of the inverse and y
+                // p2 over the slots after the level), lane 0 of the row the
+                // inverse and y
                 {
                     constexpr int jj = s * Q + j;
-                    LDS_PTR(double) zr = stg + jj * ZR + (left ? 0 : N2);
+                    // one base per level (the staging row or the lane's own
+                    // discard area), the pairs at constant offsets from it
+                    LDS_PTR(double) zr = isref ? stg + jj * ZR + (left ? 0 : N2) : dum;
 #pragma unroll
                     for (int t = 0; t < Q; t++) {
                         dbl2 zv;
@@ -1929,8 +2023,9 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
                         if (2 * t + 1 == j) zv.y = epub * lmask;
                         if (2 * t == Q + j) zv.x = epub * rmask;
                         if (2 * t + 1 == Q + j) zv.y = epub * rmask;
-                        *reinterpret_cast<LDS_PTR(dbl2)>(isref ? zr + 2 * t : dum) = zv;
+                        *reinterpret_cast<LDS_PTR(dbl2)>(zr + 2 * t) = zv;
                     }
+                    const int xp = a % 3;
                     dbl2 xv;
                     xv.x = xp == 0 ? i11 : (xp == 1 ? i21 : y1);
                     xv.y = xp == 0 ? i12 : (xp == 1 ? i22 : y2);
@@ -1938,8 +2033,8 @@ PQ_DEV bool factor(const SysView& v, bool live, GLB_PTR(double) rec, LDS_PTR(dou
                         xv;
                 }
                 double gy = isref ? ybs[s] : y;
-                gy = __builtin_fma(y1, n1, gy);
-                gy = __builtin_fma(y2, n2, gy);
+                gy = __builtin_fma(-y1, n1, gy);
+                gy = __builtin_fma(-y2, n2, gy);
                 epub = isref ? eps[s] : epub;
 #pragma unroll
                 for (int cc = 0; cc < N2; cc++) f[cc] = g[cc];
@@ -2193,7 +2288,7 @@ struct RowLds {
     // the 64-bit accesses of 16 lanes over distinct LDS bank pairs
     double buf[64][(rows::RG<Q>::S + 1) * rows::RG<Q>::RB + 1];
     alignas(16) double rec[rows::SPW][rows::RG<Q>::SB * rows::RG<Q>::ZR];  // staged records
-    alignas(16) double dum[64][2];  // per lane: discarded writes
+    alignas(16) double dum[2 * 64 + rows::RG<Q>::DUM];  // discarded writes
 };
 
 // Whole LCP solve in the row layout (FP64), four systems per wave.
@@ -2223,14 +2318,10 @@ __global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
 
     const bool exact = A.mode == LCP_EXACT;
     const bool warm = exact && A.warm;
-    // starting active set as in paqif_lcp_kernel (projected Jacobi sweeps,
-    // their second buffer the system's record area)
-    const bool swept = exact && !warm && A.sweeps > 0 && kmax >= A.sweep_min;
-    GLB_PTR(const double) us = GLB(const double, A.b + off);
-    if (swept)
-        us = start_sweeps<Q, rows::LPS>(
-            v, live, A.bounded ? GLB(const uint8_t, A.bounded + off) : GLB(const uint8_t, kOneFlags),
-            A.bounded != nullptr, GLB(double, A.u + off), rec, ls, A.sweeps);
+    // starting active set as in paqif_lcp_kernel (from the start sweeps'
+    // iterate in u for the systems they ran on)
+    const bool swept = exact && !warm && A.sweeps > 0 && live && v.npair >= A.sweep_min;
+    GLB_PTR(const double) us = GLB(const double, (swept ? A.u : A.b) + off);
     if (live) {
         constexpr int R = 8;
         const int nm = v.n - 1;
@@ -2260,7 +2351,7 @@ __global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
     bool done = !live;
     for (; it < max_it;) {
         const bool bad = rows::factor<Q>(v, live && !done, rec, lbuf, as_lds(&lds.rec[grp][0]),
-                                         as_lds(&lds.dum[0][0]), ls, kmax);
+                                         as_lds(&lds.dum[0]), ls, kmax);
         __syncthreads();
         rows::back<Q>(v, live && !done, rec, GLB(double, A.u + off), ls, kmax);
         __syncthreads();
@@ -2390,6 +2481,16 @@ int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s)
     case 2: return launch_lcp<2>(a, prec, layout, s);
     case 4: return launch_lcp<4>(a, prec, layout, s);
     case 8: return launch_lcp<8>(a, prec, layout, s);
+    default: return PAQIF_EINVAL;
+    }
+}
+
+int dispatch_sweeps(int q, const LcpArgs& a, int max_n, double* tmp, hipStream_t s)
+{
+    switch (q) {
+    case 2: return launch_sweeps<2>(a, max_n, tmp, s);
+    case 4: return launch_sweeps<4>(a, max_n, tmp, s);
+    case 8: return launch_sweeps<8>(a, max_n, tmp, s);
     default: return PAQIF_EINVAL;
     }
 }

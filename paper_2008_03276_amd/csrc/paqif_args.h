@@ -45,11 +45,27 @@ struct LcpArgs {
     // per system: first row of its band rows in `band` (null = offsets[sys]);
     // lets several systems (e.g. one matrix with several right-hand sides) share rows
     const int64_t* band_off = nullptr;
-    // exact mode without a warm start: projected Jacobi sweeps that choose
-    // the starting active set (0: the sign of b), run by the workgroups
-    // whose largest system has at least sweep_min elimination levels
+    // exact mode without a warm start: the systems with at least sweep_min
+    // elimination levels start from the iterate that `sweeps` projected
+    // Jacobi sweeps (dispatch_sweeps, run before the solve) left in u, the
+    // others (and all when sweeps == 0) from the sign of b
     int sweeps = 0;
     int sweep_min = 0;
+};
+
+// Start sweeps (paqif_sweep_kernel): rows of a system as in b and u.
+constexpr int SWC = 256;  // rows of one system per workgroup
+struct SweepArgs {
+    int32_t count;
+    const int64_t* offsets;
+    const int64_t* band_off;  // null: offsets
+    const double* band;
+    const double* b;
+    const uint8_t* bounded;  // null: all bounded
+    const double* src;       // iterate the sweeps start from (null: zero)
+    double* dst;
+    int kp;                  // sweeps of this launch
+    int sweep_min;           // systems with fewer elimination levels: untouched
 };
 
 struct FactorArgs {
@@ -73,6 +89,9 @@ struct SolveArgs {
 };
 
 int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s);
+// The start sweeps of an exact solve (a.sweeps of them, into a.u; tmp: a
+// second buffer of total-rows doubles when they take several launches).
+int dispatch_sweeps(int q, const LcpArgs& a, int max_n, double* tmp, hipStream_t s);
 int layouts_for(int q);
 int dispatch_factor(int q, const FactorArgs& a, hipStream_t s);
 int dispatch_solve(int q, const SolveArgs& a, hipStream_t s);

@@ -307,6 +307,42 @@ def test_start_sweeps_keep_the_solution(gpu, q, layout, sweeps):
         assert it[big].max() <= 2, it
 
 
+@pytest.mark.parametrize("q", [2, 4, 8])
+@pytest.mark.parametrize("sweeps", [1, 3, 8, 20])
+def test_start_sweeps_iterate_matches_oracle(gpu, q, sweeps):
+    """The start sweeps' kernel (workgroups of 512 held rows, several per
+    system, one launch per 1 + 64/q sweeps) gives the oracle's starting
+    active set: one active-set solve (max_iter = 1) from each side's A_0
+    gives the same u (a start that differs in one row changes u there by the
+    row's whole value).  The systems under 0.7 (max_n // 2) levels take the
+    sign start on both sides."""
+    P = gpu
+    dev = torch.device("cuda")
+    sizes = [4097, 1, 2, 5, 700, 2049, 3001, 2868, 2866, 4000]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=70 + q, sizes=sizes)
+    rng = np.random.default_rng(sweeps)
+    bounded = (rng.random(len(f)) < 0.9).astype(np.uint8)
+    start = oracle.lcp_start_sets(q, offs, band, f, bounded, k=sweeps)
+    bt = P.paqif.Batch(offs, q, order="lpt")
+    keep = P.paqif.get_start_sweeps(q, 0)
+    try:
+        P.paqif.set_start_sweeps(q, 0, sweeps)
+        print(f"start sweeps q={q} k={sweeps}", flush=True)
+        r = P.paqif.solve_lcp(bt, torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev),
+                              mode=2, max_iter=1, bounded=torch.as_tensor(bounded, device=dev))
+        torch.cuda.synchronize()
+    finally:
+        P.paqif.set_start_sweeps(q, 0, keep)
+    u = r["u"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = int(offs[s]), int(offs[s + 1])
+        o = oracle.lcp_solve_start(band[a:b], f[a:b], bounded[a:b], start=start[a:b], max_iter=1)
+        assert st[s] in (0, 3), (s, st[s])
+        assert (st[s] == 0) == (o["status"] == 0), (s, st[s], o["status"])
+        assert _relerr(u[a:b], o["u"]) < 1e-12, (s, sizes[s])
+
+
 def test_start_sweeps_argument_checks(gpu):
     P = gpu
     with pytest.raises(RuntimeError):

@@ -9,7 +9,11 @@
     small systems (unique solution for these P-matrices), the projected SOR
     iteration of Sec. 3.2 (Cryer), the QP characterisation (bound-constrained
     minimisation of 1/2 u'Au - b'u by scipy), and the complementarity
-    certificate at full size.
+    certificate at full size;
+  * the start sweeps (projected Jacobi, a starting active set of the exact
+    LCP): one sweep against its closed form, several against the same
+    iteration written with the dense matrix, many against the LCP solution
+    (their fixed point for a strictly diagonally dominant matrix).
 """
 import itertools
 
@@ -191,6 +195,71 @@ def test_lcp_empty_start_reaches_the_same_solution(q):
     # a start equal to the solution's active set ends after one solve
     r2 = oracle.lcp_solve_start(band, f, start=r1["active"])
     assert r2["iters"] == 1 and (r2["active"] == r1["active"]).all()
+
+
+@pytest.mark.parametrize("q", [1, 2, 4, 8])
+def test_start_sweeps_one_sweep_closed_form(q):
+    """From u = 0 one sweep gives f_i / a_ii, clipped at 0 on bounded rows."""
+    band, f = nonsym_band(37, q, 5)
+    bounded = (np.arange(37) % 3 != 0).astype(np.uint8)
+    u = oracle.start_sweeps(band, f, bounded, 1)
+    x = f / band[:, q]
+    ref = np.where(bounded != 0, np.maximum(x, 0.0), x)
+    assert np.array_equal(u, ref)
+    assert np.array_equal(oracle.start_sweeps(band, f, bounded, 0), np.zeros(37))
+
+
+@pytest.mark.parametrize("q", [1, 2, 4])
+def test_start_sweeps_match_the_dense_iteration(q):
+    """k sweeps u <- P(D^-1 (f - (A - D) u)) written with the dense matrix
+    (P: clip at 0 on bounded rows), every sweep from the previous iterate
+    only (Jacobi, not Gauss-Seidel)."""
+    for n, k in [(1, 3), (2, 4), (9, 5), (40, 7)]:
+        band, f = nonsym_band(n, q, 11 + n)
+        bounded = (np.arange(n) % 4 != 1).astype(np.uint8)
+        A = dense(band)
+        D = np.diag(A)
+        u = np.zeros(n)
+        for _ in range(k):
+            x = (f - (A - np.diag(D)) @ u) / D
+            u = np.where(bounded != 0, np.maximum(x, 0.0), x)
+        got = oracle.start_sweeps(band, f, bounded, k)
+        assert np.abs(got - u).max() <= 1e-13 * max(1.0, np.abs(u).max()), (n, k)
+
+
+@pytest.mark.parametrize("q", [2, 8])
+def test_start_sweeps_converge_to_the_lcp_solution(q):
+    """For a strictly diagonally dominant matrix the projected Jacobi
+    iteration contracts, and its fixed point (u_i = max(0, (f_i - sum_{j!=i}
+    a_ij u_j) / a_ii) on bounded rows, a_ii > 0) is the LCP's solution."""
+    band, f = synth.lcp_system(300, q, 3, 0)
+    bounded = (np.arange(300) % 5 != 2).astype(np.uint8)
+    u = oracle.start_sweeps(band, f, bounded, 400)
+    r = oracle.lcp_solve(band, f, bounded, mode=oracle.EXACT)
+    assert r["status"] == oracle.OK
+    assert np.abs(u - r["u"]).max() <= 1e-10 * max(1.0, np.abs(r["u"]).max())
+
+
+def test_lcp_start_sets_rule():
+    """The batch start rule: the systems with at least 0.7 (max_n // 2)
+    elimination levels from the sweeps, the others from the sign of f; one
+    sweep reproduces the sign start (positive diagonals)."""
+    q = 2
+    sizes = [1, 6, 40, 57, 60]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=3, sizes=sizes)
+    bounded = (np.arange(int(offs[-1])) % 7 != 3).astype(np.uint8)
+    sign = (bounded != 0) & (f <= 0.0)
+    assert np.array_equal(oracle.lcp_start_sets(q, offs, band, f, bounded, k=0), sign)
+    assert np.array_equal(oracle.lcp_start_sets(q, offs, band, f, bounded, k=1), sign)
+    st = oracle.lcp_start_sets(q, offs, band, f, bounded, k=6)
+    band = band.reshape(-1, 2 * q + 1)
+    for s, n in enumerate(sizes):  # levels 0 3 20 28 30; threshold int(0.7 * 30) = 21
+        a, b = int(offs[s]), int(offs[s + 1])
+        if n // 2 >= 21:
+            u = oracle.start_sweeps(band[a:b], f[a:b], bounded[a:b], 6)
+            assert np.array_equal(st[a:b], (bounded[a:b] != 0) & (u <= 0.0))
+        else:
+            assert np.array_equal(st[a:b], sign[a:b])
 
 
 def test_lcp_brute_force_with_free_rows():
