@@ -21,6 +21,8 @@
 // and split BF16: every operand x is split as x = hi + lo with hi = bf16(x),
 // lo = bf16(x - hi); hi*hi + hi*lo + lo*hi are accumulated in FP32 by
 // v_mfma_f32_16x16x16bf16_1k.
+#include <type_traits>
+
 #include "common.h"
 #include "ehl_internal.h"
 
@@ -239,6 +241,145 @@ __global__ void __launch_bounds__(256) line_deform_kernel(int N, int B,
 }
 
 // ---------------------------------------------------------------------------
+// Line contact, FP64 / FP32 MFMA: out[i + N*b] = sum_j k[|i-j|] P[j + N*b].
+// A wave owns one 16x16 output tile (16 rows i, 16 columns b), a workgroup
+// 4 waves along i (64 rows) with the same 16 columns; at N = 4097, B = 170
+// that is about 2.8 workgroups per CU, which hide each other's operand work
+// and barriers behind the matrix pipe (one wave per SIMD on larger tiles
+// left a third of the CUs idle).  Two accumulators take the even and odd
+// K-steps, so a wave's MFMAs do not wait on each other.  The K index is free
+// inside a chunk of LKG K-steps (4 LKG rows j): lane k-slot lk of step u takes
+// row j = j0 + LKG lk + u.  A = k[|i - j|] from the kernel vector in LDS
+// (staged once, with a zero at index N that rows i >= N and rows j >= N
+// read); where every row j of a chunk lies on one side of every row i of
+// the tile, a lane's A entries are consecutive kernel-vector entries (read
+// with immediate offsets, no index arithmetic), else entry by entry.  B: the
+// workgroup stages each chunk of its 16 P columns through LDS once (one
+// 16-byte load per thread, whole cache lines; rows j >= N and columns
+// b >= B as zero), two buffers, the next chunk's loads issued before the
+// current chunk's MFMAs.  Rows i >= N and columns b >= B are not stored.
+// ---------------------------------------------------------------------------
+// K-steps per chunk (even; rows j per chunk a multiple of 16)
+template <int PREC>
+constexpr int line_kg()
+{
+    return 16;
+}
+template <int PREC>
+constexpr int line_pb()  // staged column stride (16-byte aligned rows)
+{
+    return 4 * line_kg<PREC>() + 2;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) line_deform_tiled(int N, int B,
+                                                         const double* __restrict__ kvec,
+                                                         const double* __restrict__ P,
+                                                         double* __restrict__ out)
+{
+    using T = typename std::conditional<PREC == PREC_FP64, double, float>::type;
+    constexpr int LKG = line_kg<PREC>();
+    constexpr int LGJ = 4 * LKG;         // rows j per chunk
+    constexpr int LPB = line_pb<PREC>();
+    constexpr int SPT = LGJ / 16;        // staged values per thread
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    T* pt = reinterpret_cast<T*>(lds_raw);  // [2][16][LPB] staged B chunks
+    T* sk = pt + 2 * 16 * LPB;              // N + 1 (zero at N)
+    const int tid = threadIdx.x;
+    // the kernel vector: batches of 8 loads per thread, all issued before
+    // their LDS stores (a load-then-store loop waits on memory per entry)
+    for (int t0 = 0; t0 <= N; t0 += 8 * 256) {
+        double kv[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) kv[e] = kvec[min(t0 + e * 256 + tid, N - 1)];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int t = t0 + e * 256 + tid;
+            if (t <= N) sk[t] = t < N ? (T)kv[e] : (T)0;
+        }
+    }
+    const int wave = tid / 64, l = tid % 64;
+    const int li = l % 16, lk = l / 16;
+    const int i0 = blockIdx.x * 64 + wave * 16;  // this wave's first row
+    const int b0 = blockIdx.y * 16;
+    const int ia = i0 + li;  // A row of this lane
+    const bool ina = ia < N;
+    const int nch = (N + LGJ - 1) / LGJ;
+    // staging: thread t loads column b0 + t / 16, rows j0 + SPT (t % 16) ..
+    const int sc = tid / 16, sj = SPT * (tid % 16);
+    const bool scol = b0 + sc < B;
+    const double* pcol = P + (int64_t)(scol ? b0 + sc : 0) * N;
+    double stv[SPT];
+    auto gload = [&](int c) {
+        const int j = c * LGJ + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) stv[e] = pcol[min(j + e, N - 1)];
+    };
+    auto lstore = [&](int c) {
+        const int j = c * LGJ + sj;
+        T* d = pt + ((c & 1) * 16 + sc) * LPB + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) d[e] = (scol && j + e < N) ? (T)stv[e] : (T)0;
+    };
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    // kernel-vector index of this lane's A entry at step u of chunk c (N: zero)
+    auto aidx = [&](int c, int u) {
+        const int j = c * LGJ + LKG * lk + u;
+        return (ina && j < N) ? abs(ia - j) : N;
+    };
+    typedef typename std::conditional<PREC == PREC_FP64, f64x4, f32x4>::type acc_t;
+    acc_t ce = {0, 0, 0, 0}, co = {0, 0, 0, 0};
+    const bool rows_in = i0 + 15 < N;
+    // chunk ranges of the tile (wave-uniform): MODE 1 every j below every i,
+    // MODE 2 every j above every i (and inside), MODE 0 the others
+    const int gA = (rows_in && i0 >= LGJ - 1) ? (i0 - (LGJ - 1)) / LGJ + 1 : 0;
+    const int gB = rows_in ? max(gA, (i0 + 15 + LGJ - 1) / LGJ) : 0;
+    const int gC = rows_in ? max(gB, min(nch, N >= LGJ ? (N - LGJ) / LGJ + 1 : 0)) : 0;
+    for (int c = 0; c < nch; c++) {
+        if (c + 1 < nch) gload(c + 1);  // the next chunk in flight
+        const int jg = c * LGJ;
+        T av[LKG];
+        if (i0 < N && c < gA) {
+            const T* ap = sk + (ia - jg - LKG * lk - (LKG - 1));
+#pragma unroll
+            for (int u = 0; u < LKG; u++) av[u] = ap[LKG - 1 - u];
+        } else if (i0 < N && c >= gB && c < gC) {
+            const T* ap = sk + (jg + LKG * lk - ia);
+#pragma unroll
+            for (int u = 0; u < LKG; u++) av[u] = ap[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < LKG; u++) av[u] = sk[aidx(c, u)];
+        }
+        const T* bp = pt + ((c & 1) * 16 + li) * LPB + LKG * lk;
+#pragma unroll
+        for (int u = 0; u < LKG; u++) {
+            const T x = bp[u];
+            if constexpr (PREC == PREC_FP64) {
+                if (u % 2 == 0) ce = mfma_f64(av[u], x, ce);
+                else co = mfma_f64(av[u], x, co);
+            } else {
+                if (u % 2 == 0) ce = mfma_f32(av[u], x, ce);
+                else co = mfma_f32(av[u], x, co);
+            }
+        }
+        if (c + 1 < nch) lstore(c + 1);
+        __syncthreads();
+    }
+    // D element r of lane l: FP64 row 4 r + l/16, FP32 row 4 (l/16) + r; column l%16
+    const int ca = b0 + li;
+    if (ca < B && i0 < N) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int ro = i0 + (PREC == PREC_FP64 ? 4 * r + lk : 4 * lk + r);
+            if (ro < N) out[(int64_t)ca * N + ro] = (double)ce[r] + (double)co[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Point contact, one instance per blockIdx.z.  P, out: Nx x Ny row major
 // (P[i*Ny + j]).  Tile: 16 j (MFMA rows) x 16 i (MFMA columns) per wave,
 // 4 waves per workgroup along i.  blockIdx.y = segment s of the d range;
@@ -417,14 +558,31 @@ int launch_point_kernel_tab(int Nx, int Ny, double hx, double hy, double* k2, hi
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
+// LDS of line_deform_tiled: two staged B chunks, the kernel vector and a zero
+template <int PREC>
+static size_t line_tiled_lds(int N)
+{
+    return (size_t)(2 * 16 * line_pb<PREC>() + N + 1) * (PREC == PREC_FP64 ? 8 : 4);
+}
+
 int launch_line_deform(int N, int B, int prec, const double* k, const double* P, double* out,
                        hipStream_t s)
 {
     if (N <= 0 || B <= 0) return PAQIF_OK;
     dim3 grid((N + 63) / 64, (B + 31) / 32), block(256);
     const size_t lds = (size_t)N * sizeof(double);
-    if (prec == PREC_FP64)
+    const dim3 gridt((N + 63) / 64, (B + 15) / 16);
+    // the tiled kernel where its LDS fits in 64 KB (FP32: every line grid,
+    // nx <= 8192; FP64 up to about 6000 nodes), else the untiled one
+    constexpr size_t kLdsMax = 65536;
+    if (prec == PREC_FP64 && line_tiled_lds<PREC_FP64>(N) <= kLdsMax)
+        hipLaunchKernelGGL((line_deform_tiled<PREC_FP64>), gridt, block,
+                           line_tiled_lds<PREC_FP64>(N), s, N, B, k, P, out);
+    else if (prec == PREC_FP64)
         hipLaunchKernelGGL((line_deform_kernel<PREC_FP64>), grid, block, lds, s, N, B, k, P, out);
+    else if (prec == PREC_FP32 && line_tiled_lds<PREC_FP32>(N) <= kLdsMax)
+        hipLaunchKernelGGL((line_deform_tiled<PREC_FP32>), gridt, block,
+                           line_tiled_lds<PREC_FP32>(N), s, N, B, k, P, out);
     else if (prec == PREC_FP32)
         hipLaunchKernelGGL((line_deform_kernel<PREC_FP32>), grid, block, lds, s, N, B, k, P, out);
     else

@@ -39,9 +39,13 @@ def _tol(prec, K):
     return {0: 1e-13, 3: 8 * np.sqrt(K) * U32, 2: 2e-4}[prec]
 
 
-@pytest.mark.parametrize("N,B", [(5, 1), (17, 3), (257, 40), (1025, 5), (2049, 33)])
+@pytest.mark.parametrize("N,B", [(5, 1), (17, 3), (130, 33), (257, 40), (1025, 5), (2049, 33),
+                                 (4097, 7), (6001, 2)])
 @pytest.mark.parametrize("prec", [0, 3, 2])
 def test_line_deformation(gpu, N, B, prec):
+    """K P against the oracle's dense product: ragged row and column tiles,
+    several P chunks, the workload's N = 4097, and N = 6001, where the FP64
+    kernel vector no longer fits the tiled kernel's LDS (untiled kernel)."""
     tol = _tol(prec, N)
     P = gpu.ehl
     x, h = OE.grid(N)
