@@ -558,6 +558,143 @@ int launch_point_kernel_tab(int Nx, int Ny, double hx, double hy, double* k2, hi
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
+// ---------------------------------------------------------------------------
+// Line contact, split BF16 on gfx950's v_mfma_f32_16x16x32_bf16: every
+// operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and the product
+// hi*hi + hi*lo + lo*hi accumulated in FP32 (three MFMAs per 32 rows j).
+// Same tiling as line_deform_tiled: a 16x16 output tile per wave, 4 waves
+// along i per workgroup, 64-row chunks of the workgroup's 16 P columns
+// staged through LDS once, split into hi and lo halves as they are stored
+// (a lane's 8 consecutive rows are one aligned 16-byte read per half).  The
+// kernel vector sits in LDS split and packed, hi | lo << 16 per entry (zero
+// at index N), so a lane's 8 entries at any alignment are four 2-dword
+// reads, separated into hi and lo operands by byte permutes.  Lane k-group
+// lk, element e of step u takes row j = j0 + 16 lk + 8 u + e.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int SBJ = 64;        // rows j per chunk
+constexpr int SBP = SBJ + 8;   // staged column stride in bf16 (16-byte aligned)
+
+PQ_DEV uint32_t bf16_hi_lo(float x)
+{
+    short h, lo;
+    split_bf16(x, h, lo);
+    return (uint32_t)(uint16_t)h | ((uint32_t)(uint16_t)lo << 16);
+}
+
+PQ_DEV f32x4 mfma_bf16x32(u32x4 a, u32x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a),
+                                                   __builtin_bit_cast(bf16x8v, b), c, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) line_deform_sbf16(int N, int B,
+                                                         const double* __restrict__ kvec,
+                                                         const double* __restrict__ P,
+                                                         double* __restrict__ out)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    uint16_t* ph = reinterpret_cast<uint16_t*>(lds_raw);  // [2][16][SBP] hi halves
+    uint16_t* pl = ph + 2 * 16 * SBP;                      // [2][16][SBP] lo halves
+    uint32_t* kv = reinterpret_cast<uint32_t*>(pl + 2 * 16 * SBP);  // N + 1 packed
+    const int tid = threadIdx.x;
+    for (int t0 = 0; t0 <= N; t0 += 8 * 256) {
+        double k8[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) k8[e] = kvec[min(t0 + e * 256 + tid, N - 1)];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int t = t0 + e * 256 + tid;
+            if (t <= N) kv[t] = t < N ? bf16_hi_lo((float)k8[e]) : 0u;
+        }
+    }
+    const int wave = tid / 64, l = tid % 64;
+    const int li = l % 16, lk = l / 16;
+    const int i0 = blockIdx.x * 64 + wave * 16;
+    const int b0 = blockIdx.y * 16;
+    const int ia = i0 + li;
+    const bool ina = ia < N;
+    const int nch = (N + SBJ - 1) / SBJ;
+    constexpr int SPT = SBJ / 16;  // staged values per thread
+    const int sc = tid / 16, sj = SPT * (tid % 16);
+    const bool scol = b0 + sc < B;
+    const double* pcol = P + (int64_t)(scol ? b0 + sc : 0) * N;
+    double stv[SPT];
+    auto gload = [&](int c) {
+        const int j = c * SBJ + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) stv[e] = pcol[min(j + e, N - 1)];
+    };
+    auto lstore = [&](int c) {
+        const int j = c * SBJ + sj;
+        const int o = ((c & 1) * 16 + sc) * SBP + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) {
+            const uint32_t hl = (scol && j + e < N) ? bf16_hi_lo((float)stv[e]) : 0u;
+            ph[o + e] = (uint16_t)(hl & 0xFFFFu);
+            pl[o + e] = (uint16_t)(hl >> 16);
+        }
+    };
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+    const bool rows_in = i0 + 15 < N;
+    const int gA = (rows_in && i0 >= SBJ - 1) ? (i0 - (SBJ - 1)) / SBJ + 1 : 0;
+    const int gB = rows_in ? max(gA, (i0 + 15 + SBJ - 1) / SBJ) : 0;
+    const int gC = rows_in ? max(gB, min(nch, N >= SBJ ? (N - SBJ) / SBJ + 1 : 0)) : 0;
+    for (int c = 0; c < nch; c++) {
+        if (c + 1 < nch) gload(c + 1);
+        const int jg = c * SBJ;
+        const int bo = ((c & 1) * 16 + li) * SBP + 16 * lk;
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int jb = jg + 16 * lk + 8 * u;  // this lane's first row j of the step
+            uint32_t av[8];
+            if (i0 < N && c < gA) {  // every j below every i: k[i - j], index descending
+                const uint32_t* ap = kv + (ia - jb - 7);
+#pragma unroll
+                for (int e = 0; e < 8; e++) av[e] = ap[7 - e];
+            } else if (i0 < N && c >= gB && c < gC) {  // every j above every i: k[j - i]
+                const uint32_t* ap = kv + (jb - ia);
+#pragma unroll
+                for (int e = 0; e < 8; e++) av[e] = ap[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int j = jb + e;
+                    av[e] = kv[(ina && j < N) ? abs(ia - j) : N];
+                }
+            }
+            u32x4 ah, al;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                // low halves of entries 2q, 2q+1 -> hi operand; high halves -> lo operand
+                ah[q] = __builtin_amdgcn_perm(av[2 * q + 1], av[2 * q], 0x05040100u);
+                al[q] = __builtin_amdgcn_perm(av[2 * q + 1], av[2 * q], 0x07060302u);
+            }
+            const u32x4 bh = *reinterpret_cast<const u32x4*>(ph + bo + 8 * u);
+            const u32x4 bl = *reinterpret_cast<const u32x4*>(pl + bo + 8 * u);
+            c0 = mfma_bf16x32(ah, bh, c0);
+            c1 = mfma_bf16x32(ah, bl, c1);
+            c1 = mfma_bf16x32(al, bh, c1);
+        }
+        if (c + 1 < nch) lstore(c + 1);
+        __syncthreads();
+    }
+    const int ca = b0 + li;
+    if (ca < B && i0 < N) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int ro = i0 + 4 * lk + r;
+            if (ro < N) out[(int64_t)ca * N + ro] = (double)(c0[r] + c1[r]);
+        }
+    }
+}
+
+static size_t line_sbf16_lds(int N) { return (size_t)(4 * 16 * SBP) * 2 + (size_t)(N + 1) * 4; }
+
 // LDS of line_deform_tiled: two staged B chunks, the kernel vector and a zero
 template <int PREC>
 static size_t line_tiled_lds(int N)
@@ -585,6 +722,8 @@ int launch_line_deform(int N, int B, int prec, const double* k, const double* P,
                            line_tiled_lds<PREC_FP32>(N), s, N, B, k, P, out);
     else if (prec == PREC_FP32)
         hipLaunchKernelGGL((line_deform_kernel<PREC_FP32>), grid, block, lds, s, N, B, k, P, out);
+    else if (line_sbf16_lds(N) <= kLdsMax)
+        hipLaunchKernelGGL(line_deform_sbf16, gridt, block, line_sbf16_lds(N), s, N, B, k, P, out);
     else
         hipLaunchKernelGGL((line_deform_kernel<PREC_SPLIT_BF16>), grid, block, lds, s, N, B, k, P,
                            out);
