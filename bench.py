@@ -655,6 +655,8 @@ def main():
                     help="skip the config-2 run at ~30%% active (keeps counter runs to one batch)")
     ap.add_argument("--part-case", default="",
                     help="n:q:r -- the partitioned leg on this one case only")
+    ap.add_argument("--deformation-only", action="store_true",
+                    help="run only the MFMA deformation leg and print its figures")
     ap.add_argument("--convdiff-only", action="store_true",
                     help="run only the convection-diffusion leg (one JSON object)")
     args = ap.parse_args()
@@ -678,6 +680,9 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 8}))
         return
     P.lib()
+    if args.deformation_only:
+        print(json.dumps({"deformation_mfma": deformation_leg(P, torch, args)}))
+        return
     if args.convdiff_only:
         print(json.dumps({"convdiff": convdiff_leg(P, torch, args)}))
         return
