@@ -111,10 +111,12 @@ size_t paqif_workspace_bytes(paqif_handle handle, const paqif_batch *batch, int 
  *  band     : DEVICE, total_rows x (2q+1) doubles (layout above).
  *  pinned   : DEVICE uint8[total_rows] or NULL; rows/columns with a nonzero
  *             flag are replaced by the identity before factorising.
- *  prec     : PREC_FP64 only.
+ *  prec     : PREC_FP64, or PREC_FP32_IR: the factorisation computed and
+ *             stored in FP32 (half the record bytes; the layout of the
+ *             FP32 + refinement LCP path).  PAQIF_EINVAL otherwise.
  *  factors  : DEVICE, paqif_workspace_bytes(handle, batch, prec, LCP_LINEAR)
  *             bytes; receives the level records (layout in the library
- *             source; consumed by paqif_solve_factored).
+ *             source; consumed by paqif_solve_factored with the same prec).
  *  sys_status: DEVICE int32[count]: SYS_OK or SYS_ZERO_PIVOT.
  */
 int paqif_factor(paqif_handle handle, const paqif_batch *batch, const double *band,
@@ -125,11 +127,17 @@ int paqif_factor(paqif_handle handle, const paqif_batch *batch, const double *ba
  * paqif_solve_factored -- x = (W0 Z0)^{-1} rhs with factors from
  * paqif_factor: W0 y = rhs from the centre outwards, Z0 x = y from both ends
  * inwards (Sec. 2.2.2).  rhs entries of pinned rows are treated as 0.
+ *  prec   : the prec the factors were made with (PAQIF_EINVAL otherwise).
+ *           With PREC_FP32_IR the solve runs on the FP32 records (FP64 rhs
+ *           and x): an FP32-accurate solution, which serves as the
+ *           correction step of an iterative refinement whose residual the
+ *           caller forms in FP64 with its band.
  *  rhs, x : DEVICE, total_rows doubles each (may not alias).
  *  pinned : the same mask given to paqif_factor (or NULL).
  */
 int paqif_solve_factored(paqif_handle handle, const paqif_batch *batch, const void *factors,
-                         const uint8_t *pinned, const double *rhs, double *x, void *stream);
+                         int prec, const uint8_t *pinned, const double *rhs, double *x,
+                         void *stream);
 
 /*
  * paqif_solve_lcp -- PAQIF solve of the banded linear complementarity

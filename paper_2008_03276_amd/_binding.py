@@ -75,7 +75,7 @@ def lib():
         "paqif_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "paqif_workspace_bytes": ([vp, bp, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
         "paqif_factor": ([vp, bp, vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
-        "paqif_solve_factored": ([vp, bp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "paqif_solve_factored": ([vp, bp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "paqif_solve_lcp": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                              vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "paqif_solve_lcp_noalloc": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, d,

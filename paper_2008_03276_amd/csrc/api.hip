@@ -190,7 +190,8 @@ int paqif_factor(paqif_handle handle, const paqif_batch* batch, const double* ba
                  const uint8_t* pinned, int prec, void* factors, int32_t* sys_status,
                  void* stream)
 {
-    if (!handle || !valid_batch(batch) || prec != PREC_FP64) return PAQIF_EINVAL;
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
     if (batch->count == 0) return PAQIF_OK;
     if (!band || !factors || !sys_status) return PAQIF_EINVAL;
     pq::FactorArgs a;
@@ -201,13 +202,16 @@ int paqif_factor(paqif_handle handle, const paqif_batch* batch, const double* ba
     a.pinned = pinned;
     a.rec = factors;
     a.status = sys_status;
+    a.prec = prec;
     return pq::dispatch_factor(batch->q, a, (hipStream_t)stream);
 }
 
 int paqif_solve_factored(paqif_handle handle, const paqif_batch* batch, const void* factors,
-                         const uint8_t* pinned, const double* rhs, double* x, void* stream)
+                         int prec, const uint8_t* pinned, const double* rhs, double* x,
+                         void* stream)
 {
     if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
     if (batch->count == 0) return PAQIF_OK;
     if (!factors || !rhs || !x || (const void*)rhs == (const void*)x) return PAQIF_EINVAL;
     pq::SolveArgs a;
@@ -218,6 +222,7 @@ int paqif_solve_factored(paqif_handle handle, const paqif_batch* batch, const vo
     a.rec = const_cast<void*>(factors);
     a.rhs = rhs;
     a.x = x;
+    a.prec = prec;
     return pq::dispatch_solve(batch->q, a, (hipStream_t)stream);
 }
 

@@ -1287,15 +1287,16 @@ __global__ void __launch_bounds__(64)
     }
 }
 
-// Factor only (records with W0), no right-hand side.
+// Factor only (records with W0), no right-hand side; records in FT (FP64, or
+// FP32 at the layout of the FP32 + refinement LCP path).
 
-template <int Q>
+template <int Q, typename FT>
 __global__ void __launch_bounds__(64)
     __attribute__((amdgpu_waves_per_eu(Geo<Q, 0>::WPE, 8))) paqif_factor_kernel(FactorArgs A)
 {
     constexpr int L = 0;
     using G = Geo<Q, L>;
-    __shared__ LdsBlock<Q, L, double> lds;
+    __shared__ LdsBlock<Q, L, FT> lds;
     const int lane = threadIdx.x;
     const int grp = lane / G::LPS;
     const int ls = lane % G::LPS;
@@ -1316,22 +1317,21 @@ __global__ void __launch_bounds__(64)
     }
     const int kmax = group_max_int<64>(v.npair);
     constexpr int stride = G::ZREC + G::WREC;
-    GLB_PTR(double) rec =
-        GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride);
-    bool bad = factor_system<Q, L, double, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
-                                                     as_lds(lds.Y[grp]), as_lds(lds.X[grp]), ls,
-                                                     kmax);
+    GLB_PTR(FT) rec = GLB(FT, reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride);
+    bool bad = factor_system<Q, L, FT, true, false>(v, live, rec, stride, as_lds(lds.F[grp]),
+                                                 as_lds(lds.Y[grp]), as_lds(lds.X[grp]), ls,
+                                                 kmax);
     const int badg = group_max_int<G::LPS>(bad ? 1 : 0);
     if (live && ls == 0) A.status[sys] = badg ? SYS_ZERO_PIVOT : SYS_OK;
 }
 
 
-template <int Q>
+template <int Q, typename FT>
 __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
 {
     constexpr int L = 0;
     using G = Geo<Q, L>;
-    __shared__ LdsBlock<Q, L, double> lds;
+    __shared__ LdsBlock<Q, L, FT> lds;
     const int lane = threadIdx.x;
     const int grp = lane / G::LPS;
     const int ls = lane % G::LPS;
@@ -1353,13 +1353,11 @@ __global__ void __launch_bounds__(64) paqif_solve_factored_kernel(SolveArgs A)
     }
     const int kmax = group_max_int<64>(v.npair);
     constexpr int stride = G::ZREC + G::WREC;
-    GLB_PTR(double) rec =
-        GLB(double, reinterpret_cast<double*>(A.rec) + level_base(off, sys) * stride);
-    wsolve_system<Q, double>(v, live, GLB(const double, A.rhs + off), rec, stride, ls, kmax,
-                             gbase);
+    GLB_PTR(FT) rec = GLB(FT, reinterpret_cast<FT*>(A.rec) + level_base(off, sys) * stride);
+    wsolve_system<Q, FT>(v, live, GLB(const double, A.rhs + off), rec, stride, ls, kmax, gbase);
     __syncthreads();
-    back_system<Q, L, double, false>(v, live, rec, stride, GLB(double, A.x + off),
-                                  as_lds(lds.B[grp]), ls, kmax);
+    back_system<Q, L, FT, false>(v, live, rec, stride, GLB(double, A.x + off), as_lds(lds.B[grp]),
+                                 ls, kmax);
 }
 
 // --------------------------------------------------------------------------
@@ -2458,7 +2456,10 @@ static int launch_factor(const FactorArgs& a, hipStream_t s)
 {
     const int grid = (a.count + Geo<Q, 0>::SPW - 1) / Geo<Q, 0>::SPW;
     if (grid == 0) return PAQIF_OK;
-    hipLaunchKernelGGL((paqif_factor_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+    if (a.prec == PREC_FP32_IR)
+        hipLaunchKernelGGL((paqif_factor_kernel<Q, float>), dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((paqif_factor_kernel<Q, double>), dim3(grid), dim3(64), 0, s, a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 
@@ -2467,7 +2468,11 @@ static int launch_solve(const SolveArgs& a, hipStream_t s)
 {
     const int grid = (a.count + Geo<Q, 0>::SPW - 1) / Geo<Q, 0>::SPW;
     if (grid == 0) return PAQIF_OK;
-    hipLaunchKernelGGL((paqif_solve_factored_kernel<Q>), dim3(grid), dim3(64), 0, s, a);
+    if (a.prec == PREC_FP32_IR)
+        hipLaunchKernelGGL((paqif_solve_factored_kernel<Q, float>), dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((paqif_solve_factored_kernel<Q, double>), dim3(grid), dim3(64), 0, s,
+                           a);
     return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
 }
 

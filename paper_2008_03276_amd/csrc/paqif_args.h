@@ -76,6 +76,7 @@ struct FactorArgs {
     const uint8_t* pinned;
     void* rec;
     int32_t* status;
+    int prec = PREC_FP64;  // records in FP64, or FP32 (PREC_FP32_IR)
 };
 
 struct SolveArgs {
@@ -86,6 +87,7 @@ struct SolveArgs {
     void* rec;
     const double* rhs;
     double* x;
+    int prec = PREC_FP64;  // precision of the records in rec
 };
 
 int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s);

@@ -151,28 +151,30 @@ def solve_lcp_noalloc(batch, band, b, u, status, mode=B.LCP_EXACT, prec=B.PREC_F
                                            _ptr(iters), _stream())
 
 
-def factor(batch, band, pinned=None, factors=None):
-    """A = W0 Z0 for every system; returns (factors, status)."""
+def factor(batch, band, pinned=None, factors=None, prec=B.PREC_FP64):
+    """A = W0 Z0 for every system (records in FP64, or FP32 for
+    prec=PREC_FP32_IR); returns (factors, status)."""
     _check_system_args(batch, band, bounded=pinned)
     if factors is None:
-        factors = batch.workspace(B.PREC_FP64, B.LCP_LINEAR)
-    _check_workspace(batch, factors, B.PREC_FP64, B.LCP_LINEAR)
+        factors = batch.workspace(prec, B.LCP_LINEAR)
+    _check_workspace(batch, factors, prec, B.LCP_LINEAR)
     st = torch.empty(batch.count, dtype=torch.int32, device=band.device)
     code = B.lib().paqif_factor(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(pinned),
-                                B.PREC_FP64, _ptr(factors), _ptr(st), _stream())
+                                int(prec), _ptr(factors), _ptr(st), _stream())
     B.check(code, "paqif_factor")
     return factors, st
 
 
-def solve_factored(batch, factors, rhs, pinned=None):
+def solve_factored(batch, factors, rhs, pinned=None, prec=B.PREC_FP64):
+    """x = (W0 Z0)^{-1} rhs with the records of factor(..., prec=prec)."""
     _need(rhs, torch.float64, "rhs")
     _need_len(rhs, batch.total_rows, "rhs")
     if pinned is not None:
         _need(pinned, torch.uint8, "pinned")
         _need_len(pinned, batch.total_rows, "pinned")
-    _check_workspace(batch, factors, B.PREC_FP64, B.LCP_LINEAR)
+    _check_workspace(batch, factors, prec, B.LCP_LINEAR)
     x = torch.empty_like(rhs)
-    code = B.lib().paqif_solve_factored(handle(), ctypes.byref(batch.c), _ptr(factors),
+    code = B.lib().paqif_solve_factored(handle(), ctypes.byref(batch.c), _ptr(factors), int(prec),
                                         _ptr(pinned), _ptr(rhs), _ptr(x), _stream())
     B.check(code, "paqif_solve_factored")
     return x

@@ -99,6 +99,70 @@ def test_factor_then_solve(gpu, q):
         assert _relerr(x[a:b], xo) < 1e-12
 
 
+@pytest.mark.parametrize("q", [2, 4, 8])
+def test_factor_fp32_then_solve_and_refine(gpu, q):
+    """FP32 factors (paqif_factor with PREC_FP32_IR): the FP32 solve against
+    the oracle within 1e-4 relative, and FP64 iterative refinement with the
+    FP32 solve as its correction step (residual b - A x formed in FP64 from
+    the band) down to 1e-12.  Bound: FP32 unit roundoff 6e-8 times the
+    growth of the elimination and the condition number of these strictly
+    diagonally dominant systems (diagonal = sum |off-diagonal| + U(0.5, 1.5),
+    so kappa_inf <= (2 (2q) + 1.5) / 0.5 < 70); each refinement step
+    contracts the error by about kappa u_32 < 1e-5."""
+    P = gpu
+    sizes = [1, 2, 3, 6, 9, 50, 101, 256, 1025, 2049]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=12, sizes=sizes)
+    rng = np.random.default_rng(2)
+    pinned = (rng.random(len(f)) < 0.2).astype(np.uint8)
+    dev = torch.device("cuda")
+    bt = P.paqif.Batch(offs, q)
+    pin_d = torch.as_tensor(pinned, device=dev)
+    band_d = torch.as_tensor(band, device=dev)
+    f_d = torch.as_tensor(f, device=dev)
+    fac, st = P.paqif.factor(bt, band_d, pinned=pin_d, prec=P.PREC_FP32_IR)
+    assert fac.numel() * fac.element_size() == bt.workspace_bytes(P.PREC_FP32_IR, P.LCP_LINEAR)
+    x = P.paqif.solve_factored(bt, fac, f_d, pinned=pin_d, prec=P.PREC_FP32_IR)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    xo = np.zeros_like(f)
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        xo[a:b], sto = oracle.aqif_solve(band[a:b], f[a:b], pinned[a:b])
+        assert sto == 0
+    x0 = x.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        e = _relerr(x0[a:b], xo[a:b])
+        assert e < 1e-4, (s, e)
+        assert e > 1e-12 or b - a < 50, (s, e)  # an FP32 solve, not the FP64 one
+    # refinement: r = f_eff - A_eff x in FP64 (pinned rows: identity, rhs 0)
+    bw = 2 * q + 1
+    A_rows = band.reshape(-1, bw)
+    x = x0.copy()
+    for _ in range(4):
+        r = np.zeros_like(f)
+        for s in range(len(sizes)):
+            a, b = int(offs[s]), int(offs[s + 1])
+            n = b - a
+            for i in range(n):
+                gi = a + i
+                if pinned[gi]:
+                    r[gi] = -x[gi]
+                    continue
+                acc = f[gi]
+                for d in range(bw):
+                    j = i + d - q
+                    if 0 <= j < n and not pinned[a + j]:
+                        acc -= A_rows[gi, d] * x[a + j]
+                r[gi] = acc
+        dx = P.paqif.solve_factored(bt, fac, torch.as_tensor(r, device=dev), pinned=pin_d,
+                                    prec=P.PREC_FP32_IR)
+        x = x + dx.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        assert _relerr(x[a:b], xo[a:b]) < 1e-12, s
+
+
 def test_empty_and_zero_pivot(gpu):
     P = gpu
     dev = torch.device("cuda")
