@@ -198,18 +198,18 @@ def cpu_baseline(batches, sample, nthreads):
 
 
 def measured_traffic(kernel_q, kernel):
-    """HBM bytes per solve call (summed over its kernels) from the committed
-    counter summary, if it was taken on these kernels and the current kernel
-    sources (else None)."""
+    """HBM bytes of one exact solve call at this q (summed over its kernels)
+    from the committed counter summary, if it was taken on these kernels and
+    the current kernel sources (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "paqif_lcp_q8_hbm_counters.md")
-    if kernel_q != 8 or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m_val = re.search(r"traffic_bytes_per_launch_q8_fp64:\s*([0-9.eE+]+)", txt)
+    m_val = re.search(rf"traffic_bytes_per_call_q{kernel_q}_fp64:\s*([0-9.eE+]+)", txt)
+    m_ker = re.search(rf"traffic_kernels_q{kernel_q}:\s*(\S+)", txt)
     m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
-    m_ker = re.search(r"traffic_kernel:\s*(\S+)", txt)
     if not (m_val and m_sha and m_ker) or m_ker.group(1) != kernel:
         return None
     h = hashlib.sha256()
@@ -655,6 +655,8 @@ def main():
                     help="skip the config-2 run at ~30%% active (keeps counter runs to one batch)")
     ap.add_argument("--part-case", default="",
                     help="n:q:r -- the partitioned leg on this one case only")
+    ap.add_argument("--serial-q", action="store_true",
+                    help="run the three q batches of a step one after another on one stream")
     ap.add_argument("--deformation-only", action="store_true",
                     help="run only the MFMA deformation leg and print its figures")
     ap.add_argument("--convdiff-only", action="store_true",
@@ -702,13 +704,50 @@ def main():
                       ws64=bt.workspace(P.PREC_FP64), ws32=bt.workspace(P.PREC_FP32_IR))
     torch.cuda.synchronize()
 
-    def step(prec):
+    # the three q batches of a step are independent: by default each runs on
+    # a stream of its own (default priority), so one batch's waves fill the
+    # SIMDs that another's tail leaves idle; the step ends when all three
+    # have finished (the streams wait for the previous step).  The longest
+    # batch (q = 8) is launched first, so its workgroups take the chip first
+    # and the others fill its tail.
+    launch_order = sorted(QS, reverse=True)
+    main_stream = torch.cuda.current_stream()
+    streams = None if args.serial_q else {q: torch.cuda.Stream() for q in QS}
+
+    step_ev = []  # HIP events on the main stream around each timed step
+
+    def step(prec, ev=None):
         out = {}
-        for q in QS:
+        if ev is not None:
+            s0 = torch.cuda.Event(enable_timing=True)
+            s0.record(main_stream)
+        if streams:
+            for q in QS:
+                streams[q].wait_stream(main_stream)
+        for q in launch_order:
             g = gpu[q]
+            if streams:
+                torch.cuda.set_stream(streams[q])
+            e0 = e1 = None
+            if ev is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
             out[q] = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT, prec=prec,
                                        workspace=g["ws64"] if prec == P.PREC_FP64 else g["ws32"],
                                        refine_tol=1e-10)
+            if ev is not None:
+                e1.record()
+                ev[q].append((e0, e1, out[q]))
+            if streams:
+                torch.cuda.set_stream(main_stream)
+        if streams:
+            for q in QS:
+                main_stream.wait_stream(streams[q])
+        if ev is not None:
+            s1 = torch.cuda.Event(enable_timing=True)
+            s1.record(main_stream)
+            step_ev.append((prec, s0, s1))
         return out
 
     tune = {}
@@ -732,19 +771,25 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for q in QS:
-            g = gpu[q]
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            r = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT,
-                                  prec=P.PREC_FP64, workspace=g["ws64"])
-            e1.record()
-            ev[q].append((e0, e1, r))
+        step(P.PREC_FP64, ev)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     solves_per_s = len(QS) * COUNT / (ms_per_step / 1e3)
+    # each solve call alone on the GPU (after the timed region): the calls'
+    # own durations for the standalone roofline
+    alone = {q: [] for q in QS}
+    for q in QS:
+        g = gpu[q]
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT, prec=P.PREC_FP64,
+                              workspace=g["ws64"])
+            e1.record()
+            alone[q].append((e0, e1))
+    torch.cuda.synchronize()
 
     per_q = {}
     for q in QS:
@@ -758,13 +803,15 @@ def main():
         sw = P.paqif.get_start_sweeps(q, P.PREC_FP64)
         bytes_sweeps = sweep_bytes(q, sizes, sw)
         bytes_alg = units * algorithmic_bytes_per_row(q) + bytes_sweeps
-        per_q[q] = dict(avg_ms=avg_ms, iters_mean=float(iters.mean()),
+        alone_ms = float(np.mean([a.elapsed_time(b) for a, b in alone[q]]))
+        per_q[q] = dict(avg_ms=avg_ms, alone_ms=alone_ms, iters_mean=float(iters.mean()),
                         iters_max=int(iters.max()), start_sweeps=sw,
                         sweep_bytes_gb=round(bytes_sweeps / 1e9, 4),
                         status_ok=bool((status == 0).all()),
                         kernel=lcp_call_kernels(P, q, P.PREC_FP64),
                         active_frac=float(r["active"].float().mean().item()),
-                        gbs=bytes_alg / (avg_ms / 1e3) / 1e9, bytes=bytes_alg)
+                        gbs=bytes_alg / (avg_ms / 1e3) / 1e9,
+                        gbs_alone=bytes_alg / (alone_ms / 1e3) / 1e9, bytes=bytes_alg)
 
     log(f"LCP fp64: {ms_per_step:.2f} ms/step")
     # mixed precision (FP32 factors + FP64 refinement to 1e-10): same
@@ -775,15 +822,7 @@ def main():
     evm = {q: [] for q in QS}
     tm0 = time.perf_counter()
     for _ in range(max(1, args.steps // 2)):
-        for q in QS:
-            g = gpu[q]
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            r = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT,
-                                  prec=P.PREC_FP32_IR, workspace=g["ws32"], refine_tol=1e-10)
-            e1.record()
-            evm[q].append((e0, e1, r))
+        step(P.PREC_FP32_IR, evm)
     torch.cuda.synchronize()
     ms_mixed = (time.perf_counter() - tm0) * 1e3 / max(1, args.steps // 2)
     rm = {q: evm[q][-1][2] for q in QS}
@@ -825,24 +864,55 @@ def main():
     dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
     # the committed counter summary names the call's kernels joined by "+"
     tr = measured_traffic(dom, per_q[dom]["kernel"].replace(" ", ""))
-    roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
-                traffic=None if tr is None else round(tr / 1e9, 3),
-                kernel=per_q[dom]["kernel"],
-                timing="HIP events around each solve call (its launches on the stream)",
-                algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
-    rows_it = (per_q[dom]["bytes"] - per_q[dom]["sweep_bytes_gb"] * 1e9) / \
-        algorithmic_bytes_per_row(dom)
-    min_gbs = rows_it * minimum_bytes_per_row(dom) / (per_q[dom]["avg_ms"] / 1e3) / 1e9
-    roof["frac_without_start_sweeps"] = round(
-        (per_q[dom]["bytes"] - per_q[dom]["sweep_bytes_gb"] * 1e9) /
-        (per_q[dom]["avg_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-    roof["frac_minimum_bytes"] = round(min_gbs / HBM_PEAK_GBS, 4)
+    step_ms = float(np.mean([a.elapsed_time(b) for p_, a, b in step_ev if p_ == P.PREC_FP64]))
+    step_bytes = sum(per_q[q]["bytes"] for q in QS)
+    step_gbs_ev = step_bytes / (step_ms / 1e3) / 1e9
+    call = dict(kernel=per_q[dom]["kernel"], achieved=round(per_q[dom]["gbs"], 2),
+                frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
+                algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3),
+                traffic=None if tr is None else round(tr / 1e9, 3))
+    if streams:
+        # the launch unit is the step: its three concurrent calls' bytes over
+        # the step's duration (HIP events on the main stream around it)
+        trs = [measured_traffic(q, per_q[q]["kernel"].replace(" ", "")) for q in QS]
+        tr_step = None if any(t is None for t in trs) else sum(trs)
+        roof = dict(bound="hbm", achieved=round(step_gbs_ev, 2), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(step_gbs_ev / HBM_PEAK_GBS, 4),
+                    traffic=None if tr_step is None else round(tr_step / 1e9, 3),
+                    kernel="step: " + " | ".join(per_q[q]["kernel"] for q in launch_order) +
+                           " (concurrent, one stream per q)",
+                    step_ms_events=round(step_ms, 4),
+                    algorithmic_bytes_per_launch_gb=round(step_bytes / 1e9, 3),
+                    timing="HIP events on the main stream around each step; its three q calls "
+                           "run concurrently on three streams",
+                    dominant_call=call)
+    else:
+        roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
+                    traffic=None if tr is None else round(tr / 1e9, 3),
+                    kernel=per_q[dom]["kernel"],
+                    timing="HIP events around each solve call (one stream)",
+                    algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
+    # the same unit as `achieved` (the step, or the dominant call): without
+    # the start sweeps' bytes, and with only the band, b and u reads
+    units = QS if streams else (dom,)
+    ref_s = (step_ms if streams else per_q[dom]["avg_ms"]) / 1e3
+    no_sw = sum(per_q[q]["bytes"] - per_q[q]["sweep_bytes_gb"] * 1e9 for q in units)
+    min_b = sum((per_q[q]["bytes"] - per_q[q]["sweep_bytes_gb"] * 1e9) /
+                algorithmic_bytes_per_row(q) * minimum_bytes_per_row(q) for q in units)
+    roof["frac_without_start_sweeps"] = round(no_sw / ref_s / 1e9 / HBM_PEAK_GBS, 4)
+    roof["frac_minimum_bytes"] = round(min_b / ref_s / 1e9 / HBM_PEAK_GBS, 4)
+    # the dominant call alone on the GPU
+    roof["dominant_call_alone"] = dict(kernel=per_q[dom]["kernel"],
+                                       ms=round(per_q[dom]["alone_ms"], 4),
+                                       achieved=round(per_q[dom]["gbs_alone"], 2),
+                                       frac=round(per_q[dom]["gbs_alone"] / HBM_PEAK_GBS, 4))
     roof["copy_kernel_gbs"] = round(copy_gbs, 1)
-    roof["frac_vs_copy"] = round(per_q[dom]["gbs"] / copy_gbs, 4)
-    if tr is not None:
-        roof["traffic_unit"] = "GB per launch (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)"
-        roof["measured_hbm_gbs"] = round(tr / (per_q[dom]["avg_ms"] / 1e3) / 1e9, 2)
+    roof["frac_vs_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    if roof["traffic"] is not None:
+        roof["traffic_unit"] = ("GB per " + ("step" if streams else "launch") +
+                                " (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)")
+        roof["measured_hbm_gbs"] = round(roof["traffic"] / ref_s, 2)
 
     log(f"LCP mixed: {ms_mixed:.2f} ms/step")
     cpu = None
@@ -874,7 +944,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batched banded LCP: 3 x 4096 systems, n~U[513,4097], "
                                "q in {2,4,8}, b~N(0,1)",
-                   "systems_per_step": len(QS) * COUNT},
+                   "systems_per_step": len(QS) * COUNT,
+                   "q_batches": "concurrent, one stream each" if streams else "one after another"},
         "per_q": {str(q): {k: (round(v, 4) if isinstance(v, float) else v)
                            for k, v in per_q[q].items() if k != "bytes"} for q in QS},
         "mixed_fp32_ir": {"ms_per_step": round(ms_mixed, 4),
