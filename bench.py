@@ -68,13 +68,11 @@ def sweep_bytes(q, sizes, sweeps):
     from u = 0, paqif_sweep_kernel): its launches run up to 1 + 64/q sweeps
     each with the band rows held on chip, so per row and launch the band
     8(2q+1), b and the iterate written, plus the previous iterate read by
-    every launch after the first.  Counted for the systems with at least
-    0.7 (max_n // 2) elimination levels, the ones the sweeps run on."""
+    every launch after the first; every system is swept."""
     if sweeps <= 0:
         return 0
     launches = -(-sweeps // (1 + 64 // q))
-    npair = sizes // 2
-    rows = int(sizes[npair >= int(0.7 * (int(sizes.max()) // 2))].sum())
+    rows = int(sizes.sum())
     return rows * (launches * (8 * (2 * q + 1) + 16) + (launches - 1) * 8)
 
 

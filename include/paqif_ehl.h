@@ -215,14 +215,13 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * u_i <- (b_i - sum_{j != i} a_ij u_j) / a_ii, clipped at 0 on bounded rows
  * (0 or 1 sweep: A_0 = {bounded i : b_i <= 0}).  The solution does not
  * depend on the start (the active-set iteration ends at the LCP's solution);
- * the number of active-set solves does.  The sweeps run for the systems
- * with at least 0.7 max_n / 2 elimination levels, the ones that set the
- * solve's length (the others take the sign start), as a kernel of their
- * own before the solve: each workgroup holds 256 rows of a system and the
- * band rows within (sweeps - 1) q of them in LDS and runs the sweeps there
- * (one band read for up to 1 + 64 / q sweeps).  0 <= sweeps <=
- * PAQIF_MAX_START_SWEEPS; a new handle uses 12 for q = 2 and 8 for q = 4
- * and 8.  The sweeps write u (and,
+ * the number of active-set solves does (about one per LCP from the sweeps
+ * on the synthetic batches, about three from the sign of b).  The sweeps
+ * run for every system, as a kernel of their own before the solve: each
+ * workgroup holds 512 rows of a system, two per thread with their band
+ * rows in registers, and runs up to 1 + 64 / q sweeps on them (one band
+ * read per launch).  0 <= sweeps <= PAQIF_MAX_START_SWEEPS; a new handle
+ * uses 16 for q = 2 and 12 for q = 4 and 8.  The sweeps write u (and,
  * above 1 + 64 / q sweeps, the workspace's record area).
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),

@@ -152,10 +152,11 @@ def start_sweeps(band, f, bounded=None, k=1):
     return u
 
 
-def lcp_start_sets(q, offsets, band, f, bounded=None, k=0, frac=0.7):
+def lcp_start_sets(q, offsets, band, f, bounded=None, k=0, frac=0.0):
     """Per-system starting active sets of a batch: the systems with at
-    least int(frac * (max_n // 2)) elimination levels (n // 2) from k start
-    sweeps, the others (and all for k == 0) from the sign of f."""
+    least int(frac * (max_n // 2)) elimination levels (n // 2; frac = 0:
+    every system) from k start sweeps, the others (and all for k == 0) from
+    the sign of f."""
     offsets = np.asarray(offsets, dtype=np.int64)
     band = _f64(band).reshape(-1, 2 * q + 1)
     f = _f64(f)

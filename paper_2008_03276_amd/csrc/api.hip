@@ -107,9 +107,10 @@ static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const doubl
     a.skip = nullptr;
     a.warm = 0;
     a.sweeps = mode == LCP_EXACT ? handle->sweeps[pq::q_index(batch->q)][prec != 0] : 0;
-    // the batch's largest systems set the solve's length: they start from
-    // the sweeps, the others from the sign of b
-    a.sweep_min = (int)(0.7 * (double)(batch->max_n / 2));
+    // every system starts from the sweeps: as a kernel of their own they
+    // cost a band read per launch, and they bring the active-set solves per
+    // LCP to about one (from about three from the sign of b)
+    a.sweep_min = 0;
     if (a.sweeps > 0) {
         // second sweep buffer: the record area, free until the solve
         const int e = pq::dispatch_sweeps(batch->q, a, (int)batch->max_n,
@@ -139,7 +140,7 @@ int paqif_create(paqif_handle* handle)
     // 16 rows), FP32 solves with refinement to the lane-per-system layout.
     // Start sweeps of exact solves: measured on 4096 systems of 513-4097
     // rows, the sweep count that gave the fastest solve (q = 2, 4, 8).
-    static const int default_sweeps[3] = {12, 8, 8};
+    static const int default_sweeps[3] = {16, 12, 12};
     for (int qi = 0; qi < 3; qi++) {
         h->layout[qi][PREC_FP64] = 3;
         h->layout[qi][PREC_FP32_IR] = 0;

@@ -46,9 +46,10 @@ struct LcpArgs {
     // lets several systems (e.g. one matrix with several right-hand sides) share rows
     const int64_t* band_off = nullptr;
     // exact mode without a warm start: the systems with at least sweep_min
-    // elimination levels start from the iterate that `sweeps` projected
-    // Jacobi sweeps (dispatch_sweeps, run before the solve) left in u, the
-    // others (and all when sweeps == 0) from the sign of b
+    // elimination levels (paqif_solve_lcp: 0, every system) start from the
+    // iterate that `sweeps` projected Jacobi sweeps (dispatch_sweeps, run
+    // before the solve) left in u, the others (and all when sweeps == 0)
+    // from the sign of b
     int sweeps = 0;
     int sweep_min = 0;
 };

@@ -378,15 +378,14 @@ def test_start_sweeps_iterate_matches_oracle(gpu, q, sweeps):
     system, one launch per 1 + 64/q sweeps) gives the oracle's starting
     active set: one active-set solve (max_iter = 1) from each side's A_0
     gives the same u (a start that differs in one row changes u there by the
-    row's whole value).  The systems under 0.7 (max_n // 2) levels take the
-    sign start on both sides."""
+    row's whole value).  Every system starts from the sweeps."""
     P = gpu
     dev = torch.device("cuda")
     sizes = [4097, 1, 2, 5, 700, 2049, 3001, 2868, 2866, 4000]
     offs, band, f = synth.lcp_batch(len(sizes), q, seed=70 + q, sizes=sizes)
     rng = np.random.default_rng(sweeps)
     bounded = (rng.random(len(f)) < 0.9).astype(np.uint8)
-    start = oracle.lcp_start_sets(q, offs, band, f, bounded, k=sweeps)
+    start = oracle.lcp_start_sets(q, offs, band, f, bounded, k=sweeps, frac=0.0)
     bt = P.paqif.Batch(offs, q, order="lpt")
     keep = P.paqif.get_start_sweeps(q, 0)
     try:

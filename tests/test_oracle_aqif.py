@@ -241,9 +241,10 @@ def test_start_sweeps_converge_to_the_lcp_solution(q):
 
 
 def test_lcp_start_sets_rule():
-    """The batch start rule: the systems with at least 0.7 (max_n // 2)
-    elimination levels from the sweeps, the others from the sign of f; one
-    sweep reproduces the sign start (positive diagonals)."""
+    """The batch start rule with a size threshold: the systems with at
+    least 0.7 (max_n // 2) elimination levels from the sweeps, the others
+    from the sign of f; without one (frac = 0) every system from the
+    sweeps; one sweep reproduces the sign start (positive diagonals)."""
     q = 2
     sizes = [1, 6, 40, 57, 60]
     offs, band, f = synth.lcp_batch(len(sizes), q, seed=3, sizes=sizes)
@@ -251,7 +252,7 @@ def test_lcp_start_sets_rule():
     sign = (bounded != 0) & (f <= 0.0)
     assert np.array_equal(oracle.lcp_start_sets(q, offs, band, f, bounded, k=0), sign)
     assert np.array_equal(oracle.lcp_start_sets(q, offs, band, f, bounded, k=1), sign)
-    st = oracle.lcp_start_sets(q, offs, band, f, bounded, k=6)
+    st = oracle.lcp_start_sets(q, offs, band, f, bounded, k=6, frac=0.7)
     band = band.reshape(-1, 2 * q + 1)
     for s, n in enumerate(sizes):  # levels 0 3 20 28 30; threshold int(0.7 * 30) = 21
         a, b = int(offs[s]), int(offs[s + 1])
@@ -260,6 +261,11 @@ def test_lcp_start_sets_rule():
             assert np.array_equal(st[a:b], (bounded[a:b] != 0) & (u <= 0.0))
         else:
             assert np.array_equal(st[a:b], sign[a:b])
+    st0 = oracle.lcp_start_sets(q, offs, band, f, bounded, k=6)
+    for s, n in enumerate(sizes):
+        a, b = int(offs[s]), int(offs[s + 1])
+        u = oracle.start_sweeps(band[a:b], f[a:b], bounded[a:b], 6)
+        assert np.array_equal(st0[a:b], (bounded[a:b] != 0) & (u <= 0.0))
 
 
 def test_lcp_brute_force_with_free_rows():
