@@ -69,7 +69,8 @@ enum {
 enum {
     LCP_LINEAR = 0, /* u = A^{-1} b, no projection                         */
     LCP_CLIP = 1,   /* u = max(0, A^{-1} b) on bounded rows (projection)    */
-    LCP_EXACT = 2   /* exact LCP by a primal-dual active-set iteration      */
+    LCP_EXACT = 2,  /* exact LCP by a primal-dual active-set iteration      */
+    LCP_EXACT_FROM_U = 3 /* LCP_EXACT started from the u passed in          */
 };
 
 /* Library handle: device properties.  Create once per process/device. */
@@ -152,11 +153,16 @@ int paqif_solve_factored(paqif_handle handle, const paqif_batch *batch, const vo
  *                   A_k), w = A u - b,
  *                   A_{k+1} = {i in A_k : w_i > 0} u {i not in A_k : u_i < 0}
  *                   (bounded rows), until A_{k+1} = A_k or max_iter solves.
+ *  mode LCP_EXACT_FROM_U: LCP_EXACT with A_0 = {bounded i : u_i <= 0} for
+ *                   the u passed in (DEVICE in and out; typically the
+ *                   iterate of paqif_start_sweeps, which makes the result
+ *                   that of LCP_EXACT bit for bit); no start sweeps run.
  *  prec       : PREC_FP64, or PREC_FP32_IR (FP32 factors; every solve is
  *               refined with FP64 residuals until |r|_inf <= refine_tol *
  *               max(|b|_inf, 1) or 8 refinement steps, else
  *               SYS_REFINE_STALLED).
- *  u          : DEVICE out, total_rows doubles.
+ *  u          : DEVICE out, total_rows doubles (in and out with
+ *               LCP_EXACT_FROM_U).
  *  w          : DEVICE out or NULL, total_rows doubles, w = A u - b.
  *  active_out : DEVICE out or NULL, uint8 per row (1 = u_i pinned at 0).
  *  sys_status : DEVICE out, int32[count].
@@ -221,14 +227,15 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * workgroup holds 512 rows of a system, two per thread with their band
  * rows in registers, and runs up to 1 + 64 / q sweeps on them (one band
  * read per launch).  0 <= sweeps <= PAQIF_MAX_START_SWEEPS; a new handle
- * uses 16 for q = 2 and 12 for q = 4 and 8.  The sweeps write u (and,
+ * uses 16 for q = 2 and 4 and 12 for q = 8.  The sweeps write u (and,
  * above 1 + 64 / q sweeps, the workspace's record area).
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),
  * stores the fastest in the handle and, if times_ms (host, float[count]) is
  * not NULL, the measured times; in mode LCP_EXACT it then times the start
- * sweeps 0, 2, 4, 6, 8, 12, 16 with that layout and keeps the fastest.  Arguments
- * as for paqif_solve_lcp; u, sys_status and workspace are used as scratch.
+ * sweeps 0, 2, 4, 6, 8, 12, 16, 20, 24, 32 with that layout and keeps the
+ * fastest.  Arguments as for paqif_solve_lcp; u, sys_status and workspace
+ * are used as scratch.
  */
 #define PAQIF_MAX_START_SWEEPS 32
 int paqif_layout_count(int q);
@@ -236,6 +243,60 @@ int paqif_set_layout(paqif_handle handle, int q, int prec, int layout);
 int paqif_get_layout(paqif_handle handle, int q, int prec);
 int paqif_set_start_sweeps(paqif_handle handle, int q, int prec, int sweeps);
 int paqif_get_start_sweeps(paqif_handle handle, int q, int prec);
+
+/*
+ * paqif_solve_lcp_many -- several paqif_solve_lcp calls on one stream (each
+ * its own batch, e.g. one per half-bandwidth q), with the results of calling
+ * paqif_solve_lcp for each in turn with the same mode, prec, refine_tol and
+ * max_iter, bit for bit.  Their order on the chip differs: every call's start
+ * sweeps run first (bandwidth-bound kernels that fill the chip), then the
+ * FP64 solves of the calls whose (q, prec) uses the row layout run in ONE
+ * launch, workgroup g taking wave g / ncalls' of call g mod ncalls' (ncalls'
+ * of them), so that the first waves of every call, which hold its largest
+ * systems in LPT order, start together and the batches share the chip from
+ * the start; the other calls' solves follow, one kernel each.  (Sec. 2
+ * algorithm, batched; the scheduling is this library's.)
+ *  ncalls : 0 <= ncalls <= PAQIF_MAX_LCP_CALLS.
+ *  calls  : HOST, ncalls entries; each entry's pointers as for
+ *           paqif_solve_lcp.  Calls may not share an output array or a
+ *           workspace (they run concurrently).
+ * Returns PAQIF_EINVAL for a bad count, batch, mode or prec, or a null
+ * pointer a non-empty call needs.
+ */
+#define PAQIF_MAX_LCP_CALLS 8
+typedef struct paqif_lcp_call {
+    const paqif_batch *batch;
+    const double *band;
+    const double *b;
+    const uint8_t *bounded;
+    double *u;
+    double *w;
+    uint8_t *active_out;
+    int32_t *sys_status;
+    int32_t *sys_iters;
+    void *workspace;
+} paqif_lcp_call;
+int paqif_solve_lcp_many(paqif_handle handle, int ncalls, const paqif_lcp_call *calls, int mode,
+                         int prec, double refine_tol, int max_iter, void *stream);
+
+/*
+ * paqif_start_sweeps -- the starting iterate of LCP_EXACT on its own: the
+ * handle's start sweeps for (batch->q, prec) from u = 0 into u (with 0
+ * sweeps, u = b, whose signs give the same A_0).  A following
+ * paqif_solve_lcp in mode LCP_EXACT_FROM_U with this u solves exactly as one
+ * LCP_EXACT call; split in two, the sweeps of several batches can run
+ * before their solves (a bandwidth-bound kernel that fills the chip ahead of
+ * latency-bound ones).
+ *  band, b, bounded : as for paqif_solve_lcp.
+ *  u         : DEVICE out, total_rows doubles.
+ *  workspace : DEVICE, paqif_workspace_bytes(handle, batch, prec,
+ *              LCP_EXACT); its record area holds the iterate between
+ *              launches when the sweeps take several (above 1 + 64 / q).
+ * Returns PAQIF_EINVAL for a bad batch, prec or null pointer.
+ */
+int paqif_start_sweeps(paqif_handle handle, const paqif_batch *batch, const double *band,
+                       const double *b, const uint8_t *bounded, int prec, double *u,
+                       void *workspace, void *stream);
 int paqif_autotune(paqif_handle handle, const paqif_batch *batch, const double *band,
                    const double *b, const uint8_t *bounded, int mode, int prec, int max_iter,
                    double *u, int32_t *sys_status, void *workspace, void *stream,

@@ -18,13 +18,24 @@ SYS_OK, SYS_ZERO_PIVOT, SYS_NONFINITE, SYS_LCP_NOT_CONVERGED = 0, 1, 2, 3
 SYS_REFINE_STALLED, SYS_NEGATIVE_FILM, SYS_NEWTON_NOT_CONVERGED = 4, 5, 6
 SYS_ADJOINT_NOT_CONVERGED = 7
 PREC_FP64, PREC_FP32_IR, PREC_SPLIT_BF16, PREC_FP32 = 0, 1, 2, 3
-LCP_LINEAR, LCP_CLIP, LCP_EXACT = 0, 1, 2
+LCP_LINEAR, LCP_CLIP, LCP_EXACT, LCP_EXACT_FROM_U = 0, 1, 2, 3
 
 
 class PaqifBatch(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("offsets", ctypes.c_void_p), ("max_n", ctypes.c_int64),
                 ("total_rows", ctypes.c_int64), ("order", ctypes.c_void_p)]
+
+
+class PaqifLcpCall(ctypes.Structure):
+    _fields_ = [("batch", ctypes.POINTER(PaqifBatch)), ("band", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("bounded", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("active_out", ctypes.c_void_p),
+                ("sys_status", ctypes.c_void_p), ("sys_iters", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p)]
+
+
+MAX_LCP_CALLS = 8
 
 
 class EhlGrid(ctypes.Structure):
@@ -85,6 +96,9 @@ def lib():
         "paqif_get_layout": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "paqif_set_start_sweeps": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "paqif_get_start_sweeps": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "paqif_start_sweeps": ([vp, bp, vp, vp, vp, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "paqif_solve_lcp_many": ([vp, ctypes.c_int, ctypes.POINTER(PaqifLcpCall), ctypes.c_int,
+                                  ctypes.c_int, d, ctypes.c_int, vp], ctypes.c_int),
         "paqif_autotune": ([vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
                             vp, vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "ehl_deformation_workspace_bytes": ([ctypes.POINTER(EhlGrid), ctypes.c_int],

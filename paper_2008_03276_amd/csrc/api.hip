@@ -80,11 +80,13 @@ LcpLayout lcp_layout_tight(const paqif_batch* b, int prec)
 }
 }  // namespace
 
-static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const double* band,
-                      const double* b, const uint8_t* bounded, int mode, int prec,
-                      double refine_tol, int max_iter, double* u, double* w,
-                      uint8_t* active_out, int32_t* sys_status, int32_t* sys_iters, char* ws,
-                      const LcpLayout& L, void* stream)
+// Kernel arguments of one LCP solve (a.sweeps: the start sweeps to run
+// first, 0 for none, 1 with LCP_EXACT_FROM_U whose start is u as passed in).
+static pq::LcpArgs lcp_args(paqif_handle handle, const paqif_batch* batch, const double* band,
+                            const double* b, const uint8_t* bounded, int mode, int prec,
+                            double refine_tol, int max_iter, double* u, double* w,
+                            uint8_t* active_out, int32_t* sys_status, int32_t* sys_iters,
+                            char* ws, const LcpLayout& L)
 {
     pq::LcpArgs a;
     a.count = batch->count;
@@ -93,7 +95,9 @@ static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const doubl
     a.band = band;
     a.b = b;
     a.bounded = bounded;
-    a.mode = mode;
+    // LCP_EXACT_FROM_U: the exact kernels, reading their start from u
+    const bool from_u = mode == LCP_EXACT_FROM_U;
+    a.mode = from_u ? LCP_EXACT : mode;
     a.max_iter = max_iter;
     a.refine_tol = refine_tol;
     a.u = u;
@@ -111,12 +115,29 @@ static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const doubl
     // cost a band read per launch, and they bring the active-set solves per
     // LCP to about one (from about three from the sign of b)
     a.sweep_min = 0;
-    if (a.sweeps > 0) {
-        // second sweep buffer: the record area, free until the solve
-        const int e = pq::dispatch_sweeps(batch->q, a, (int)batch->max_n,
-                                          reinterpret_cast<double*>(ws), (hipStream_t)stream);
-        if (e) return e;
-    }
+    if (from_u) a.sweeps = 1;  // the kernels' start is then the sign of u as passed in
+    return a;
+}
+
+// The start sweeps of a (none for LCP_EXACT_FROM_U, whose u is the start);
+// second sweep buffer: the record area, free until the solve.
+static int run_sweeps(const paqif_batch* batch, const pq::LcpArgs& a, int mode, char* ws,
+                      hipStream_t s)
+{
+    if (mode == LCP_EXACT_FROM_U || a.sweeps <= 0) return PAQIF_OK;
+    return pq::dispatch_sweeps(batch->q, a, (int)batch->max_n, reinterpret_cast<double*>(ws), s);
+}
+
+static int launch_lcp(paqif_handle handle, const paqif_batch* batch, const double* band,
+                      const double* b, const uint8_t* bounded, int mode, int prec,
+                      double refine_tol, int max_iter, double* u, double* w,
+                      uint8_t* active_out, int32_t* sys_status, int32_t* sys_iters, char* ws,
+                      const LcpLayout& L, void* stream)
+{
+    const pq::LcpArgs a = lcp_args(handle, batch, band, b, bounded, mode, prec, refine_tol,
+                                   max_iter, u, w, active_out, sys_status, sys_iters, ws, L);
+    const int e = run_sweeps(batch, a, mode, ws, (hipStream_t)stream);
+    if (e) return e;
     return pq::dispatch_lcp(batch->q, a, prec, handle->layout[pq::q_index(batch->q)][prec != 0],
                             (hipStream_t)stream);
 }
@@ -140,7 +161,7 @@ int paqif_create(paqif_handle* handle)
     // 16 rows), FP32 solves with refinement to the lane-per-system layout.
     // Start sweeps of exact solves: measured on 4096 systems of 513-4097
     // rows, the sweep count that gave the fastest solve (q = 2, 4, 8).
-    static const int default_sweeps[3] = {16, 12, 12};
+    static const int default_sweeps[3] = {16, 16, 12};
     for (int qi = 0; qi < 3; qi++) {
         h->layout[qi][PREC_FP64] = 3;
         h->layout[qi][PREC_FP32_IR] = 0;
@@ -233,11 +254,12 @@ int paqif_solve_lcp(paqif_handle handle, const paqif_batch* batch, const double*
                     int32_t* sys_status, int32_t* sys_iters, void* workspace, void* stream)
 {
     if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
-    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT) return PAQIF_EINVAL;
+    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT && mode != LCP_EXACT_FROM_U)
+        return PAQIF_EINVAL;
     if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
     if (batch->count == 0) return PAQIF_OK;
     if (!band || !b || !u || !sys_status || !workspace) return PAQIF_EINVAL;
-    if (mode == LCP_EXACT && max_iter < 1) return PAQIF_EINVAL;
+    if ((mode == LCP_EXACT || mode == LCP_EXACT_FROM_U) && max_iter < 1) return PAQIF_EINVAL;
     if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
     const LcpLayout L = lcp_layout(batch, prec);
     return launch_lcp(handle, batch, band, b, bounded, mode, prec, refine_tol, max_iter, u, w,
@@ -252,11 +274,12 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch* batch, const
                             void* stream)
 {
     if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
-    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT) return PAQIF_EINVAL;
+    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT && mode != LCP_EXACT_FROM_U)
+        return PAQIF_EINVAL;
     if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
     if (batch->count == 0) return PAQIF_OK;
     if (!band || !b || !u || !sys_status) return PAQIF_EINVAL;
-    if (mode == LCP_EXACT && max_iter < 1) return PAQIF_EINVAL;
+    if ((mode == LCP_EXACT || mode == LCP_EXACT_FROM_U) && max_iter < 1) return PAQIF_EINVAL;
     if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return PAQIF_EHIP;
@@ -268,6 +291,84 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch* batch, const
     return launch_lcp(handle, batch, band, b, bounded, mode, prec, refine_tol, max_iter, u, w,
                       active_out, sys_status, sys_iters, static_cast<char*>(handle->scratch), L,
                       stream);
+}
+
+int paqif_solve_lcp_many(paqif_handle handle, int ncalls, const paqif_lcp_call* calls, int mode,
+                         int prec, double refine_tol, int max_iter, void* stream)
+{
+    if (!handle || ncalls < 0 || ncalls > PAQIF_MAX_LCP_CALLS || (ncalls > 0 && !calls))
+        return PAQIF_EINVAL;
+    if (mode != LCP_LINEAR && mode != LCP_CLIP && mode != LCP_EXACT && mode != LCP_EXACT_FROM_U)
+        return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if ((mode == LCP_EXACT || mode == LCP_EXACT_FROM_U) && max_iter < 1) return PAQIF_EINVAL;
+    if (prec == PREC_FP32_IR && !(refine_tol > 0.0)) return PAQIF_EINVAL;
+    for (int c = 0; c < ncalls; c++) {
+        const paqif_lcp_call& k = calls[c];
+        if (!valid_batch(k.batch)) return PAQIF_EINVAL;
+        if (k.batch->count > 0 && (!k.band || !k.b || !k.u || !k.sys_status || !k.workspace))
+            return PAQIF_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // every call's start sweeps first (bandwidth-bound, the whole chip), then
+    // the solves: the FP64 row-layout ones in one launch, the others each in
+    // its own kernel
+    pq::RowsManyArgs m;
+    m.n = 0;
+    static_assert(PAQIF_MAX_LCP_CALLS <= pq::kMaxManyCalls, "many-call launch size");
+    pq::LcpArgs args[PAQIF_MAX_LCP_CALLS];
+    for (int c = 0; c < ncalls; c++) {
+        const paqif_lcp_call& k = calls[c];
+        if (k.batch->count == 0) continue;
+        const LcpLayout L = lcp_layout(k.batch, prec);
+        char* ws = static_cast<char*>(k.workspace);
+        args[c] = lcp_args(handle, k.batch, k.band, k.b, k.bounded, mode, prec, refine_tol,
+                           max_iter, k.u, k.w, k.active_out, k.sys_status, k.sys_iters, ws, L);
+        const int e = run_sweeps(k.batch, args[c], mode, ws, s);
+        if (e) return e;
+    }
+    for (int c = 0; c < ncalls; c++) {
+        const paqif_lcp_call& k = calls[c];
+        if (k.batch->count == 0) continue;
+        const int layout = handle->layout[pq::q_index(k.batch->q)][prec != 0];
+        if (prec == PREC_FP64 && layout == 3) {
+            m.a[m.n] = args[c];
+            m.q[m.n] = k.batch->q;
+            m.waves[m.n] = pq::rows_waves(k.batch->count);
+            m.n++;
+        } else {
+            const int e = pq::dispatch_lcp(k.batch->q, args[c], prec, layout, s);
+            if (e) return e;
+        }
+    }
+    return m.n > 0 ? pq::dispatch_lcp_rows_many(m, s) : PAQIF_OK;
+}
+
+int paqif_start_sweeps(paqif_handle handle, const paqif_batch* batch, const double* band,
+                       const double* b, const uint8_t* bounded, int prec, double* u,
+                       void* workspace, void* stream)
+{
+    if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    if (prec != PREC_FP64 && prec != PREC_FP32_IR) return PAQIF_EINVAL;
+    if (batch->count == 0) return PAQIF_OK;
+    if (!band || !b || !u || !workspace) return PAQIF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int k = handle->sweeps[pq::q_index(batch->q)][prec != 0];
+    if (k == 0)  // the sign start: u = b
+        return pq::hip_ok(hipMemcpyAsync(u, b, (size_t)batch->total_rows * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s))
+                   ? PAQIF_OK
+                   : PAQIF_EHIP;
+    pq::LcpArgs a;
+    a.count = batch->count;
+    a.offsets = batch->offsets;
+    a.band = band;
+    a.b = b;
+    a.bounded = bounded;
+    a.u = u;
+    a.sweeps = k;
+    a.sweep_min = 0;
+    return pq::dispatch_sweeps(batch->q, a, (int)batch->max_n, static_cast<double*>(workspace), s);
 }
 
 int paqif_layout_count(int q) { return pq::layouts_for(q); }
@@ -310,6 +411,8 @@ int paqif_autotune(paqif_handle handle, const paqif_batch* batch, const double* 
                    float* times_ms)
 {
     if (!handle || !valid_batch(batch)) return PAQIF_EINVAL;
+    // u is scratch here: a start from u is timed as the sweeps' start
+    if (mode == LCP_EXACT_FROM_U) mode = LCP_EXACT;
     const int nl = pq::layouts_for(batch->q);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -343,7 +446,7 @@ int paqif_autotune(paqif_handle handle, const paqif_batch* batch, const double* 
     handle->layout[pq::q_index(batch->q)][prec != 0] = best;
     // exact mode: then the start sweeps with that layout
     if (st == PAQIF_OK && mode == LCP_EXACT) {
-        static const int cand[] = {0, 2, 4, 6, 8, 12, 16};
+        static const int cand[] = {0, 2, 4, 6, 8, 12, 16, 20, 24, 32};
         int& sw = handle->sweeps[pq::q_index(batch->q)][prec != 0];
         int best_sw = sw;
         float best_sw_ms = -1.0f;

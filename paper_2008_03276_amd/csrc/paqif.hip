@@ -2289,16 +2289,16 @@ struct RowLds {
     alignas(16) double dum[2 * 64 + rows::RG<Q>::DUM];  // discarded writes
 };
 
-// Whole LCP solve in the row layout (FP64), four systems per wave.
+// Whole LCP solve in the row layout (FP64), four systems per wave: the
+// systems of wave `wave` of the call A, with the wave's LDS in `lds`.
 template <int Q>
-__global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
+PQ_DEV void lcp_rows_wave(const LcpArgs& A, int wave, RowLds<Q>& lds)
 {
     using G = rows::RG<Q>;
-    __shared__ RowLds<Q> lds;
     const int lane = threadIdx.x;
     const int grp = lane >> 4;
     const int ls = lane & 15;
-    const int slot = blockIdx.x * rows::SPW + grp;
+    const int slot = wave * rows::SPW + grp;
     bool live = slot < A.count;
     int sys = live ? (A.order ? A.order[slot] : slot) : 0;
     if (live && A.skip && A.skip[sys]) live = false;
@@ -2406,6 +2406,51 @@ __global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
         }
     }
 }
+
+template <int Q>
+__global__ void __launch_bounds__(64) paqif_lcp_rows_kernel(LcpArgs A)
+{
+    __shared__ RowLds<Q> lds;
+    lcp_rows_wave<Q>(A, blockIdx.x, lds);
+}
+
+// Several calls in one launch (each of its own q): workgroup g takes wave
+// g / n of call g mod n, so the calls' waves interleave and the first
+// (largest, in LPT order) waves of every call start first.  The wave's LDS
+// is one block sized for the largest q.
+constexpr size_t kRowsLds = sizeof(RowLds<8>) > sizeof(RowLds<4>)
+                                ? (sizeof(RowLds<8>) > sizeof(RowLds<2>) ? sizeof(RowLds<8>)
+                                                                         : sizeof(RowLds<2>))
+                                : (sizeof(RowLds<4>) > sizeof(RowLds<2>) ? sizeof(RowLds<4>)
+                                                                         : sizeof(RowLds<2>));
+
+__global__ void __launch_bounds__(64) paqif_lcp_rows_many_kernel(RowsManyArgs M)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char raw[kRowsLds];
+    const int c = (int)(blockIdx.x % (unsigned)M.n);
+    const int wave = (int)(blockIdx.x / (unsigned)M.n);
+    if (wave >= M.waves[c]) return;  // the whole workgroup
+    switch (M.q[c]) {
+    case 2: lcp_rows_wave<2>(M.a[c], wave, *reinterpret_cast<RowLds<2>*>(raw)); break;
+    case 4: lcp_rows_wave<4>(M.a[c], wave, *reinterpret_cast<RowLds<4>*>(raw)); break;
+    default: lcp_rows_wave<8>(M.a[c], wave, *reinterpret_cast<RowLds<8>*>(raw)); break;
+    }
+}
+
+int dispatch_lcp_rows_many(const RowsManyArgs& m, hipStream_t s)
+{
+    if (m.n < 1 || m.n > kMaxManyCalls) return PAQIF_EINVAL;
+    int wmax = 0;
+    for (int c = 0; c < m.n; c++) {
+        if (m.q[c] != 2 && m.q[c] != 4 && m.q[c] != 8) return PAQIF_EINVAL;
+        wmax = m.waves[c] > wmax ? m.waves[c] : wmax;
+    }
+    if (wmax == 0) return PAQIF_OK;
+    hipLaunchKernelGGL(paqif_lcp_rows_many_kernel, dim3(wmax * m.n), dim3(64), 0, s, m);
+    return hip_ok(hipGetLastError()) ? PAQIF_OK : PAQIF_EHIP;
+}
+
+int rows_waves(int count) { return (count + rows::SPW - 1) / rows::SPW; }
 
 
 // --------------------------------------------------------------------------

@@ -92,6 +92,18 @@ struct SolveArgs {
 };
 
 int dispatch_lcp(int q, const LcpArgs& a, int prec, int layout, hipStream_t s);
+
+// Several FP64 row-layout solves in one launch (paqif_lcp_rows_many_kernel):
+// call c has half-bandwidth q[c] and waves[c] = rows_waves(count) waves.
+constexpr int kMaxManyCalls = 8;
+struct RowsManyArgs {
+    LcpArgs a[kMaxManyCalls];
+    int q[kMaxManyCalls];
+    int waves[kMaxManyCalls];
+    int n;
+};
+int dispatch_lcp_rows_many(const RowsManyArgs& m, hipStream_t s);
+int rows_waves(int count);
 // The start sweeps of an exact solve (a.sweeps of them, into a.u; tmp: a
 // second buffer of total-rows doubles when they take several launches).
 int dispatch_sweeps(int q, const LcpArgs& a, int max_n, double* tmp, hipStream_t s);

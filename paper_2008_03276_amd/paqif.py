@@ -99,14 +99,25 @@ class Batch:
 
 
 def solve_lcp(batch, band, b, mode=B.LCP_EXACT, prec=B.PREC_FP64, bounded=None,
-              refine_tol=1e-10, max_iter=64, workspace=None, want_w=True, want_active=True):
+              refine_tol=1e-10, max_iter=64, workspace=None, want_w=True, want_active=True,
+              u=None):
     """PAQIF solve of the banded LCP for every system of ``batch``.
 
+    With mode=LCP_EXACT_FROM_U, ``u`` (the iterate of ``start_sweeps``) is
+    the start and is overwritten by the solution.
     Returns dict(u, w, active, status, iters) (device tensors)."""
     _check_system_args(batch, band, b, bounded)
     dev = band.device
     n = batch.total_rows
-    u = torch.empty(n, dtype=torch.float64, device=dev)
+    if mode == B.LCP_EXACT_FROM_U:
+        if u is None:
+            raise ValueError("mode LCP_EXACT_FROM_U needs the start iterate u")
+        _need(u, torch.float64, "u")
+        _need_len(u, n, "u")
+    elif u is not None:
+        raise ValueError("u is an input only with mode LCP_EXACT_FROM_U")
+    else:
+        u = torch.empty(n, dtype=torch.float64, device=dev)
     w = torch.empty(n, dtype=torch.float64, device=dev) if want_w else None
     act = torch.empty(n, dtype=torch.uint8, device=dev) if want_active else None
     st = torch.empty(batch.count, dtype=torch.int32, device=dev)
@@ -149,6 +160,73 @@ def solve_lcp_noalloc(batch, band, b, u, status, mode=B.LCP_EXACT, prec=B.PREC_F
                                            _ptr(bounded), mode, prec, refine_tol, max_iter,
                                            _ptr(u), _ptr(w), _ptr(active), _ptr(status),
                                            _ptr(iters), _stream())
+
+
+def solve_lcp_many(calls, mode=B.LCP_EXACT, prec=B.PREC_FP64, refine_tol=1e-10, max_iter=64,
+                   want_w=True, want_active=True):
+    """Several ``solve_lcp`` calls in one (paqif_solve_lcp_many): ``calls`` is
+    a list of dicts with keys batch, band, b and optionally bounded,
+    workspace (distinct per call) and u (the start with LCP_EXACT_FROM_U).
+    Every call's start sweeps run first, then the FP64 row-layout solves of
+    all calls in one launch.  Returns one result dict per call, as
+    ``solve_lcp``."""
+    if len(calls) > B.MAX_LCP_CALLS:
+        raise ValueError(f"at most {B.MAX_LCP_CALLS} calls")
+    arr = (B.PaqifLcpCall * max(len(calls), 1))()
+    out = []
+    keep = []
+    for i, c in enumerate(calls):
+        batch, band, b = c["batch"], c["band"], c["b"]
+        bounded = c.get("bounded")
+        _check_system_args(batch, band, b, bounded)
+        dev = band.device
+        n = batch.total_rows
+        u = c.get("u")
+        if mode == B.LCP_EXACT_FROM_U:
+            if u is None:
+                raise ValueError("mode LCP_EXACT_FROM_U needs the start iterate u")
+            _need(u, torch.float64, "u")
+            _need_len(u, n, "u")
+        elif u is not None:
+            raise ValueError("u is an input only with mode LCP_EXACT_FROM_U")
+        else:
+            u = torch.empty(n, dtype=torch.float64, device=dev)
+        w = torch.empty(n, dtype=torch.float64, device=dev) if want_w else None
+        act = torch.empty(n, dtype=torch.uint8, device=dev) if want_active else None
+        st = torch.empty(batch.count, dtype=torch.int32, device=dev)
+        it = torch.empty(batch.count, dtype=torch.int32, device=dev)
+        ws = c.get("workspace")
+        if ws is None:
+            ws = batch.workspace(prec, mode)
+        _check_workspace(batch, ws, prec, mode)
+        arr[i] = B.PaqifLcpCall(ctypes.pointer(batch.c), _ptr(band), _ptr(b), _ptr(bounded),
+                                _ptr(u), _ptr(w), _ptr(act), _ptr(st), _ptr(it), _ptr(ws))
+        keep.append(ws)
+        out.append(dict(u=u, w=w, active=act, status=st, iters=it))
+    code = B.lib().paqif_solve_lcp_many(handle(), len(calls), arr, mode, prec, refine_tol,
+                                        max_iter, _stream())
+    B.check(code, "paqif_solve_lcp_many")
+    return out
+
+
+def start_sweeps(batch, band, b, prec=B.PREC_FP64, bounded=None, workspace=None, u=None):
+    """The exact LCP's starting iterate alone (the handle's start sweeps for
+    (q, prec)); pass it to ``solve_lcp(..., mode=LCP_EXACT_FROM_U, u=u)``.
+    ``workspace``: as for solve_lcp in mode LCP_EXACT (its record area holds
+    the iterate between launches).  Returns u."""
+    _check_system_args(batch, band, b, bounded)
+    if u is None:
+        u = torch.empty(batch.total_rows, dtype=torch.float64, device=band.device)
+    _need(u, torch.float64, "u")
+    _need_len(u, batch.total_rows, "u")
+    if workspace is None:
+        workspace = batch.workspace(prec, B.LCP_EXACT)
+    _check_workspace(batch, workspace, prec, B.LCP_EXACT)
+    code = B.lib().paqif_start_sweeps(handle(), ctypes.byref(batch.c), _ptr(band), _ptr(b),
+                                      _ptr(bounded), int(prec), _ptr(u), _ptr(workspace),
+                                      _stream())
+    B.check(code, "paqif_start_sweeps")
+    return u
 
 
 def factor(batch, band, pinned=None, factors=None, prec=B.PREC_FP64):

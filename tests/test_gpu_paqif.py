@@ -406,6 +406,129 @@ def test_start_sweeps_iterate_matches_oracle(gpu, q, sweeps):
         assert _relerr(u[a:b], o["u"]) < 1e-12, (s, sizes[s])
 
 
+@pytest.mark.parametrize("q", [2, 4, 8])
+@pytest.mark.parametrize("sweeps", [0, 3, 12, 20])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_start_sweeps_split_matches_exact(gpu, q, sweeps, prec):
+    """The start sweeps on their own (paqif_start_sweeps) followed by the
+    solve from that iterate (LCP_EXACT_FROM_U) is one LCP_EXACT call split in
+    two: the same u, w, active set, statuses and solve counts, bit for bit,
+    with one sweep launch and several (q = 8 above 9 sweeps, q = 4 above 17),
+    and the sign start (0 sweeps: u = b); the oracle's active set too."""
+    P = gpu
+    dev = torch.device("cuda")
+    sizes = [4097, 1, 2, 5, 700, 2049, 3001, 0, 2868, 513]
+    offs, band, f = synth.lcp_batch(len(sizes), q, seed=90 + q, sizes=sizes)
+    rng = np.random.default_rng(sweeps + 7)
+    bounded = (rng.random(len(f)) < 0.9).astype(np.uint8)
+    bt = P.paqif.Batch(offs, q, order="lpt")
+    bd, fd = torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev)
+    kd = torch.as_tensor(bounded, device=dev)
+    keep = P.paqif.get_start_sweeps(q, prec)
+    try:
+        P.paqif.set_start_sweeps(q, prec, sweeps)
+        print(f"split start q={q} k={sweeps} prec={prec}", flush=True)
+        ref = P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT, prec=prec, bounded=kd)
+        ws = bt.workspace(prec)
+        u0 = P.paqif.start_sweeps(bt, bd, fd, prec=prec, bounded=kd, workspace=ws)
+        got = P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT_FROM_U, prec=prec, bounded=kd,
+                                workspace=ws, u=u0)
+        torch.cuda.synchronize()
+    finally:
+        P.paqif.set_start_sweeps(q, prec, keep)
+    assert got["u"].data_ptr() == u0.data_ptr()
+    for k in ("u", "w", "active", "status", "iters"):
+        assert torch.equal(got[k].cpu(), ref[k].cpu()), k
+    st = got["status"].cpu().numpy()
+    assert (st == 0).all(), st
+    o = oracle.lcp_batch(q, offs, band, f, mode=oracle.EXACT, bounded=bounded)
+    assert (got["active"].cpu().numpy() == o["active"]).all()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_lcp_many_matches_single_calls(gpu, mode, prec):
+    """paqif_solve_lcp_many (every call's start sweeps, then the row-layout
+    solves of all calls in one launch with their waves interleaved, the
+    other layouts one kernel each) gives each call's paqif_solve_lcp result
+    bit for bit: batches of q = 2, 4, 8 (ragged, up to 4097 rows, one with
+    the same q twice, one empty), one of them on another lane layout."""
+    P = gpu
+    dev = torch.device("cuda")
+    specs = [(8, [4097, 33, 1, 700, 2049, 5]), (2, [513, 4000, 2, 17, 0, 3001, 64]),
+             (4, [2868, 9, 1500]), (2, [100, 257, 4097]), (4, []), (4, [65, 1025])]
+    calls, singles = [], []
+    keep_layout = P.paqif.get_layout(4, prec)
+    try:
+        for i, (q, sizes) in enumerate(specs):
+            offs, band, f = synth.lcp_batch(len(sizes), q, seed=300 + i, sizes=sizes)
+            rng = np.random.default_rng(i)
+            bounded = (rng.random(len(f)) < 0.9).astype(np.uint8)
+            bt = P.paqif.Batch(offs, q, order="lpt")
+            bd, fd = torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev)
+            kd = torch.as_tensor(bounded, device=dev)
+            c = dict(batch=bt, band=bd, b=fd, bounded=kd)
+            if mode == 3:
+                c["u"] = P.paqif.start_sweeps(bt, bd, fd, prec=prec, bounded=kd)
+            calls.append(c)
+        # the last q = 4 call on the lane layout 0 (a kernel of its own)
+        print(f"solve_lcp_many mode={mode} prec={prec}", flush=True)
+        P.paqif.set_layout(4, prec, 3 if prec == 0 else 0)
+        got = P.paqif.solve_lcp_many(calls[:5], mode=mode, prec=prec)
+        P.paqif.set_layout(4, prec, 0)
+        got += P.paqif.solve_lcp_many(calls[5:], mode=mode, prec=prec)
+        P.paqif.set_layout(4, prec, 3 if prec == 0 else 0)
+        for i, c in enumerate(calls):
+            if i == 5:
+                P.paqif.set_layout(4, prec, 0)
+            if mode == 3:  # the many-call solve overwrote u: start again
+                c["u"] = P.paqif.start_sweeps(c["batch"], c["band"], c["b"], prec=prec,
+                                              bounded=c["bounded"])
+            singles.append(P.paqif.solve_lcp(c["batch"], c["band"], c["b"], mode=mode, prec=prec,
+                                             bounded=c["bounded"], u=c.get("u")))
+        torch.cuda.synchronize()
+    finally:
+        P.paqif.set_layout(4, prec, keep_layout)
+    for i, (g, r) in enumerate(zip(got, singles)):
+        for k in ("u", "w", "active", "status", "iters"):
+            assert torch.equal(g[k].cpu(), r[k].cpu()), (i, k)
+        assert (g["status"].cpu().numpy() == 0).all(), (i, g["status"])
+    assert P.paqif.solve_lcp_many([], mode=mode, prec=prec) == []
+
+
+def test_solve_lcp_many_argument_checks(gpu):
+    P = gpu
+    dev = torch.device("cuda")
+    offs, band, f = synth.lcp_batch(2, 2, seed=5, sizes=[10, 20])
+    bt = P.paqif.Batch(offs, 2)
+    c = dict(batch=bt, band=torch.as_tensor(band, device=dev), b=torch.as_tensor(f, device=dev))
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp_many([c] * 9)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp_many([c], mode=P.LCP_EXACT_FROM_U)
+    with pytest.raises(RuntimeError):
+        P.paqif.solve_lcp_many([c], mode=7)
+    with pytest.raises(RuntimeError):
+        P.paqif.solve_lcp_many([c], max_iter=0)
+
+
+def test_start_from_u_argument_checks(gpu):
+    P = gpu
+    dev = torch.device("cuda")
+    offs, band, f = synth.lcp_batch(3, 2, seed=5, sizes=[10, 20, 7])
+    bt = P.paqif.Batch(offs, 2)
+    bd, fd = torch.as_tensor(band, device=dev), torch.as_tensor(f, device=dev)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT_FROM_U)
+    with pytest.raises(ValueError):
+        P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT, u=torch.zeros_like(fd))
+    with pytest.raises(ValueError):
+        P.paqif.start_sweeps(bt, bd, fd, u=torch.zeros(5, dtype=torch.float64, device=dev))
+    with pytest.raises(RuntimeError):  # max_iter < 1 is rejected by the library
+        P.paqif.solve_lcp(bt, bd, fd, mode=P.LCP_EXACT_FROM_U, u=torch.zeros_like(fd),
+                          max_iter=0)
+
+
 def test_start_sweeps_argument_checks(gpu):
     P = gpu
     with pytest.raises(RuntimeError):
