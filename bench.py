@@ -216,6 +216,27 @@ def measured_traffic(kernel_q, kernel):
     return float(m_val.group(1)) if h.hexdigest() == m_sha.group(1) else None
 
 
+def measured_step_traffic(kernels):
+    """HBM bytes of one step of the default (one-call) mode, summed over its
+    kernels, from the committed counter summary, if it was taken on these
+    kernels and the current kernel sources (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "paqif_lcp_q8_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_val = re.search(r"traffic_bytes_per_step_fp64:\s*([0-9.eE+]+)", txt)
+    m_ker = re.search(r"traffic_kernels_step:\s*(\S+)", txt)
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    if not (m_val and m_sha and m_ker) or m_ker.group(1) != kernels:
+        return None
+    h = hashlib.sha256()
+    for f in ("paqif.hip", "common.h", "paqif_args.h"):
+        h.update(open(os.path.join(ROOT, "paper_2008_03276_amd", "csrc", f), "rb").read())
+    return float(m_val.group(1)) if h.hexdigest() == m_sha.group(1) else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -653,8 +674,10 @@ def main():
                     help="skip the config-2 run at ~30%% active (keeps counter runs to one batch)")
     ap.add_argument("--part-case", default="",
                     help="n:q:r -- the partitioned leg on this one case only")
-    ap.add_argument("--serial-q", action="store_true",
-                    help="run the three q batches of a step one after another on one stream")
+    ap.add_argument("--step-mode", choices=("many", "streams", "serial"), default="many",
+                    help="how a step runs its three q batches: one paqif_solve_lcp_many call "
+                         "(default), a call per batch on a stream each, or the calls one "
+                         "after another on one stream")
     ap.add_argument("--deformation-only", action="store_true",
                     help="run only the MFMA deformation leg and print its figures")
     ap.add_argument("--convdiff-only", action="store_true",
@@ -702,17 +725,18 @@ def main():
                       ws64=bt.workspace(P.PREC_FP64), ws32=bt.workspace(P.PREC_FP32_IR))
     torch.cuda.synchronize()
 
-    # the three q batches of a step are independent: by default each runs on
-    # a stream of its own (default priority, the longest launched first), so
-    # one batch's waves fill the SIMDs that another's tail leaves idle
-    # (measured with about one active-set solve per LCP: 4.45 ms per step,
-    # against 5.21 with q = 8 beside q = 4 then q = 2 on two streams and
-    # 6.48 one after another); the step ends when all streams have finished
-    # (they wait for the previous step)
+    # the three q batches of a step are independent.  By default a step is
+    # one paqif_solve_lcp_many call: every batch's start sweeps, then one
+    # launch whose workgroups interleave the batches' waves (largest systems
+    # first in each), so the batches share the chip from the start (measured
+    # with about one active-set solve per LCP: 4.20-4.22 ms per step, against
+    # 4.45 with a call per batch on a stream each and 5.5 one after another).
+    # The FP32 + refinement leg has no row layout: its calls run on a stream
+    # each.  The step ends when all its work has finished (the next waits).
     launch_order = sorted(QS, reverse=True)
     main_stream = torch.cuda.current_stream()
-    streams = None if args.serial_q else {q: torch.cuda.Stream() for q in QS}
-    stream_set = [] if streams is None else list(streams.values())
+    step_mode = args.step_mode
+    streams = {q: torch.cuda.Stream() for q in QS}
 
     step_ev = []  # HIP events on the main stream around each timed step
 
@@ -721,31 +745,40 @@ def main():
         if ev is not None:
             s0 = torch.cuda.Event(enable_timing=True)
             s0.record(main_stream)
-        for st_ in stream_set:
-            st_.wait_stream(main_stream)
-        for q in launch_order:
-            g = gpu[q]
-            if streams:
-                torch.cuda.set_stream(streams[q])
-            e0 = e1 = None
-            if ev is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-            out[q] = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT, prec=prec,
-                                       workspace=g["ws64"] if prec == P.PREC_FP64 else g["ws32"],
-                                       refine_tol=1e-10)
-            if ev is not None:
-                e1.record()
-                ev[q].append((e0, e1, out[q]))
-            if streams:
-                torch.cuda.set_stream(main_stream)
-        for st_ in stream_set:
-            main_stream.wait_stream(st_)
+        ws = "ws64" if prec == P.PREC_FP64 else "ws32"
+        if step_mode == "many" and prec == P.PREC_FP64:
+            res = P.paqif.solve_lcp_many(
+                [dict(batch=gpu[q]["bt"], band=gpu[q]["band"], b=gpu[q]["f"], workspace=gpu[q][ws])
+                 for q in launch_order], mode=P.LCP_EXACT, prec=prec, refine_tol=1e-10)
+            out = dict(zip(launch_order, res))
+        else:
+            conc = step_mode != "serial"
+            if conc:
+                for st_ in streams.values():
+                    st_.wait_stream(main_stream)
+            for q in launch_order:
+                g = gpu[q]
+                if conc:
+                    torch.cuda.set_stream(streams[q])
+                e0 = e1 = None
+                if ev is not None:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                out[q] = P.paqif.solve_lcp(g["bt"], g["band"], g["f"], mode=P.LCP_EXACT,
+                                           prec=prec, workspace=g[ws], refine_tol=1e-10)
+                if ev is not None:
+                    e1.record()
+                    ev[q].append((e0, e1, out[q]))
+                if conc:
+                    torch.cuda.set_stream(main_stream)
+            if conc:
+                for st_ in streams.values():
+                    main_stream.wait_stream(st_)
         if ev is not None:
             s1 = torch.cuda.Event(enable_timing=True)
             s1.record(main_stream)
-            step_ev.append((prec, s0, s1))
+            step_ev.append((prec, s0, s1, out))
         return out
 
     tune = {}
@@ -758,13 +791,46 @@ def main():
                 layout=chosen, ms=[round(t, 3) for t in times],
                 start_sweeps=P.paqif.get_start_sweeps(q, prec))
     log(f"autotuned layouts: {tune}")
+    # the calls' start sweeps were tuned one batch at a time; the step runs
+    # the three together, where fewer sweeps can pay (the chip is shared):
+    # a coordinate search over the sweep counts, one q at a time, timing
+    # whole steps (HIP events), keeps the fastest combination
+    def step_ms_now(reps=5):
+        for _ in range(2):
+            step(P.PREC_FP64)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step(P.PREC_FP64)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    best = {q: P.paqif.get_start_sweeps(q, P.PREC_FP64) for q in QS}
+    best_ms = step_ms_now()
+    tried = {",".join(str(best[q]) for q in QS): round(best_ms, 4)}
+    for q in launch_order:
+        for k in (8, 12, 16, 20, 24, 32):
+            if k == best[q]:
+                continue
+            P.paqif.set_start_sweeps(q, P.PREC_FP64, k)
+            ms = step_ms_now()
+            tried[",".join(str(k if p_ == q else best[p_]) for p_ in QS)] = round(ms, 4)
+            if ms < best_ms:
+                best_ms, best[q] = ms, k
+        P.paqif.set_start_sweeps(q, P.PREC_FP64, best[q])
+    tune["step_start_sweeps"] = dict(chosen={str(q): best[q] for q in QS},
+                                     step_ms=round(best_ms, 4), tried_q2_q4_q8=tried)
+    log(f"start sweeps for the step: {best} ({best_ms:.3f} ms)")
     log("inputs resident; warm-up")
     for _ in range(args.warmup):
         step(P.PREC_FP64)
     torch.cuda.synchronize()
     log("timed LCP steps")
 
-    # timed region: K steps, events per solve on the launching stream
+    # timed region: K steps (events around each step on the main stream; in
+    # the stream and serial modes also around each call on its stream)
     ev = {q: [] for q in QS}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -789,26 +855,27 @@ def main():
             alone[q].append((e0, e1))
     torch.cuda.synchronize()
 
+    last = [o for p_, _, _, o in step_ev if p_ == P.PREC_FP64][-1]
     per_q = {}
     for q in QS:
-        durs = [a.elapsed_time(b) for a, b, _ in ev[q]]
-        r = ev[q][-1][2]
+        r = last[q]
         iters = r["iters"].cpu().numpy().astype(np.int64)
         status = r["status"].cpu().numpy()
         sizes = batches[q][0][1:] - batches[q][0][:-1]
         units = int((sizes * iters).sum())  # rows x active-set iterations
-        avg_ms = float(np.mean(durs))
         sw = P.paqif.get_start_sweeps(q, P.PREC_FP64)
         bytes_sweeps = sweep_bytes(q, sizes, sw)
         bytes_alg = units * algorithmic_bytes_per_row(q) + bytes_sweeps
         alone_ms = float(np.mean([a.elapsed_time(b) for a, b in alone[q]]))
-        per_q[q] = dict(avg_ms=avg_ms, alone_ms=alone_ms, iters_mean=float(iters.mean()),
+        # in the stream / serial modes: the call's own HIP events in the step
+        in_step = ({"avg_ms": float(np.mean([a.elapsed_time(b) for a, b, _ in ev[q]]))}
+                   if ev[q] else {})
+        per_q[q] = dict(**in_step, alone_ms=alone_ms, iters_mean=float(iters.mean()),
                         iters_max=int(iters.max()), start_sweeps=sw,
                         sweep_bytes_gb=round(bytes_sweeps / 1e9, 4),
                         status_ok=bool((status == 0).all()),
                         kernel=lcp_call_kernels(P, q, P.PREC_FP64),
                         active_frac=float(r["active"].float().mean().item()),
-                        gbs=bytes_alg / (avg_ms / 1e3) / 1e9,
                         gbs_alone=bytes_alg / (alone_ms / 1e3) / 1e9, bytes=bytes_alg)
 
     log(f"LCP fp64: {ms_per_step:.2f} ms/step")
@@ -859,57 +926,61 @@ def main():
     part = partitioned_leg(P, torch, synth, args) if not args.no_partitioned else None
     copy_gbs = copy_bandwidth(torch)
 
-    dom = max(QS, key=lambda q: per_q[q]["avg_ms"])
-    # the committed counter summary names the call's kernels joined by "+"
-    tr = measured_traffic(dom, per_q[dom]["kernel"].replace(" ", ""))
-    step_ms = float(np.mean([a.elapsed_time(b) for p_, a, b in step_ev if p_ == P.PREC_FP64]))
+    dom = max(QS, key=lambda q: per_q[q]["alone_ms"])
+    step_ms = float(np.mean([a.elapsed_time(b) for p_, a, b, _ in step_ev
+                             if p_ == P.PREC_FP64]))
     step_bytes = sum(per_q[q]["bytes"] for q in QS)
     step_gbs_ev = step_bytes / (step_ms / 1e3) / 1e9
-    call = dict(kernel=per_q[dom]["kernel"], achieved=round(per_q[dom]["gbs"], 2),
-                frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
-                algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3),
-                traffic=None if tr is None else round(tr / 1e9, 3))
-    if streams:
-        # the launch unit is the step: its three concurrent calls' bytes over
-        # the step's duration (HIP events on the main stream around it)
-        trs = [measured_traffic(q, per_q[q]["kernel"].replace(" ", "")) for q in QS]
-        tr_step = None if any(t is None for t in trs) else sum(trs)
-        roof = dict(bound="hbm", achieved=round(step_gbs_ev, 2), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(step_gbs_ev / HBM_PEAK_GBS, 4),
-                    traffic=None if tr_step is None else round(tr_step / 1e9, 3),
-                    kernel="step: " + " || ".join(per_q[q]["kernel"] for q in launch_order) +
-                           " (one stream per q)",
-                    step_ms_events=round(step_ms, 4),
-                    algorithmic_bytes_per_launch_gb=round(step_bytes / 1e9, 3),
-                    timing="HIP events on the main stream around each step; its three q calls "
-                           "run concurrently, one stream each",
-                    dominant_call=call)
+    # the launch unit is the step: its three calls' algorithmic bytes over
+    # its duration (HIP events on the main stream around it)
+    if step_mode == "many":
+        sweeps = [f"paqif_sweep_kernel<{q}>" for q in launch_order
+                  if P.paqif.get_start_sweeps(q, P.PREC_FP64) > 0]
+        kernel = ("step: " + " + ".join(sweeps) + (" then " if sweeps else "") +
+                  "paqif_lcp_rows_many_kernel (q = " +
+                  ", ".join(str(q) for q in launch_order) + " in one launch)")
+        timing = ("HIP events on the main stream around each step: one "
+                  "paqif_solve_lcp_many call (the three batches' start sweeps, then one "
+                  "solve launch)")
+        # the committed counter summary names the step's kernels joined by "+"
+        tr_step = measured_step_traffic("+".join(
+            [f"paqif_sweep_kernel<{q}>" for q in launch_order
+             if P.paqif.get_start_sweeps(q, P.PREC_FP64) > 0] + ["paqif_lcp_rows_many_kernel"]))
     else:
-        roof = dict(bound="hbm", achieved=round(per_q[dom]["gbs"], 2), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(per_q[dom]["gbs"] / HBM_PEAK_GBS, 4),
-                    traffic=None if tr is None else round(tr / 1e9, 3),
-                    kernel=per_q[dom]["kernel"],
-                    timing="HIP events around each solve call (one stream)",
-                    algorithmic_bytes_per_launch_gb=round(per_q[dom]["bytes"] / 1e9, 3))
-    # the same unit as `achieved` (the step, or the dominant call): without
-    # the start sweeps' bytes, and with only the band, b and u reads
-    units = QS if streams else (dom,)
-    ref_s = (step_ms if streams else per_q[dom]["avg_ms"]) / 1e3
-    no_sw = sum(per_q[q]["bytes"] - per_q[q]["sweep_bytes_gb"] * 1e9 for q in units)
+        sep = " || " if step_mode == "streams" else " then "
+        kernel = "step: " + sep.join(per_q[q]["kernel"] for q in launch_order) + (
+            " (one stream per q)" if step_mode == "streams" else " (one stream)")
+        timing = ("HIP events on the main stream around each step; its three q calls " +
+                  ("run concurrently, one stream each" if step_mode == "streams"
+                   else "one after another"))
+        tr_step = None
+    roof = dict(bound="hbm", achieved=round(step_gbs_ev, 2), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(step_gbs_ev / HBM_PEAK_GBS, 4),
+                traffic=None if tr_step is None else round(tr_step / 1e9, 3),
+                kernel=kernel, step_ms_events=round(step_ms, 4),
+                algorithmic_bytes_per_launch_gb=round(step_bytes / 1e9, 3), timing=timing)
+    # the same unit: without the start sweeps' bytes, and with only the band,
+    # b and u reads
+    ref_s = step_ms / 1e3
+    no_sw = sum(per_q[q]["bytes"] - per_q[q]["sweep_bytes_gb"] * 1e9 for q in QS)
     min_b = sum((per_q[q]["bytes"] - per_q[q]["sweep_bytes_gb"] * 1e9) /
-                algorithmic_bytes_per_row(q) * minimum_bytes_per_row(q) for q in units)
+                algorithmic_bytes_per_row(q) * minimum_bytes_per_row(q) for q in QS)
     roof["frac_without_start_sweeps"] = round(no_sw / ref_s / 1e9 / HBM_PEAK_GBS, 4)
     roof["frac_minimum_bytes"] = round(min_b / ref_s / 1e9 / HBM_PEAK_GBS, 4)
-    # the dominant call alone on the GPU
+    # the dominant call (the longest alone) on its own on the GPU, with the
+    # counter traffic of that call when the summary holds it
+    tr = measured_traffic(dom, per_q[dom]["kernel"].replace(" ", ""))
     roof["dominant_call_alone"] = dict(kernel=per_q[dom]["kernel"],
                                        ms=round(per_q[dom]["alone_ms"], 4),
                                        achieved=round(per_q[dom]["gbs_alone"], 2),
-                                       frac=round(per_q[dom]["gbs_alone"] / HBM_PEAK_GBS, 4))
+                                       frac=round(per_q[dom]["gbs_alone"] / HBM_PEAK_GBS, 4),
+                                       algorithmic_bytes_per_launch_gb=round(
+                                           per_q[dom]["bytes"] / 1e9, 3),
+                                       traffic=None if tr is None else round(tr / 1e9, 3))
     roof["copy_kernel_gbs"] = round(copy_gbs, 1)
     roof["frac_vs_copy"] = round(roof["achieved"] / copy_gbs, 4)
     if roof["traffic"] is not None:
-        roof["traffic_unit"] = ("GB per " + ("step" if streams else "launch") +
-                                " (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)")
+        roof["traffic_unit"] = "GB per step (FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)"
         roof["measured_hbm_gbs"] = round(roof["traffic"] / ref_s, 2)
 
     log(f"LCP mixed: {ms_mixed:.2f} ms/step")
@@ -943,7 +1014,9 @@ def main():
         "config": {"workload": "batched banded LCP: 3 x 4096 systems, n~U[513,4097], "
                                "q in {2,4,8}, b~N(0,1)",
                    "systems_per_step": len(QS) * COUNT,
-                   "q_batches": "concurrent, one stream each" if streams else "one after another"},
+                   "q_batches": {"many": "one paqif_solve_lcp_many call",
+                                 "streams": "concurrent, one stream each",
+                                 "serial": "one after another"}[step_mode]},
         "per_q": {str(q): {k: (round(v, 4) if isinstance(v, float) else v)
                            for k, v in per_q[q].items() if k != "bytes"} for q in QS},
         "mixed_fp32_ir": {"ms_per_step": round(ms_mixed, 4),
