@@ -65,13 +65,13 @@ def lcp_kernel_name(P, q, prec):
 
 def sweep_bytes(q, sizes, sweeps):
     """Algorithmic bytes of the exact LCP's start sweeps (projected Jacobi
-    from u = 0, paqif_sweep_kernel): its launches run up to 1 + 64/q sweeps
+    from u = 0, paqif_sweep_kernel): its launches run up to 1 + 128/q sweeps
     each with the band rows held on chip, so per row and launch the band
     8(2q+1), b and the iterate written, plus the previous iterate read by
     every launch after the first; every system is swept."""
     if sweeps <= 0:
         return 0
-    launches = -(-sweeps // (1 + 64 // q))
+    launches = -(-sweeps // (1 + 128 // q))
     rows = int(sizes.sum())
     return rows * (launches * (8 * (2 * q + 1) + 16) + (launches - 1) * 8)
 

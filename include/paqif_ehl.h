@@ -225,10 +225,10 @@ int paqif_solve_lcp_noalloc(paqif_handle handle, const paqif_batch *batch, const
  * on the synthetic batches, about three from the sign of b).  The sweeps
  * run for every system, as a kernel of their own before the solve: each
  * workgroup holds 512 rows of a system, two per thread with their band
- * rows in registers, and runs up to 1 + 64 / q sweeps on them (one band
+ * rows in registers, and runs up to 1 + 128 / q sweeps on them (one band
  * read per launch).  0 <= sweeps <= PAQIF_MAX_START_SWEEPS; a new handle
  * uses 16 for q = 2 and 4 and 12 for q = 8.  The sweeps write u (and,
- * above 1 + 64 / q sweeps, the workspace's record area).
+ * above 1 + 128 / q sweeps, the workspace's record area).
  * paqif_autotune: times every layout on the caller's batch (one warm-up and
  * one timed solve each, HIP events on `stream`, which it synchronises),
  * stores the fastest in the handle and, if times_ms (host, float[count]) is
@@ -291,7 +291,7 @@ int paqif_solve_lcp_many(paqif_handle handle, int ncalls, const paqif_lcp_call *
  *  u         : DEVICE out, total_rows doubles.
  *  workspace : DEVICE, paqif_workspace_bytes(handle, batch, prec,
  *              LCP_EXACT); its record area holds the iterate between
- *              launches when the sweeps take several (above 1 + 64 / q).
+ *              launches when the sweeps take several (above 1 + 128 / q).
  * Returns PAQIF_EINVAL for a bad batch, prec or null pointer.
  */
 int paqif_start_sweeps(paqif_handle handle, const paqif_batch *batch, const double *band,

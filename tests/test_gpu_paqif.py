@@ -375,7 +375,7 @@ def test_start_sweeps_keep_the_solution(gpu, q, layout, sweeps):
 @pytest.mark.parametrize("sweeps", [1, 3, 8, 20])
 def test_start_sweeps_iterate_matches_oracle(gpu, q, sweeps):
     """The start sweeps' kernel (workgroups of 512 held rows, several per
-    system, one launch per 1 + 64/q sweeps) gives the oracle's starting
+    system, one launch per 1 + 128/q sweeps) gives the oracle's starting
     active set: one active-set solve (max_iter = 1) from each side's A_0
     gives the same u (a start that differs in one row changes u there by the
     row's whole value).  Every system starts from the sweeps."""
@@ -413,7 +413,7 @@ def test_start_sweeps_split_matches_exact(gpu, q, sweeps, prec):
     """The start sweeps on their own (paqif_start_sweeps) followed by the
     solve from that iterate (LCP_EXACT_FROM_U) is one LCP_EXACT call split in
     two: the same u, w, active set, statuses and solve counts, bit for bit,
-    with one sweep launch and several (q = 8 above 9 sweeps, q = 4 above 17),
+    with one sweep launch and two (q = 8 above 17 sweeps),
     and the sign start (0 sweeps: u = b); the oracle's active set too."""
     P = gpu
     dev = torch.device("cuda")
