@@ -532,6 +532,179 @@ __global__ void __launch_bounds__(256) point_deform_kernel32(int Nx, int Ny, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Point contact, FP64 / FP32 MFMA, staged like the line kernel.  For each x
+// offset d the product is a Toeplitz product along y,
+//   out[i][j] += sum_jp k2[|d|][|j - jp|] P[i - d][jp],
+// i.e. the line kernel with the kernel row k2[|d|] and the P rows shifted
+// by d as its instances.  A workgroup: 4 waves along j (16 rows j each, 64
+// in all) and 16 columns i; it runs the chunk loop of the line kernel (32
+// rows jp per chunk) once per d of its segment of the d range, with the
+// kernel row in LDS (two buffers by the parity of d, so the next row is
+// stored while the current one is still read) and each chunk of its 16 P
+// rows i - d staged once (two buffers).  The items (d, chunk) form one
+// pipeline: the next item's loads, and at a d boundary the next kernel row,
+// are issued before the current item's MFMAs; one barrier per item.  The
+// partial sums of the segments (blockIdx.y) go to part as for the other
+// point kernels.  Needs Ny + 1 <= 2048 (the kernel row in 8 loads per
+// thread).
+// ---------------------------------------------------------------------------
+constexpr int kPtKG = 8;                // K-steps per chunk
+constexpr int kPtGJ = 4 * kPtKG;        // rows jp per chunk
+constexpr int kPtPB = 4 * kPtKG + 2;    // staged column stride
+constexpr int kPtKV = 8;                // kernel-row loads per thread
+
+template <int PREC>
+__global__ void __launch_bounds__(256) point_deform_tiled(int Nx, int Ny, int nseg, int B,
+                                                          const double* __restrict__ k2,
+                                                          const double* __restrict__ P,
+                                                          double* __restrict__ part)
+{
+    using T = typename std::conditional<PREC == PREC_FP64, double, float>::type;
+    constexpr int LKG = kPtKG, LGJ = kPtGJ, LPB = kPtPB;
+    constexpr int SPT = LGJ / 16;  // staged values per thread
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    T* pt = reinterpret_cast<T*>(lds_raw);  // [2][16][LPB] staged P chunks
+    T* skb = pt + 2 * 16 * LPB;             // [2][Ny + 1] kernel rows (zero at Ny)
+    const int NS = Ny + 1;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, l = tid % 64;
+    const int li = l % 16, lk = l / 16;
+    const int nbj = (Ny + 63) / 64;
+    const int tj = (int)blockIdx.x % nbj, ti = (int)blockIdx.x / nbj;
+    const int jw0 = tj * 64 + wave * 16;  // this wave's first output row j
+    const int i0 = ti * 16;               // the workgroup's output columns i
+    const int s = blockIdx.y, inst = blockIdx.z;
+    if (i0 >= Nx) return;  // the whole workgroup
+    const double* Pi = P + (int64_t)inst * Nx * Ny;
+    // offsets d with i - d in [0, Nx) for some i of the workgroup, split
+    // into nseg segments
+    const int dlo = i0 - (Nx - 1), dhi = min(i0 + 15, Nx - 1);
+    const int per = (dhi - dlo + 1 + nseg - 1) / nseg;
+    const int ds0 = dlo + s * per, ds1 = min(dhi, ds0 + per - 1);
+    const int nd = ds1 >= ds0 ? ds1 - ds0 + 1 : 0;
+    const int nch = (Ny + LGJ - 1) / LGJ;
+    const int nitems = nd * nch;
+    typedef typename std::conditional<PREC == PREC_FP64, f64x4, f32x4>::type acc_t;
+    acc_t ce = {0, 0, 0, 0}, co = {0, 0, 0, 0};
+    const int ja = jw0 + li;  // A row (output j) of this lane
+    const bool ina = ja < Ny;
+    const bool rows_in = jw0 + 15 < Ny;
+    // chunk ranges of the wave's rows (uniform): every jp below every j,
+    // every jp above (and inside), the others
+    const int gA = (rows_in && jw0 >= LGJ - 1) ? (jw0 - (LGJ - 1)) / LGJ + 1 : 0;
+    const int gB = rows_in ? max(gA, (jw0 + 15 + LGJ - 1) / LGJ) : 0;
+    const int gC = rows_in ? max(gB, min(nch, Ny >= LGJ ? (Ny - LGJ) / LGJ + 1 : 0)) : 0;
+    // staging of P: thread t takes column i0 + t / 16 (P row i - d), rows
+    // jp = chunk start + SPT (t % 16) ..
+    const int sc = tid / 16, sj = SPT * (tid % 16);
+    const int icol = i0 + sc;
+    double stv[SPT];
+    bool sok = false;
+    auto gload = [&](int d, int c) {
+        const int ip = icol - d;
+        sok = icol < Nx && ip >= 0 && ip < Nx;
+        const double* pr = Pi + (int64_t)min(max(ip, 0), Nx - 1) * Ny;
+        const int j = c * LGJ + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) stv[e] = pr[min(j + e, Ny - 1)];
+    };
+    auto lstore = [&](int buf, int c) {
+        const int j = c * LGJ + sj;
+        T* d = pt + (buf * 16 + sc) * LPB + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) d[e] = (sok && j + e < Ny) ? (T)stv[e] : (T)0;
+    };
+    double kv[kPtKV];
+    auto kload = [&](int d) {
+        const double* kr = k2 + (int64_t)abs(d) * Ny;
+#pragma unroll
+        for (int e = 0; e < kPtKV; e++) kv[e] = kr[min(tid + 256 * e, Ny - 1)];
+    };
+    auto kstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < kPtKV; e++) {
+            const int t = tid + 256 * e;
+            if (t <= Ny) skb[buf * NS + t] = t < Ny ? (T)kv[e] : (T)0;
+        }
+    };
+    if (nitems > 0) {
+        kload(ds0);
+        gload(ds0, 0);
+        kstore(0);
+        lstore(0, 0);
+        __syncthreads();
+        int d = ds0, c = 0, dpar = 0;
+        for (int it = 0; it < nitems; it++) {
+            int dn = d, cn = c + 1;
+            if (cn == nch) {
+                cn = 0;
+                dn = d + 1;
+            }
+            const bool more = it + 1 < nitems;
+            const bool newd = more && cn == 0;
+            if (more) gload(dn, cn);  // the next item in flight
+            if (newd) kload(dn);
+            if (jw0 < Ny) {
+                const T* sk = skb + dpar * NS;
+                const int jg = c * LGJ;
+                T av[LKG];
+                if (c < gA) {
+                    const T* ap = sk + (ja - jg - LKG * lk - (LKG - 1));
+#pragma unroll
+                    for (int u = 0; u < LKG; u++) av[u] = ap[LKG - 1 - u];
+                } else if (c >= gB && c < gC) {
+                    const T* ap = sk + (jg + LKG * lk - ja);
+#pragma unroll
+                    for (int u = 0; u < LKG; u++) av[u] = ap[u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < LKG; u++) {
+                        const int jp = jg + LKG * lk + u;
+                        av[u] = sk[(ina && jp < Ny) ? abs(ja - jp) : Ny];
+                    }
+                }
+                const T* bp = pt + ((it & 1) * 16 + li) * LPB + LKG * lk;
+#pragma unroll
+                for (int u = 0; u < LKG; u++) {
+                    const T x = bp[u];
+                    if constexpr (PREC == PREC_FP64) {
+                        if (u % 2 == 0) ce = mfma_f64(av[u], x, ce);
+                        else co = mfma_f64(av[u], x, co);
+                    } else {
+                        if (u % 2 == 0) ce = mfma_f32(av[u], x, ce);
+                        else co = mfma_f32(av[u], x, co);
+                    }
+                }
+            }
+            if (more) lstore((it + 1) & 1, cn);
+            if (newd) kstore(dpar ^ 1);
+            __syncthreads();
+            if (newd) dpar ^= 1;
+            d = dn;
+            c = cn;
+        }
+    }
+    // D element r of lane l: FP64 row 4 r + l/16, FP32 row 4 (l/16) + r (output
+    // j), column l % 16 (output i); every segment writes its tile (the
+    // reduction sums all of them)
+    double* dst = part + ((int64_t)s * B + inst) * Nx * Ny;
+    const int io = i0 + li;
+    if (io < Nx && jw0 < Ny) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int jo = jw0 + (PREC == PREC_FP64 ? 4 * r + lk : 4 * lk + r);
+            if (jo < Ny) dst[(int64_t)io * Ny + jo] = (double)ce[r] + (double)co[r];
+        }
+    }
+}
+
+template <int PREC>
+static size_t point_tiled_lds(int Ny)
+{
+    return (size_t)(2 * 16 * kPtPB + 2 * (Ny + 1)) * (PREC == PREC_FP64 ? 8 : 4);
+}
+
 __global__ void point_reduce_kernel(int64_t count, int nseg, const double* __restrict__ part,
                                     double* __restrict__ out)
 {
@@ -747,12 +920,25 @@ int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const
                         double* out, double* part, hipStream_t s)
 {
     if (Nx <= 0 || Ny <= 0 || B <= 0) return PAQIF_OK;
-    const int nseg = point_segments(Nx, Ny);
+    int nseg = point_segments(Nx, Ny);
     const int ntj32 = (Ny + 31) / 32, nti32 = (Nx + 31) / 32;
     const dim3 grid32(ntj32 * ((nti32 + 3) / 4), nseg, B), block(256);
     const int ntj = (Ny + 15) / 16, nti = (Nx + 15) / 16;
     const dim3 grid(ntj * ((nti + 3) / 4), nseg, B);
-    if (prec == PREC_FP64)
+    // the staged kernel for FP64 / FP32 (Ny + 1 <= 256 kPtKV); segments for
+    // about 4096 waves at one instance, within the workspace's nseg
+    const bool tiled = (prec == PREC_FP64 || prec == PREC_FP32) && Ny + 1 <= 256 * kPtKV;
+    if (tiled) {
+        const int nbj = (Ny + 63) / 64, nbi = (Nx + 15) / 16;
+        nseg = std::max(1, std::min(nseg, 4096 / (4 * nbj * nbi)));
+        const dim3 gridp(nbj * nbi, nseg, B);
+        if (prec == PREC_FP64)
+            hipLaunchKernelGGL((point_deform_tiled<PREC_FP64>), gridp, block,
+                               point_tiled_lds<PREC_FP64>(Ny), s, Nx, Ny, nseg, B, k2, P, part);
+        else
+            hipLaunchKernelGGL((point_deform_tiled<PREC_FP32>), gridp, block,
+                               point_tiled_lds<PREC_FP32>(Ny), s, Nx, Ny, nseg, B, k2, P, part);
+    } else if (prec == PREC_FP64)
         hipLaunchKernelGGL((point_deform_kernel32<PREC_FP64>), grid32, block, 0, s, Nx, Ny, nseg,
                            B, k2, P, part);
     else if (prec == PREC_FP32)

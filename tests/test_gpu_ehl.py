@@ -57,9 +57,13 @@ def test_line_deformation(gpu, N, B, prec):
     assert _rel(out.cpu().numpy(), ref) < tol
 
 
-@pytest.mark.parametrize("Nx,Ny,B", [(9, 7, 1), (33, 33, 2), (65, 65, 1), (129, 97, 1)])
+@pytest.mark.parametrize("Nx,Ny,B", [(9, 7, 1), (33, 33, 2), (65, 65, 1), (129, 97, 1),
+                                     (17, 130, 3), (40, 257, 1), (70, 64, 2)])
 @pytest.mark.parametrize("prec", [0, 3, 2])
 def test_point_deformation(gpu, Nx, Ny, B, prec):
+    """H_el = K P of point grids against the oracle's direct sum: ragged
+    tiles and chunks along y (Ny = 7, 97, 130, 257), along x (Nx = 17, 70)
+    and several instances."""
     tol = _tol(prec, Nx * Ny)
     P = gpu.ehl
     grid = P.point_grid(Nx, Ny)
