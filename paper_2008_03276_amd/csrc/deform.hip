@@ -868,6 +868,156 @@ __global__ void __launch_bounds__(256) line_deform_sbf16(int N, int B,
 
 static size_t line_sbf16_lds(int N) { return (size_t)(4 * 16 * SBP) * 2 + (size_t)(N + 1) * 4; }
 
+// ---------------------------------------------------------------------------
+// Point contact, split BF16: the items (d, chunk of rows jp) of
+// point_deform_tiled with the operands of line_deform_sbf16: the kernel row
+// k2[|d|] packed hi | lo (two buffers by the parity of d), each staged chunk
+// of the 16 shifted P rows as hi and lo halves, one K = 32 step per chunk
+// (k-group lk of a lane takes rows jp = chunk start + 8 lk .. + 7), three
+// products hi*hi + hi*lo + lo*hi.  Needs Ny + 1 <= 2048.
+// ---------------------------------------------------------------------------
+constexpr int kPsJ = 32;        // rows jp per chunk
+constexpr int kPsP = kPsJ + 8;  // staged column stride in bf16 (16-byte aligned)
+
+__global__ void __launch_bounds__(256) point_deform_sbf16(int Nx, int Ny, int nseg, int B,
+                                                          const double* __restrict__ k2,
+                                                          const double* __restrict__ P,
+                                                          double* __restrict__ part)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    uint16_t* ph = reinterpret_cast<uint16_t*>(lds_raw);  // [2][16][kPsP] hi halves
+    uint16_t* pl = ph + 2 * 16 * kPsP;                     // [2][16][kPsP] lo halves
+    uint32_t* skb = reinterpret_cast<uint32_t*>(pl + 2 * 16 * kPsP);  // [2][Ny + 1] packed
+    const int NS = Ny + 1;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, l = tid % 64;
+    const int li = l % 16, lk = l / 16;
+    const int nbj = (Ny + 63) / 64;
+    const int tj = (int)blockIdx.x % nbj, ti = (int)blockIdx.x / nbj;
+    const int jw0 = tj * 64 + wave * 16;
+    const int i0 = ti * 16;
+    const int s = blockIdx.y, inst = blockIdx.z;
+    if (i0 >= Nx) return;  // the whole workgroup
+    const double* Pi = P + (int64_t)inst * Nx * Ny;
+    const int dlo = i0 - (Nx - 1), dhi = min(i0 + 15, Nx - 1);
+    const int per = (dhi - dlo + 1 + nseg - 1) / nseg;
+    const int ds0 = dlo + s * per, ds1 = min(dhi, ds0 + per - 1);
+    const int nd = ds1 >= ds0 ? ds1 - ds0 + 1 : 0;
+    const int nch = (Ny + kPsJ - 1) / kPsJ;
+    const int nitems = nd * nch;
+    f32x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+    const int ja = jw0 + li;
+    const bool ina = ja < Ny;
+    const bool rows_in = jw0 + 15 < Ny;
+    const int gA = (rows_in && jw0 >= kPsJ - 1) ? (jw0 - (kPsJ - 1)) / kPsJ + 1 : 0;
+    const int gB = rows_in ? max(gA, (jw0 + 15 + kPsJ - 1) / kPsJ) : 0;
+    const int gC = rows_in ? max(gB, min(nch, Ny >= kPsJ ? (Ny - kPsJ) / kPsJ + 1 : 0)) : 0;
+    constexpr int SPT = kPsJ / 16;
+    const int sc = tid / 16, sj = SPT * (tid % 16);
+    const int icol = i0 + sc;
+    double stv[SPT];
+    bool sok = false;
+    auto gload = [&](int d, int c) {
+        const int ip = icol - d;
+        sok = icol < Nx && ip >= 0 && ip < Nx;
+        const double* pr = Pi + (int64_t)min(max(ip, 0), Nx - 1) * Ny;
+        const int j = c * kPsJ + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) stv[e] = pr[min(j + e, Ny - 1)];
+    };
+    auto lstore = [&](int buf, int c) {
+        const int j = c * kPsJ + sj;
+        const int o = (buf * 16 + sc) * kPsP + sj;
+#pragma unroll
+        for (int e = 0; e < SPT; e++) {
+            const uint32_t hl = (sok && j + e < Ny) ? bf16_hi_lo((float)stv[e]) : 0u;
+            ph[o + e] = (uint16_t)(hl & 0xFFFFu);
+            pl[o + e] = (uint16_t)(hl >> 16);
+        }
+    };
+    double kv[kPtKV];
+    auto kload = [&](int d) {
+        const double* kr = k2 + (int64_t)abs(d) * Ny;
+#pragma unroll
+        for (int e = 0; e < kPtKV; e++) kv[e] = kr[min(tid + 256 * e, Ny - 1)];
+    };
+    auto kstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < kPtKV; e++) {
+            const int t = tid + 256 * e;
+            if (t <= Ny) skb[buf * NS + t] = t < Ny ? bf16_hi_lo((float)kv[e]) : 0u;
+        }
+    };
+    if (nitems > 0) {
+        kload(ds0);
+        gload(ds0, 0);
+        kstore(0);
+        lstore(0, 0);
+        __syncthreads();
+        int d = ds0, c = 0, dpar = 0;
+        for (int it = 0; it < nitems; it++) {
+            int dn = d, cn = c + 1;
+            if (cn == nch) {
+                cn = 0;
+                dn = d + 1;
+            }
+            const bool more = it + 1 < nitems;
+            const bool newd = more && cn == 0;
+            if (more) gload(dn, cn);
+            if (newd) kload(dn);
+            if (jw0 < Ny) {
+                const uint32_t* sk = skb + dpar * NS;
+                const int jb = c * kPsJ + 8 * lk;  // this lane's first row jp
+                uint32_t av[8];
+                if (c < gA) {
+                    const uint32_t* ap = sk + (ja - jb - 7);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) av[e] = ap[7 - e];
+                } else if (c >= gB && c < gC) {
+                    const uint32_t* ap = sk + (jb - ja);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) av[e] = ap[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const int jp = jb + e;
+                        av[e] = sk[(ina && jp < Ny) ? abs(ja - jp) : Ny];
+                    }
+                }
+                u32x4 ah, al;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    ah[q] = __builtin_amdgcn_perm(av[2 * q + 1], av[2 * q], 0x05040100u);
+                    al[q] = __builtin_amdgcn_perm(av[2 * q + 1], av[2 * q], 0x07060302u);
+                }
+                const int bo = ((it & 1) * 16 + li) * kPsP + 8 * lk;
+                const u32x4 bh = *reinterpret_cast<const u32x4*>(ph + bo);
+                const u32x4 bl = *reinterpret_cast<const u32x4*>(pl + bo);
+                c0 = mfma_bf16x32(ah, bh, c0);
+                c1 = mfma_bf16x32(ah, bl, c1);
+                c1 = mfma_bf16x32(al, bh, c1);
+            }
+            if (more) lstore((it + 1) & 1, cn);
+            if (newd) kstore(dpar ^ 1);
+            __syncthreads();
+            if (newd) dpar ^= 1;
+            d = dn;
+            c = cn;
+        }
+    }
+    double* dst = part + ((int64_t)s * B + inst) * Nx * Ny;
+    const int io = i0 + li;
+    if (io < Nx && jw0 < Ny) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int jo = jw0 + 4 * lk + r;
+            if (jo < Ny) dst[(int64_t)io * Ny + jo] = (double)(c0[r] + c1[r]);
+        }
+    }
+}
+
+static size_t point_sbf16_lds(int Ny) { return (size_t)(4 * 16 * kPsP) * 2 + (size_t)(Ny + 1) * 8; }
+
 // LDS of line_deform_tiled: two staged B chunks, the kernel vector and a zero
 template <int PREC>
 static size_t line_tiled_lds(int N)
@@ -925,9 +1075,9 @@ int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const
     const dim3 grid32(ntj32 * ((nti32 + 3) / 4), nseg, B), block(256);
     const int ntj = (Ny + 15) / 16, nti = (Nx + 15) / 16;
     const dim3 grid(ntj * ((nti + 3) / 4), nseg, B);
-    // the staged kernel for FP64 / FP32 (Ny + 1 <= 256 kPtKV); segments for
-    // about 4096 waves at one instance, within the workspace's nseg
-    const bool tiled = (prec == PREC_FP64 || prec == PREC_FP32) && Ny + 1 <= 256 * kPtKV;
+    // the staged kernels (Ny + 1 <= 256 kPtKV); segments for about 4096
+    // waves at one instance, within the workspace's nseg
+    const bool tiled = Ny + 1 <= 256 * kPtKV;
     if (tiled) {
         const int nbj = (Ny + 63) / 64, nbi = (Nx + 15) / 16;
         nseg = std::max(1, std::min(nseg, 4096 / (4 * nbj * nbi)));
@@ -935,9 +1085,12 @@ int launch_point_deform(int Nx, int Ny, int B, int prec, const double* k2, const
         if (prec == PREC_FP64)
             hipLaunchKernelGGL((point_deform_tiled<PREC_FP64>), gridp, block,
                                point_tiled_lds<PREC_FP64>(Ny), s, Nx, Ny, nseg, B, k2, P, part);
-        else
+        else if (prec == PREC_FP32)
             hipLaunchKernelGGL((point_deform_tiled<PREC_FP32>), gridp, block,
                                point_tiled_lds<PREC_FP32>(Ny), s, Nx, Ny, nseg, B, k2, P, part);
+        else
+            hipLaunchKernelGGL(point_deform_sbf16, gridp, block, point_sbf16_lds(Ny), s, Nx, Ny,
+                               nseg, B, k2, P, part);
     } else if (prec == PREC_FP64)
         hipLaunchKernelGGL((point_deform_kernel32<PREC_FP64>), grid32, block, 0, s, Nx, Ny, nseg,
                            B, k2, P, part);
