@@ -224,6 +224,54 @@ def test_wrapper_refuses_short_buffers(gpu):
         P.paqif.factor(bt, band_d, factors=ws32)
 
 
+def test_full_size_step_sampled(gpu):
+    """The benchmark's step at full size: the three batches (q = 8, 4, 2,
+    4096 systems each, n in [513, 4097]) in one paqif_solve_lcp_many call
+    with the sweep counts its step tuning picks most often (16 / 16 / 12);
+    the LCP certificate on every system, the largest and smallest systems
+    and a random sample of each batch re-solved by the oracle."""
+    P = gpu
+    count = 4096
+    dev = torch.device("cuda")
+    data, calls = {}, []
+    keep = {q: P.paqif.get_start_sweeps(q, 0) for q in (2, 4, 8)}
+    try:
+        for q, k in ((8, 12), (4, 16), (2, 16)):
+            P.paqif.set_start_sweeps(q, 0, k)
+            offs, band, f = synth.lcp_batch(count, q, seed=0)
+            data[q] = (offs, band, f)
+            bt = P.paqif.Batch(offs, q, order="lpt")
+            calls.append(dict(batch=bt, band=torch.as_tensor(band, device=dev),
+                              b=torch.as_tensor(f, device=dev)))
+        print("full-size step, one solve_lcp_many call", flush=True)
+        res = P.paqif.solve_lcp_many(calls, mode=P.LCP_EXACT)
+        torch.cuda.synchronize()
+    finally:
+        for q, k in keep.items():
+            P.paqif.set_start_sweeps(q, 0, k)
+    for q, r in zip((8, 4, 2), res):
+        offs, band, f = data[q]
+        u = r["u"].cpu().numpy()
+        w = r["w"].cpu().numpy()
+        act = r["active"].cpu().numpy()
+        assert (r["status"].cpu().numpy() == 0).all(), q
+        scale = np.abs(f).max()
+        assert u.min() >= 0.0
+        assert (u[act == 1] == 0.0).all()
+        assert w.min() >= -1e-12 * scale
+        assert np.abs(u * w).max() <= 1e-12 * scale * max(1.0, np.abs(u).max())
+        sizes = offs[1:] - offs[:-1]
+        rng = np.random.default_rng(10 + q)
+        pick = set(rng.choice(count, size=4, replace=False).tolist())
+        pick |= {int(np.argmax(sizes)), int(np.argmin(sizes))}
+        for s in sorted(pick):
+            a, b = offs[s], offs[s + 1]
+            o = oracle.lcp_solve(band[a:b], f[a:b])
+            assert o["status"] == 0
+            assert (o["active"] == act[a:b]).all(), (q, s)
+            assert _relerr(u[a:b], o["u"]) < 1e-12, (q, s)
+
+
 @pytest.mark.parametrize("q", [2, 4, 8])
 def test_full_size_sampled(gpu, q):
     """Full-size workload (4096 systems, n in [513, 4097]) in the launch
